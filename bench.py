@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark of the GenASM hot path on one MI355X.
+
+One step = the whole path over one batch already resident in device memory:
+2-bit packing of the ASCII reads and references, the start search, and the
+windowed DC + traceback with run-length CIGAR output (batched form: search
+kernels, then the persistent window kernel with its work queue). Prints ONE
+JSON line on stdout; progress goes to stderr.
+
+Default workload: 20,000 pairs of 10 kb reads with 10% PacBio-like edits,
+reference = true segment +-500 bp, 30% unrelated 10 kb decoys, k=64, W=64,
+O=24 (synthetic, seeded).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# int32 VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rle(ops: str) -> str:
+    out, k = [], 0
+    while k < len(ops):
+        j = k
+        while j < len(ops) and ops[j] == ops[k]:
+            j += 1
+        out.append(f"{j - k}{ops[k]}")
+        k = j
+    return "".join(out)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="long10k")
+    ap.add_argument("--pairs", type=int, default=None, help="pairs (default: the full workload)")
+    ap.add_argument("--no-plain", action="store_true", help="skip timing the plain form")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=4000,
+                    help="pairs of the workload the CPU oracle aligns for the baseline")
+    ap.add_argument("--verify", type=int, default=32, help="pairs checked against the oracle")
+    ap.add_argument("--group-lanes", type=int, default=0)
+    ap.add_argument("--lds-rows", type=int, default=0)
+    ap.add_argument("--workers-per-cu", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: pairs are independent and this build runs on a single "
+              "MI355X; run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2203_15561_amd as ga
+    from workloads import gen
+
+    t0 = time.time()
+    ps = gen.make(args.workload, args.pairs)
+    log(f"generated {ps.n_pairs} pairs of {args.workload} in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    reads_ascii = torch.from_numpy(np.frombuffer(gen.to_ascii(ps.reads), dtype=np.uint8).copy()).to(dev)
+    refs_ascii = torch.from_numpy(np.frombuffer(gen.to_ascii(ps.refs), dtype=np.uint8).copy()).to(dev)
+    roff = torch.from_numpy(ps.read_off.astype(np.int64)).to(dev)
+    foff = torch.from_numpy(ps.ref_off.astype(np.int64)).to(dev)
+    nr, nf = int(ps.read_off[-1]), int(ps.ref_off[-1])
+    reads2b = torch.empty((nr + 3) // 4, dtype=torch.uint8, device=dev)
+    refs2b = torch.empty((nf + 3) // 4, dtype=torch.uint8, device=dev)
+    bad = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = torch.empty((ps.n_pairs, 32), dtype=torch.uint8, device=dev)
+    cigar = torch.empty(nr + nf, dtype=torch.int32, device=dev)
+    max_ref = int(np.diff(ps.ref_off).max())
+
+    ctx = ga.Context(0)
+    kw = {}
+    if args.group_lanes:
+        kw["group_lanes"] = args.group_lanes
+    if args.lds_rows:
+        kw["lds_rows"] = args.lds_rows
+    if args.workers_per_cu:
+        kw["workers_per_cu"] = args.workers_per_cu
+    batched = ga.make_launch(ga.FORM_BATCHED, **kw)
+    plain = ga.make_launch(ga.FORM_PLAIN)
+
+    def step(launch):
+        ctx.pack_dev(reads_ascii, reads2b, bad)
+        ctx.pack_dev(refs_ascii, refs2b, bad)
+        ctx.align_dev(reads2b, roff, refs2b, foff, ps.k, ps.W, ps.O, launch=launch, out=out,
+                      cigar=cigar, total_read_bases=nr, total_ref_bases=nf, max_ref_len=max_ref)
+
+    # warm-up
+    for _ in range(args.warmup):
+        step(batched)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 0
+    log("warm-up done")
+
+    # timed region: K steps, library profiling on (HIP events around each stage on
+    # the same stream), one profile read per step for the window-kernel time
+    ctx.profile(True)
+    win_ms, search_ms, total_ms = [], [], []
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step(batched)
+        pr = ctx.profile_read()
+        win_ms.append(pr["windows_ms"])
+        search_ms.append(pr["search_ms"])
+        total_ms.append(pr["total_ms"])
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    ctx.profile(False)
+    log(f"batched: {ms_step:.2f} ms/step; window kernel {np.mean(win_ms):.2f} ms, search "
+        f"{np.mean(search_ms):.2f} ms")
+
+    res = out.cpu().numpy().view(ga.RESULT_DTYPE).reshape(-1)
+    assert (res["flags"] == 0).all()
+
+    # spot-check results against the oracle
+    verified = 0
+    if args.verify:
+        import oracle
+        idx = np.linspace(0, ps.n_pairs - 1, min(args.verify, ps.n_pairs)).astype(int)
+        sub = ps.subset(idx)
+        ro, ops, _, _ = oracle.batch(sub)
+        elems = cigar.cpu().numpy().view(np.uint32)
+        for j, i in enumerate(idx):
+            r = res[i]
+            o, n = int(r["cigar_off"]), int(r["cigar_len"])
+            assert int(r["edit_distance"]) == int(ro["score"][j]), (i, r, ro[j])
+            want = rle(oracle.pair_ops(sub, ro, ops, j)) if ro["score"][j] >= 0 else ""
+            assert ga.decode_cigar(elems[o:o + n]) == want, i
+            verified += 1
+        log(f"verified {verified} pairs against the oracle")
+
+    cells = pr["window_cells"] + pr["search_cells"]
+    int_ops_windows = 2 * pr["window_word_ops"]  # two 32-bit halves per 64-bit word op
+    achieved = int_ops_windows / (np.mean(win_ms) / 1e3) / 1e12
+    line = {
+        "metric": "alignments/s (10 kb reads, 10% edits, batched form)",
+        "value": ps.n_pairs / (ms_step / 1e3),
+        "unit": "alignments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {gen.DESCRIPTIONS[args.workload]}",
+                   "pairs": ps.n_pairs, "k": ps.k, "W": ps.W, "O": ps.O, "form": "batched",
+                   "group_lanes": batched.group_lanes, "lds_rows": batched.lds_rows,
+                   "workers_per_cu": batched.workers_per_cu},
+        "gcups": cells / (ms_step / 1e3) / 1e9,
+        "window_kernel_ms": float(np.mean(win_ms)),
+        "search_ms": float(np.mean(search_ms)),
+        "roofline": {"bound": "alu", "kernel": "k_windows (window DC + traceback)",
+                     "achieved": achieved, "peak": INT32_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / INT32_PEAK_TOPS, "traffic": None,
+                     "ops_per_launch": int_ops_windows},
+        "work": {k: int(v) for k, v in pr.items() if not k.endswith("_ms")},
+        "verified_pairs": verified,
+    }
+
+    if not args.no_plain:
+        torch.cuda.synchronize()
+        step(plain)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step(plain)
+        e1.record()
+        torch.cuda.synchronize()
+        pm = e0.elapsed_time(e1)
+        line["plain"] = {"alignments_per_s": ps.n_pairs / (pm / 1e3), "ms": pm,
+                         "gcups": cells / (pm / 1e3) / 1e9}
+        log(f"plain: {pm:.2f} ms/step")
+
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = min(args.cpu_sample, ps.n_pairs)
+        sub = ps.subset(np.arange(sample))
+        _, _, secs, used = oracle.batch(sub)
+        line["cpu_baseline"] = {"value": sample / secs, "unit": "alignments/s", "cores": used,
+                                "kind": "oracle",
+                                "sample": f"first {sample} pairs of {args.workload} (same mix), "
+                                          f"improved form, {used} threads, {secs:.2f} s wall"}
+        log(f"cpu oracle: {sample / secs:.1f} alignments/s on {used} threads")
+
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * genasm.h - C ABI of the gfx950 GenASM aligner (windowed bit-parallel
+ * edit-distance calculation, GenASM-DC, plus traceback, GenASM-TB, with the
+ * three improvements of Lindegger et al., "Algorithmic Improvement and GPU
+ * Acceleration of the GenASM Algorithm", 2022).
+ *
+ * The operation (paper, Introduction): build the DP table of bitvectors R[d]
+ * for each window of a (read, reference) pair, then trace back through it to
+ * recover the alignment, storing per DP entry only the AND of its four edge
+ * bitvectors (key idea 1), stopping once a row holds the full solution (key
+ * idea 2) and never storing entries the traceback cannot reach (key idea 3).
+ * The paper's Results section aligns (read, reference) candidate pairs; this
+ * library aligns batches of such pairs, one result and one CIGAR per pair.
+ *
+ * Semantics, in the notation of the GenASM recurrence (0 = match, bit p of a
+ * word stands for pattern character Pw[mw-1-p]):
+ *   - K = min(k, W) caps the rows of every window and of the start search.
+ *   - The alignment starts at the least edit row, then the leftmost column,
+ *     in which the first read window (at most W bases) fits anywhere in the
+ *     reference (start search).
+ *   - Windows of at most W read and W reference bases follow; each window's
+ *     traceback takes the first valid edge in the order match, substitution,
+ *     insertion, deletion, and commits at most W-O bases of either sequence.
+ *   - A window with no solution within K fails the pair: edit_distance = -1,
+ *     empty CIGAR, ref_begin = ref_end = 0.
+ *   - A read of length 0 gives edit_distance 0, an empty CIGAR, span [0,0).
+ * CIGAR ops are '=', 'X', 'I' (read base absent from the reference) and 'D'
+ * (reference base absent from the read); runs merge across window seams.
+ *
+ * Threading: a genasm_ctx is not thread-safe; use one per host thread.
+ * No C++ exception crosses this interface. Every call returns GENASM_OK (0)
+ * or a negative error code.
+ */
+#ifndef GENASM_H
+#define GENASM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GENASM_ABI_VERSION 1
+
+/* Error codes. */
+#define GENASM_OK 0
+#define GENASM_E_INVAL (-1)     /* bad argument: W not in [2,64], O not in [0,W-1], k < 0,
+                                   null pointer, offsets not non-decreasing, bad launch */
+#define GENASM_E_ALPHABET (-2)  /* a sequence byte outside A,C,G,T,a,c,g,t */
+#define GENASM_E_NOMEM (-3)     /* host or device allocation failed */
+#define GENASM_E_DEVICE (-4)    /* HIP error; genasm_last_error() has the message */
+#define GENASM_E_NOSPACE (-5)   /* output buffer too small; the needed size is reported */
+#define GENASM_E_BUSY (-6)      /* serving: request refused, admission budget exhausted */
+#define GENASM_E_TOOLONG (-7)   /* a sequence is longer than 2^31 - 1 bases */
+
+/* Per-pair result. 32 bytes, 8-byte aligned. */
+typedef struct {
+    int32_t edit_distance; /* total committed edits, -1 if some window had no solution within k */
+    uint32_t ref_begin;    /* alignment covers reference bases [ref_begin, ref_end) */
+    uint32_t ref_end;
+    uint32_t n_windows;    /* windows processed (0 for an empty read or a failed start search) */
+    uint64_t cigar_off;    /* first CIGAR element of this pair (see the two call forms) */
+    uint32_t cigar_len;    /* CIGAR elements (device form) or characters (host form) */
+    uint32_t flags;        /* GENASM_FLAG_* bits; 0 on success */
+} genasm_result;
+
+#define GENASM_FLAG_CIGAR_OVERFLOW 1u  /* device form: the CIGAR did not fit; cigar_len is 0 */
+#define GENASM_FLAG_INTERNAL 2u        /* traceback found no valid edge (never expected) */
+
+/* Device-form CIGAR element: run length in bits 31..2, op in bits 1..0. */
+#define GENASM_OP_MATCH 0u    /* '=' */
+#define GENASM_OP_MISMATCH 1u /* 'X' */
+#define GENASM_OP_INS 2u      /* 'I' */
+#define GENASM_OP_DEL 3u      /* 'D' */
+#define GENASM_CIGAR_LEN(e) ((e) >> 2)
+#define GENASM_CIGAR_OP(e) ((e) & 3u)
+
+/* Launch forms. */
+#define GENASM_FORM_PLAIN 0    /* one pair per workgroup: 64 lanes = 64 DP rows of one pair */
+#define GENASM_FORM_BATCHED 1  /* search kernels, then one persistent window kernel with a
+                                  device work queue; several pairs per wavefront */
+
+typedef struct {
+    int32_t form;            /* GENASM_FORM_* */
+    int32_t group_lanes;     /* batched: lanes (= DP rows per pass) per pair in the window
+                                kernel, 16 or 64; 0 = default */
+    int32_t search_lanes;    /* batched: lanes per pair in the start search, 16 or 64; 0 = default */
+    int32_t lds_rows;        /* batched: window-table rows kept in LDS per pair (multiple of
+                                group_lanes, <= 64); rows above spill to device memory; 0 = default */
+    int32_t workers_per_cu;  /* batched: resident workgroups per compute unit; 0 = default */
+    int32_t lpt_order;       /* batched: 1 = longest reads first, 0 = input order; -1 = default */
+    int32_t reserved[2];
+} genasm_launch;
+
+typedef struct genasm_ctx genasm_ctx;
+
+/* Creates a context on HIP device `hip_device`. The context owns a stream,
+ * device scratch (grown on demand, reused across calls) and kernel handles.
+ * Returns GENASM_E_DEVICE if no such device exists or it is not gfx950. */
+int genasm_create(genasm_ctx** out, int hip_device);
+
+/* Frees everything the context owns. Safe on NULL. */
+void genasm_destroy(genasm_ctx* ctx);
+
+/* Message of the last error on this context (never NULL). With ctx == NULL:
+ * the reason of the calling thread's last failed genasm_create. */
+const char* genasm_last_error(const genasm_ctx* ctx);
+
+/* Static text for an error code. */
+const char* genasm_strerror(int code);
+
+/* Fills *out with the default launch parameters of `form`. */
+int genasm_default_launch(int32_t form, genasm_launch* out);
+
+/*
+ * Host-memory form, synchronous.
+ *   reads, refs      ASCII sequences (ACGT, either case), concatenated.
+ *   read_off,        n_pairs + 1 non-decreasing offsets: pair i is
+ *   ref_off          reads[read_off[i] .. read_off[i+1]) against
+ *                    refs[ref_off[i] .. ref_off[i+1]). read_off[0] may be
+ *                    non-zero.
+ *   k, W, O          error cap per window, window size (2..64), overlap (0..W-1).
+ *   out              n_pairs results; cigar_off/cigar_len index cigar_buf.
+ *   cigar_buf        CIGAR text of all pairs, back to back, no separators and no
+ *                    terminating NUL (e.g. "12=1X3="); may be NULL when
+ *                    cigar_cap == 0.
+ *   cigar_needed     receives the number of characters the CIGARs need.
+ *   launch           NULL for the default batched launch.
+ * Returns GENASM_E_NOSPACE (results are still written, CIGAR text is not)
+ * when cigar_cap < *cigar_needed. The caller owns every buffer; nothing is
+ * retained after the call returns.
+ */
+int genasm_batch_align(genasm_ctx* ctx, const char* reads, const uint64_t* read_off,
+                       const char* refs, const uint64_t* ref_off, uint64_t n_pairs,
+                       int32_t k, int32_t W, int32_t O, genasm_result* out, char* cigar_buf,
+                       uint64_t cigar_cap, uint64_t* cigar_needed, const genasm_launch* launch);
+
+/*
+ * Device-memory form, asynchronous on `stream` (a hipStream_t; NULL = the
+ * context's stream).
+ *   d_reads2b,       2-bit packed sequences in device memory: base b of the
+ *   d_refs2b         stream is bits 2*(b%4)..2*(b%4)+1 of byte b/4, codes
+ *                    A=0, C=1, G=2, T=3 (see genasm_pack).
+ *   d_read_off,      n_pairs + 1 non-decreasing base offsets, in device memory.
+ *   d_ref_off
+ *   d_out            n_pairs results in device memory.
+ *   d_cigar          device CIGAR elements (GENASM_CIGAR_LEN/OP); pair i writes
+ *                    at most m_i + n_i elements starting at element
+ *                    (d_read_off[i] - d_read_off[0]) + (d_ref_off[i] - d_ref_off[0]),
+ *                    where m_i, n_i are its read and reference lengths, so
+ *                    cigar_cap must be at least (total read bases + total
+ *                    reference bases); a pair whose CIGAR would pass cigar_cap
+ *                    gets GENASM_FLAG_CIGAR_OVERFLOW.
+ *   total_read_bases, total_ref_bases
+ *                    d_read_off[n_pairs] - d_read_off[0] and the same for refs
+ *                    (sizes the device scratch without a device-to-host copy).
+ *   max_ref_len      an upper bound on the longest reference (sizes scratch).
+ * The caller keeps every buffer alive until the stream has passed this call.
+ * Scratch is owned by the context; calls on one context are serialized on
+ * its device scratch, so do not run two calls of one context on different
+ * streams at once.
+ */
+int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
+                           const uint8_t* d_refs2b, const uint64_t* d_ref_off, uint64_t n_pairs,
+                           uint64_t total_read_bases, uint64_t total_ref_bases,
+                           uint32_t max_ref_len, int32_t k, int32_t W, int32_t O,
+                           genasm_result* d_out, uint32_t* d_cigar, uint64_t cigar_cap,
+                           const genasm_launch* launch, void* stream);
+
+/*
+ * Packs n ASCII bases (host memory) into 2-bit codes (host memory, (n+3)/4
+ * bytes, layout as for genasm_batch_align_dev). Returns GENASM_E_ALPHABET and
+ * sets *bad_index (if not NULL) to the first offending byte.
+ */
+int genasm_pack(const char* ascii, uint64_t n, uint8_t* packed, uint64_t* bad_index);
+
+/*
+ * Device version of genasm_pack, asynchronous on `stream`: packs d_ascii[0..n)
+ * into d_packed[0..(n+3)/4) and adds the number of non-ACGT bytes to
+ * *d_bad_count (device memory, caller-initialised).
+ */
+int genasm_pack_dev(genasm_ctx* ctx, const char* d_ascii, uint64_t n, uint8_t* d_packed,
+                    uint32_t* d_bad_count, void* stream);
+
+/*
+ * Checks arguments of a host-form call without touching a device: the values
+ * of W, O and k, the offsets (non-decreasing, in range of the given stream
+ * lengths) and the alphabet. Returns GENASM_OK or the code genasm_batch_align
+ * would return.
+ */
+int genasm_validate(const char* reads, uint64_t reads_len, const uint64_t* read_off,
+                    const char* refs, uint64_t refs_len, const uint64_t* ref_off,
+                    uint64_t n_pairs, int32_t k, int32_t W, int32_t O);
+
+/*
+ * Profiling of genasm_batch_align_dev calls (off by default). While enabled,
+ * each call records HIP events around its stages on the call's stream and
+ * fills per-pair work counters; genasm_profile_read waits for the last
+ * profiled call and returns its stage times and the counters summed over
+ * its pairs. Counters follow the GenASM recurrence: a DC window costs
+ * nw * (2 + 6 d*) 64-bit word operations (row 0: shift, or; rows 1..d*:
+ * and, shift, or, shift, and, and), the start search n * (2 + 6 d_min).
+ */
+typedef struct {
+    float total_ms;            /* first to last kernel of the call */
+    float order_ms;            /* longest-first ordering (batched form) */
+    float search_ms;           /* start-search kernels (batched form) */
+    float windows_ms;          /* window kernel (batched) or the whole plain kernel */
+    uint64_t n_pairs;
+    uint64_t window_word_ops;  /* sum of nw * (2 + 6 d*) */
+    uint64_t search_word_ops;  /* sum of n * (2 + 6 d_min) */
+    uint64_t window_cells;     /* sum over windows of mw * nw */
+    uint64_t search_cells;     /* sum of m1 * n */
+    uint64_t table_words;      /* sum of (d* + 1) * (min(nw, W-O) + 1): stored DP words */
+    uint64_t tb_reads;         /* DP words read by tracebacks */
+    uint64_t window_lane_steps;/* lane-steps issued by DC passes, speculative rows included */
+    uint64_t search_lane_steps;/* lane-cell-steps issued by the start search */
+} genasm_profile;
+
+int genasm_profile_enable(genasm_ctx* ctx, int on);
+int genasm_profile_read(genasm_ctx* ctx, genasm_profile* out);
+
+/* Library version string. */
+const char* genasm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GENASM_H */

@@ -1,0 +1,305 @@
+"""ctypes binding of libgenasm.so (declarations in include/genasm.h).
+
+Argument marshalling only: every step of the alignment runs in the library's
+HIP kernels. Loading fails loudly when the library has not been built; there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgenasm.so")
+
+OK = 0
+E_INVAL = -1
+E_ALPHABET = -2
+E_NOMEM = -3
+E_DEVICE = -4
+E_NOSPACE = -5
+E_BUSY = -6
+E_TOOLONG = -7
+
+FORM_PLAIN = 0
+FORM_BATCHED = 1
+
+FLAG_CIGAR_OVERFLOW = 1
+FLAG_INTERNAL = 2
+
+OP_CHARS = "=XID"
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("edit_distance", ctypes.c_int32),
+        ("ref_begin", ctypes.c_uint32),
+        ("ref_end", ctypes.c_uint32),
+        ("n_windows", ctypes.c_uint32),
+        ("cigar_off", ctypes.c_uint64),
+        ("cigar_len", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+RESULT_DTYPE = np.dtype([("edit_distance", "<i4"), ("ref_begin", "<u4"), ("ref_end", "<u4"),
+                         ("n_windows", "<u4"), ("cigar_off", "<u8"), ("cigar_len", "<u4"),
+                         ("flags", "<u4")])
+assert RESULT_DTYPE.itemsize == ctypes.sizeof(Result) == 32
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [
+        ("form", ctypes.c_int32),
+        ("group_lanes", ctypes.c_int32),
+        ("search_lanes", ctypes.c_int32),
+        ("lds_rows", ctypes.c_int32),
+        ("workers_per_cu", ctypes.c_int32),
+        ("lpt_order", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
+    ]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [
+        ("total_ms", ctypes.c_float),
+        ("order_ms", ctypes.c_float),
+        ("search_ms", ctypes.c_float),
+        ("windows_ms", ctypes.c_float),
+        ("n_pairs", ctypes.c_uint64),
+        ("window_word_ops", ctypes.c_uint64),
+        ("search_word_ops", ctypes.c_uint64),
+        ("window_cells", ctypes.c_uint64),
+        ("search_cells", ctypes.c_uint64),
+        ("table_words", ctypes.c_uint64),
+        ("tb_reads", ctypes.c_uint64),
+        ("window_lane_steps", ctypes.c_uint64),
+        ("search_lane_steps", ctypes.c_uint64),
+    ]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+# Every symbol include/genasm.h declares.
+EXPORTS = [
+    "genasm_create", "genasm_destroy", "genasm_last_error", "genasm_strerror",
+    "genasm_default_launch", "genasm_batch_align", "genasm_batch_align_dev", "genasm_pack",
+    "genasm_pack_dev", "genasm_validate", "genasm_version", "genasm_profile_enable",
+    "genasm_profile_read",
+]
+
+_c = ctypes
+_u8p = _c.POINTER(_c.c_uint8)
+_u64p = _c.POINTER(_c.c_uint64)
+_SIGS = {
+    "genasm_create": (_c.c_int, [_c.POINTER(_c.c_void_p), _c.c_int]),
+    "genasm_destroy": (None, [_c.c_void_p]),
+    "genasm_last_error": (_c.c_char_p, [_c.c_void_p]),
+    "genasm_strerror": (_c.c_char_p, [_c.c_int]),
+    "genasm_default_launch": (_c.c_int, [_c.c_int32, _c.POINTER(Launch)]),
+    "genasm_batch_align": (_c.c_int, [_c.c_void_p, _c.c_char_p, _u64p, _c.c_char_p, _u64p,
+                                      _c.c_uint64, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p,
+                                      _c.c_void_p, _c.c_uint64, _u64p, _c.POINTER(Launch)]),
+    "genasm_batch_align_dev": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                          _c.c_void_p, _c.c_uint64, _c.c_uint64, _c.c_uint64,
+                                          _c.c_uint32, _c.c_int32, _c.c_int32, _c.c_int32,
+                                          _c.c_void_p, _c.c_void_p, _c.c_uint64,
+                                          _c.POINTER(Launch), _c.c_void_p]),
+    "genasm_pack": (_c.c_int, [_c.c_char_p, _c.c_uint64, _c.c_void_p, _u64p]),
+    "genasm_pack_dev": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_uint64, _c.c_void_p,
+                                   _c.c_void_p, _c.c_void_p]),
+    "genasm_validate": (_c.c_int, [_c.c_char_p, _c.c_uint64, _u64p, _c.c_char_p, _c.c_uint64,
+                                   _u64p, _c.c_uint64, _c.c_int32, _c.c_int32, _c.c_int32]),
+    "genasm_version": (_c.c_char_p, []),
+    "genasm_profile_enable": (_c.c_int, [_c.c_void_p, _c.c_int]),
+    "genasm_profile_read": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+}
+
+_lib = None
+
+
+class GenasmError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        self.code = code
+        super().__init__(f"genasm error {code} ({strerror(code)}){': ' + msg if msg else ''}")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2203_15561_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().genasm_strerror(code).decode()
+
+
+def version() -> str:
+    return lib().genasm_version().decode()
+
+
+def default_launch(form: int = FORM_BATCHED) -> Launch:
+    L = Launch()
+    rc = lib().genasm_default_launch(form, ctypes.byref(L))
+    if rc:
+        raise GenasmError(rc)
+    return L
+
+
+def make_launch(form: int = FORM_BATCHED, **kw) -> Launch:
+    L = default_launch(form)
+    for key, val in kw.items():
+        setattr(L, key, int(val))
+    return L
+
+
+def _ascii(x) -> bytes:
+    if isinstance(x, str):
+        return x.encode()
+    if isinstance(x, (bytes, bytearray)):
+        return bytes(x)
+    a = np.asarray(x, dtype=np.uint8)
+    return np.frombuffer(b"ACGT", dtype=np.uint8)[a].tobytes()
+
+
+def _concat(seqs):
+    parts = [_ascii(s) for s in seqs]
+    off = np.zeros(len(parts) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([len(p) for p in parts], dtype=np.uint64)
+    return b"".join(parts), off
+
+
+def pack(seq) -> np.ndarray:
+    """2-bit packing of an ACGT sequence by the library's host packer."""
+    b = _ascii(seq)
+    out = np.zeros((len(b) + 3) // 4, dtype=np.uint8)
+    bad = ctypes.c_uint64(0)
+    rc = lib().genasm_pack(b, len(b), out.ctypes.data, ctypes.byref(bad))
+    if rc:
+        raise GenasmError(rc, f"at byte {bad.value}")
+    return out
+
+
+def validate(reads, refs, k: int, W: int = 64, O: int = 24) -> int:
+    r, roff = _concat(reads)
+    f, foff = _concat(refs)
+    return lib().genasm_validate(r, len(r), roff.ctypes.data_as(_u64p), f, len(f),
+                                 foff.ctypes.data_as(_u64p), len(roff) - 1, k, W, O)
+
+
+def decode_cigar(elems) -> str:
+    """Text form of device CIGAR elements."""
+    e = np.asarray(elems, dtype=np.uint32)
+    return "".join(f"{int(x) >> 2}{OP_CHARS[int(x) & 3]}" for x in e)
+
+
+class Context:
+    """One HIP device context (stream + scratch). Not thread-safe."""
+
+    def __init__(self, device: int = 0):
+        self._ctx = ctypes.c_void_p()
+        rc = lib().genasm_create(ctypes.byref(self._ctx), device)
+        if rc:
+            raise GenasmError(rc, "genasm_create: " + lib().genasm_last_error(None).decode())
+        self.device = device
+
+    def close(self):
+        if self._ctx:
+            lib().genasm_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+    def last_error(self) -> str:
+        return lib().genasm_last_error(self._ctx).decode()
+
+    def _check(self, rc: int, what: str):
+        if rc:
+            raise GenasmError(rc, f"{what}: {self.last_error()}")
+
+    def align(self, reads, refs, k: int, W: int = 64, O: int = 24, launch: Launch | None = None):
+        """Host-memory form. Returns (results structured array, list of CIGAR strings)."""
+        r, roff = _concat(reads)
+        f, foff = _concat(refs)
+        n = len(roff) - 1
+        out = np.zeros(n, dtype=RESULT_DTYPE)
+        need = ctypes.c_uint64(0)
+        cap = 4 * (len(r) + len(f)) + 16
+        buf = ctypes.create_string_buffer(cap)
+        rc = lib().genasm_batch_align(self._ctx, r, roff.ctypes.data_as(_u64p), f,
+                                      foff.ctypes.data_as(_u64p), n, k, W, O, out.ctypes.data,
+                                      buf, cap, ctypes.byref(need),
+                                      ctypes.byref(launch) if launch is not None else None)
+        if rc == E_NOSPACE:
+            buf = ctypes.create_string_buffer(int(need.value))
+            rc = lib().genasm_batch_align(self._ctx, r, roff.ctypes.data_as(_u64p), f,
+                                          foff.ctypes.data_as(_u64p), n, k, W, O,
+                                          out.ctypes.data, buf, need.value, ctypes.byref(need),
+                                          ctypes.byref(launch) if launch is not None else None)
+        self._check(rc, "genasm_batch_align")
+        raw = buf.raw
+        cig = [raw[int(o):int(o) + int(L)].decode() for o, L in zip(out["cigar_off"], out["cigar_len"])]
+        return out, cig
+
+    def align_dev(self, reads2b, read_off, refs2b, ref_off, k: int, W: int = 64, O: int = 24,
+                  launch: Launch | None = None, out=None, cigar=None, stream=None,
+                  total_read_bases=None, total_ref_bases=None, max_ref_len: int = 0):
+        """Device-memory form on torch tensors (uint8 packed streams, int64
+        offsets). Returns (out uint8 tensor [n, 32], cigar int32 tensor)."""
+        import torch
+        n = read_off.numel() - 1
+        if total_read_bases is None:
+            total_read_bases = int(read_off[-1] - read_off[0])
+        if total_ref_bases is None:
+            total_ref_bases = int(ref_off[-1] - ref_off[0])
+        if out is None:
+            out = torch.empty((max(n, 1), 32), dtype=torch.uint8, device=read_off.device)
+        cap = total_read_bases + total_ref_bases
+        if cigar is None:
+            cigar = torch.empty(max(cap, 1), dtype=torch.int32, device=read_off.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(read_off.device).cuda_stream
+        rc = lib().genasm_batch_align_dev(
+            self._ctx, reads2b.data_ptr(), read_off.data_ptr(), refs2b.data_ptr(),
+            ref_off.data_ptr(), n, total_read_bases, total_ref_bases, max_ref_len, k, W, O,
+            out.data_ptr(), cigar.data_ptr(), cigar.numel(),
+            ctypes.byref(launch) if launch is not None else None, stream)
+        self._check(rc, "genasm_batch_align_dev")
+        return out, cigar
+
+    def profile(self, on: bool = True):
+        self._check(lib().genasm_profile_enable(self._ctx, int(on)), "genasm_profile_enable")
+
+    def profile_read(self) -> dict:
+        pr = Profile()
+        self._check(lib().genasm_profile_read(self._ctx, ctypes.byref(pr)), "genasm_profile_read")
+        return pr.as_dict()
+
+    def pack_dev(self, ascii_dev, packed_dev, bad_dev, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(ascii_dev.device).cuda_stream
+        rc = lib().genasm_pack_dev(self._ctx, ascii_dev.data_ptr(), ascii_dev.numel(),
+                                   packed_dev.data_ptr(), bad_dev.data_ptr(), stream)
+        self._check(rc, "genasm_pack_dev")

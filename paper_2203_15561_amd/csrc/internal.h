@@ -1,0 +1,87 @@
+// Internal interface between the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "genasm.h"
+
+namespace genasm {
+
+// Per-pair start-search outcome kept in device scratch.
+struct SearchOut {
+    int32_t row;   // least edit row with a hit; kSearchFailed / kSearchDone when no window work
+    uint32_t col;  // leftmost hit column of that row
+};
+constexpr int32_t kSearchFailed = -1;  // no hit within K rows: the result is already written
+constexpr int32_t kSearchDone = -2;    // empty read: the result is already written
+constexpr int32_t kSearchPending = -3; // not searched yet (retry list)
+
+struct AlignParams {
+    const uint8_t* reads;       // 2-bit packed read stream
+    const uint64_t* read_off;   // n_pairs + 1 base offsets
+    const uint8_t* refs;        // 2-bit packed reference stream
+    const uint64_t* ref_off;
+    uint64_t n_pairs;
+    int32_t K;                  // min(k, W)
+    int32_t W;
+    int32_t L;                  // W - O: bases committed per window at most
+    int32_t stride;             // words per stored table row: L + 3
+    genasm_result* out;
+    uint32_t* cigar;            // CIGAR elements
+    uint64_t cigar_cap;
+    SearchOut* search;          // per pair
+    const uint32_t* order;      // window-kernel pair order (null = identity)
+    uint32_t* counters;         // device queue heads and list lengths (see kCounter*)
+    const uint32_t* list_in;    // search kernel: pairs to search (null = all pairs)
+    uint32_t* list_out;         // search kernel: pairs that need more rows
+    unsigned long long* spill;  // window table rows >= lds_rows, per worker
+    int32_t lds_rows;
+    int32_t list_slot;          // which counters[] pair this search stage uses
+    unsigned long long* stats;  // optional, kStatCount counters per pair (null = off)
+};
+
+// Per-pair work counters written when AlignParams::stats is set.
+constexpr int kStatWindowWordOps = 0;   // sum over windows of nw * (2 + 6 d*)  (64-bit DC ops)
+constexpr int kStatSearchWordOps = 1;   // n * (2 + 6 d_min)
+constexpr int kStatWindowCells = 2;     // sum over windows of mw * nw
+constexpr int kStatSearchCells = 3;     // m1 * n
+constexpr int kStatTableWords = 4;      // sum over windows of (d* + 1) * (min(nw, W-O) + 1)
+constexpr int kStatTbReads = 5;         // table words read by traceback
+constexpr int kStatWindowLaneSteps = 6; // lane-steps issued by DC passes (speculative rows included)
+constexpr int kStatSearchLaneSteps = 7; // lane-steps issued by the start search (all stages)
+constexpr int kStatCount = 8;
+
+// counters[] layout: queue heads and list lengths for the batched pipeline.
+constexpr int kCounterWindowHead = 0;
+constexpr int kCounterListBase = 2;  // stage s: counters[2 + 2s] = list length, [3 + 2s] = head
+constexpr int kCounterCount = 16;
+
+// LDS words per group, by kernel.
+constexpr int kGroupHeaderWords = 160;
+__host__ __device__ inline int window_group_words(int lds_rows, int stride) {
+    return kGroupHeaderWords + lds_rows * stride;
+}
+constexpr int kSearchGroupWords = kGroupHeaderWords;  // PM, ring, broadcast slots
+
+// Kernel launchers (kernels.hip). All return hipError_t of the launch.
+hipError_t launch_plain(const AlignParams& p, hipStream_t s);
+hipError_t launch_search(const AlignParams& p, int group_lanes, int rows_per_lane, int blocks,
+                         hipStream_t s);
+hipError_t launch_windows(const AlignParams& p, int group_lanes, int blocks, hipStream_t s);
+hipError_t launch_pack(const char* ascii, uint64_t n, uint8_t* packed, uint32_t* bad,
+                       hipStream_t s);
+hipError_t launch_init_counters(uint32_t* counters, uint32_t stage0_len, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_lpt_keys(const uint64_t* read_off, uint64_t n_pairs, uint32_t* keys,
+                           uint32_t* vals, hipStream_t s);
+hipError_t launch_compact_cigar(const genasm_result* d_out, const uint64_t* dst_off,
+                                uint64_t n_pairs, const uint32_t* cigar, uint32_t* dst,
+                                hipStream_t s);
+
+// Occupancy helpers.
+int plain_lds_bytes(int stride);
+int window_lds_bytes(int group_lanes, int lds_rows, int stride);
+int search_lds_bytes(int group_lanes);
+
+}  // namespace genasm

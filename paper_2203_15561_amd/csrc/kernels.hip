@@ -1,0 +1,800 @@
+// gfx950 kernels of the GenASM aligner: 2-bit packing, start search, windowed
+// DC + TB with the paper's three improvements (Introduction, key ideas 1-3),
+// and CIGAR compaction.
+//
+// Work decomposition. A "group" is G consecutive lanes of a 64-lane wavefront
+// (G = 16 or 64) that handles one (read, reference) pair at a time. Lane gl
+// of the group owns DP row d = c*G + gl in pass c, and the G rows advance as an
+// anti-diagonal wavefront over the text columns: at step t lane gl computes
+// column i = nw-1-t+gl, so the row above (lane gl-1) produced column i one step
+// earlier and hands it over with a one-lane DPP shift (row_shr:1 inside a
+// 16-lane row, wave_shr:1 across the whole wavefront). Each cell is
+//   R[d][i] = D & (((D & U) << 1) | [d == 0]) & ((R[d][i+1] << 1) | PM[T[i]])
+// with D = R[d-1][i+1] and U = R[d-1][i]; this is the AND of the match,
+// substitution, insertion and deletion bitvectors of the GenASM recurrence,
+// folded into four 64-bit operations.
+//
+// Improvement 1: only R (the AND) is stored per entry. Improvement 2: rows are
+// computed G at a time and no further pass runs once a row's column 0 has its
+// top bit clear. Improvement 3: only columns 0..min(nw, W-O) are stored, the
+// only ones the traceback of a window can reach; rows at or above the read
+// window length are never stored at all (their used bits are all zero).
+// The stored table lives in LDS; rows past `lds_rows` spill to device memory.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace genasm {
+
+typedef unsigned long long u64;
+
+// ---------------------------------------------------------------------------
+// Small device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ u64 init_word(int d) { return d >= 64 ? 0ull : (~0ull << d); }
+
+__device__ __forceinline__ int clampi(int x, int lo, int hi) { return min(max(x, lo), hi); }
+
+// Shift a 64-bit value by one lane with a DPP move; lanes without a source lane
+// inside their DPP row (or the wavefront, for wave_shr) receive `old`.
+template <int CTRL>
+__device__ __forceinline__ u64 dpp64(u64 old, u64 src) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)old, (int)(unsigned)src,
+                                                              CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(old >> 32),
+                                                              (int)(unsigned)(src >> 32), CTRL, 0xF,
+                                                              0xF, false);
+    return ((u64)hi << 32) | lo;
+}
+
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppRowRor1 = 0x121;
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveRor1 = 0x13C;
+
+template <int G> struct LaneShift;
+template <> struct LaneShift<16> {
+    // value of lane gl-1 within the 16-lane group; lane 0 gets `old`
+    static __device__ __forceinline__ u64 up(u64 old, u64 v) { return dpp64<kDppRowShr1>(old, v); }
+    // value of lane gl-1, lane 0 gets lane 15 (rotation inside the group)
+    static __device__ __forceinline__ u64 rot(u64 v) { return dpp64<kDppRowRor1>(v, v); }
+};
+template <> struct LaneShift<64> {
+    static __device__ __forceinline__ u64 up(u64 old, u64 v) { return dpp64<kDppWaveShr1>(old, v); }
+    static __device__ __forceinline__ u64 rot(u64 v) { return dpp64<kDppWaveRor1>(v, v); }
+};
+
+// Orders the LDS accesses of one wavefront: the compiler may not move memory
+// operations across it, and it waits for the wavefront's outstanding LDS
+// operations (LDS executes one wavefront's operations in order).
+// s_waitcnt immediates (gfx9 encoding): lgkmcnt(0) alone, and vmcnt(0) lgkmcnt(0).
+constexpr int kWaitLgkm0 = 0xC07F;
+constexpr int kWaitVm0Lgkm0 = 0x0070;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// As wave_sync, and also waits for the wavefront's device-memory accesses.
+__device__ __forceinline__ void mem_sync() {
+    __builtin_amdgcn_s_waitcnt(kWaitVm0Lgkm0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int base_at(const uint8_t* s, uint64_t b) {
+    return (s[b >> 2] >> ((unsigned)(b & 3) * 2)) & 3;
+}
+
+__device__ __forceinline__ u64 pick_pm(u64 p0, u64 p1, u64 p2, u64 p3, int c) {
+    const u64 lo = (c & 1) ? p1 : p0;
+    const u64 hi = (c & 1) ? p3 : p2;
+    return (c & 2) ? hi : lo;
+}
+
+__device__ __forceinline__ u64 group_ballot(bool pred, int G, int lane) {
+    const u64 b = __ballot(pred);
+    if (G == 64) return b;
+    const int shift = lane & ~(G - 1);
+    return (b >> shift) & ((1ull << G) - 1);
+}
+
+// Device-memory loads that bypass the per-CU vector cache (the spill area is
+// rewritten every window).
+__device__ __forceinline__ u64 load_coherent(const u64* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Per-group LDS layout (64-bit words).
+constexpr int OFF_PM = 0;      // 4 pattern masks / match accumulators
+constexpr int OFF_PMT = 4;     // PM[T[i]] for i in 0..nw, ~0 at nw..64 (66 words)
+constexpr int OFF_BROW = 70;   // boundary row between passes: slot 1+i, i in -1..nw+1 (68 words)
+constexpr int OFF_CH = 138;    // 64 pattern bytes, 64 text bytes (16 words)
+constexpr int OFF_BC = 154;    // broadcast slots (4 words)
+constexpr int OFF_TAB = 160;   // stored table rows, `stride` words each
+static_assert(OFF_TAB == kGroupHeaderWords, "layout");
+constexpr int OFF_RING = 4;    // start search: 128-word text-mask ring (reuses PMT + BROW)
+
+// ---------------------------------------------------------------------------
+// Pattern masks
+// ---------------------------------------------------------------------------
+
+// Builds PM for pattern bases P[0..mw) (read stream offset rb) into
+// lds[OFF_PM..+4): bit q of PM[c] is 0 iff P[mw-1-q] == c. Also stores the
+// pattern bases as bytes at OFF_CH when `keep_chars`.
+template <int G>
+__device__ void build_pm(u64* lds, int gl, const uint8_t* reads, uint64_t rb, int mw,
+                         bool keep_chars) {
+    uint8_t* pch = reinterpret_cast<uint8_t*>(lds + OFF_CH);
+    u64* acc = lds + OFF_PM;
+    if (gl < 4) acc[gl] = 0ull;
+    wave_sync();
+#pragma unroll
+    for (int u = 0; u < 64 / G; ++u) {
+        const int b = gl + u * G;
+        const int c = b < mw ? base_at(reads, rb + b) : 0;
+        if (keep_chars) pch[b] = (uint8_t)c;
+        if (b < mw) atomicOr(&acc[c], 1ull << (mw - 1 - b));
+    }
+    wave_sync();
+    if (gl < 4) acc[gl] = ~acc[gl];
+    wave_sync();
+}
+
+// Loads a window: pattern bases, text bases, PM and PMT (PM[T[i]] per column).
+template <int G>
+__device__ void load_window(u64* lds, int gl, const uint8_t* reads, uint64_t rb, int mw,
+                           const uint8_t* refs, uint64_t fb, int nw) {
+    uint8_t* tch = reinterpret_cast<uint8_t*>(lds + OFF_CH) + 64;
+    build_pm<G>(lds, gl, reads, rb, mw, true);
+    const u64 p0 = lds[OFF_PM + 0], p1 = lds[OFF_PM + 1], p2 = lds[OFF_PM + 2],
+              p3 = lds[OFF_PM + 3];
+    u64* pmt = lds + OFF_PMT;
+#pragma unroll
+    for (int u = 0; u < 64 / G; ++u) {
+        const int i = gl + u * G;
+        const int c = i < nw ? base_at(refs, fb + i) : 0;
+        tch[i] = (uint8_t)c;
+        pmt[i] = i < nw ? pick_pm(p0, p1, p2, p3, c) : ~0ull;
+    }
+    if (gl == 0) pmt[64] = ~0ull;
+    wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// DC: one pass of G rows over a window
+// ---------------------------------------------------------------------------
+
+// Computes rows c*G .. c*G+G-1 (this lane: row c*G+gl) over columns nw-1..0.
+// Stores columns 0..Lc of the row (slots 1..Lc+1 of its table row; slot 0 and
+// Lc+2 absorb the out-of-window steps). Lane G-1 writes its row into the
+// boundary row, which lane 0 of the next pass reads as the row above.
+template <int G, bool SPILL>
+__device__ void dc_pass(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int stride,
+                        int lds_rows) {
+    const u64* pmt = lds + OFF_PMT;
+    u64* brow = lds + OFF_BROW;
+    const int d = c * G + gl;
+    u64* trow = SPILL ? spill + (size_t)(d - lds_rows) * stride : lds + OFF_TAB + d * stride;
+    u64 R = init_word(d);
+    u64 Dp = d == 0 ? ~0ull : init_word(d - 1);
+    const u64 lowin = d == 0 ? 1ull : 0ull;
+    const bool first = (c == 0);
+    const int steps = nw + G - 1;
+    constexpr int U = 4;
+    u64 qpm[U], qov[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int i = nw - 1 - u + gl;
+        qpm[u] = pmt[clampi(i, 0, nw)];
+        qov[u] = first ? ~0ull : brow[1 + clampi(i, -1, nw + 1)];
+    }
+    for (int t0 = 0; t0 < steps; t0 += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = nw - 1 - (t0 + u) + gl;
+            const u64 pm_t = qpm[u];
+            const u64 ov = qov[u];
+            // operands of step t0+u+U (its column is i-U); the boundary row entry it
+            // reads is written by lane G-1 only G-1+U steps later
+            const int ip = i - U;
+            qpm[u] = pmt[clampi(ip, 0, nw)];
+            qov[u] = first ? ~0ull : brow[1 + clampi(ip, -1, nw + 1)];
+            const u64 up = LaneShift<G>::up(ov, R);
+            const u64 x = Dp & (((Dp & up) << 1) | lowin);
+            R = x & ((R << 1) | pm_t);
+            Dp = up;
+            trow[1 + clampi(i, -1, Lc + 1)] = R;
+            if (gl == G - 1) brow[1 + clampi(i, -1, nw + 1)] = R;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Start search: rows 0.. of the first read window against the whole reference
+// ---------------------------------------------------------------------------
+
+// RS rows per lane: slot s of lane gl is row s*G + gl, lagging slot s-1 by G
+// steps; lane 0 of slot s takes lane G-1 of slot s-1 through the rotation.
+// Returns (in *row, *col) the least row <= Kr with a hit and its leftmost
+// column, or row = -1 when rows 0..min(Kr, RS*G-1) have none.
+template <int G, int RS>
+__device__ void search_rows(u64* lds, int gl, int lane, const uint8_t* refs, uint64_t fb, int n,
+                            int m1, int Kr, int* row_out, int* col_out) {
+    const u64 p0 = lds[OFF_PM + 0], p1 = lds[OFF_PM + 1], p2 = lds[OFF_PM + 2],
+              p3 = lds[OFF_PM + 3];
+    u64* ring = lds + OFF_RING;
+    constexpr int BPL = 64 / G;  // text bases each lane converts per 64-column block
+    constexpr int O = RS * G;
+    const int top = m1 - 1;
+    // columns n..n+63 lie past the text end: the all-mismatch mask
+#pragma unroll
+    for (int u = 0; u < BPL; ++u) ring[(n + gl * BPL + u) & 127] = ~0ull;
+
+    u64 R[RS], Dp[RS];
+    int hit[RS];
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+        const int d = s * G + gl;
+        R[s] = init_word(d);
+        Dp[s] = d == 0 ? ~0ull : init_word(d - 1);
+        hit[s] = -1;
+    }
+    const u64 lowin = gl == 0 ? 1ull : 0ull;  // slot 0 only
+
+    auto fetch = [&](int blk) -> unsigned {
+        const int c0 = n - 64 * (blk + 1) + gl * BPL;
+        unsigned v = 0;
+#pragma unroll
+        for (int u = 0; u < BPL; ++u) {
+            const int col = c0 + u;
+            if (col >= 0 && col < n) v |= (unsigned)base_at(refs, fb + col) << (2 * u);
+        }
+        return v;
+    };
+
+    const int steps = n + O - 1;
+    const int nblk = (steps + 63) / 64;
+    unsigned cur = fetch(0);
+    for (int blk = 0; blk < nblk; ++blk) {
+        // fill ring entries of this block's columns, prefetch the next block's bases
+        const int c0 = n - 64 * (blk + 1) + gl * BPL;
+#pragma unroll
+        for (int u = 0; u < BPL; ++u) {
+            const int col = c0 + u;
+            ring[col & 127] = pick_pm(p0, p1, p2, p3, (cur >> (2 * u)) & 3);
+        }
+        cur = fetch(blk + 1);
+        wave_sync();
+        const int t0 = blk * 64;
+#pragma unroll 8
+        for (int tt = 0; tt < 64; ++tt) {
+            const int t = t0 + tt;
+            u64 rot[RS];
+#pragma unroll
+            for (int s = 0; s < RS; ++s) rot[s] = LaneShift<G>::rot(R[s]);
+#pragma unroll
+            for (int s = 0; s < RS; ++s) {
+                const int i = n - 1 - t + s * G + gl;
+                const u64 pm_t = ring[i & 127];
+                const u64 up = gl == 0 ? (s == 0 ? ~0ull : rot[s - 1]) : rot[s];
+                const u64 li = s == 0 ? lowin : 0ull;
+                const u64 x = Dp[s] & (((Dp[s] & up) << 1) | li);
+                R[s] = x & ((R[s] << 1) | pm_t);
+                Dp[s] = up;
+                const bool h = i >= 0 && !((R[s] >> top) & 1ull);
+                hit[s] = h ? i : hit[s];
+            }
+        }
+        wave_sync();
+    }
+    // least row with a hit
+    int row = -1;
+#pragma unroll
+    for (int s = RS - 1; s >= 0; --s) {
+        const int d = s * G + gl;
+        const u64 bits = group_ballot(hit[s] >= 0 && d <= Kr, G, lane);
+        if (bits) {
+            const int w = __builtin_ctzll(bits);
+            row = s * G + w;
+            if (gl == w) lds[OFF_BC] = (u64)(unsigned)hit[s];
+        }
+    }
+    wave_sync();
+    *row_out = row;
+    *col_out = row >= 0 ? (int)(unsigned)lds[OFF_BC] : 0;
+    wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// One pair: windows (DC passes + TB + stitching), run by all G lanes of a group
+// ---------------------------------------------------------------------------
+
+struct PairCursor {
+    uint64_t rb, fb;      // read / reference stream base offsets
+    int m, n;
+    int ti, pj;
+};
+
+struct TbOut {
+    int i_end, j_end, edits;
+    uint32_t reads;  // table words read
+    bool internal;
+};
+
+// Reads stored R[row][col] for the traceback.
+__device__ __forceinline__ u64 read_r(const u64* lds, const u64* spill, int row, int col, int nw,
+                                      int mw, int lds_rows, int stride) {
+    if (row >= mw) return 0ull;                  // rows >= mw: every used bit is 0
+    if (col == nw) return init_word(row);        // the column past the text end
+    if (row < lds_rows) return lds[OFF_TAB + row * stride + 1 + col];
+    return load_coherent(spill + (size_t)(row - lds_rows) * stride + 1 + col);
+}
+
+// CIGAR run writer, held by lane 0 of a group.
+struct RunWriter {
+    uint32_t* cigar;
+    uint64_t base, limit;  // element range of this pair
+    uint32_t n;
+    uint32_t cur_len;
+    int cur_op;
+    bool overflow;
+    __device__ void flush() {
+        if (cur_len) {
+            const uint64_t idx = base + n;
+            if (idx < limit) cigar[idx] = (cur_len << 2) | (uint32_t)cur_op;
+            else overflow = true;
+            ++n;
+        }
+        cur_len = 0;
+    }
+    __device__ void push(int op) {
+        if (op == cur_op && cur_len) {
+            ++cur_len;
+        } else {
+            flush();
+            cur_op = op;
+            cur_len = 1;
+        }
+    }
+};
+
+// Traceback of one window from (i=0, p=mw-1, d=dstar); lane 0 of the group only.
+__device__ TbOut traceback(const u64* lds, const u64* spill, int mw, int nw, int dstar, int L,
+                           int lds_rows, int stride, RunWriter& rw) {
+    const uint8_t* pch = reinterpret_cast<const uint8_t*>(lds + OFF_CH);
+    const uint8_t* tch = pch + 64;
+    int i = 0, p = mw - 1, d = dstar, j = 0;
+    TbOut o{0, 0, 0, 0u, false};
+    while (p >= 0 && i < L && j < L) {
+        const u64 A = read_r(lds, spill, d, i + 1, nw, mw, lds_rows, stride);
+        const u64 B = d >= 1 ? read_r(lds, spill, d - 1, i + 1, nw, mw, lds_rows, stride) : ~0ull;
+        const u64 C = d >= 1 ? read_r(lds, spill, d - 1, i, nw, mw, lds_rows, stride) : ~0ull;
+        const bool intext = i < nw;
+        const int pc = pch[j];
+        const int tc = tch[i < 64 ? i : 63];
+        const bool p0 = p == 0;
+        const int q = p0 ? 0 : p - 1;
+        const bool m_ok = intext && pc == tc && (p0 || !((A >> q) & 1ull));
+        const bool s_ok = d >= 1 && intext && (p0 || !((B >> q) & 1ull));
+        const bool i_ok = d >= 1 && (p0 || !((C >> q) & 1ull));
+        const bool d_ok = d >= 1 && intext && !((B >> p) & 1ull);
+        int op;
+        if (m_ok) op = GENASM_OP_MATCH;
+        else if (s_ok) op = GENASM_OP_MISMATCH;
+        else if (i_ok) op = GENASM_OP_INS;
+        else if (d_ok) op = GENASM_OP_DEL;
+        else { o.internal = true; break; }
+        rw.push(op);
+        o.reads += d >= 1 ? 3u : 1u;
+        i += op != GENASM_OP_INS;
+        p -= op != GENASM_OP_DEL;
+        d -= op != GENASM_OP_MATCH;
+        j = mw - 1 - p;
+    }
+    o.i_end = i;
+    o.j_end = j;
+    o.edits = dstar - d;
+    return o;
+}
+
+// Aligns the windows of one pair whose start search gave column `s`.
+// All G lanes of the group call this together; returns in lane 0 the result.
+template <int G>
+__device__ void align_windows(const AlignParams& P, u64* lds, u64* spill, int gl, int lane,
+                              uint64_t pair, const PairCursor& pc0, int s, genasm_result* res) {
+    PairCursor pc = pc0;
+    pc.ti = s;
+    pc.pj = 0;
+    const uint64_t run_base = (P.read_off[pair] - P.read_off[0]) + (P.ref_off[pair] - P.ref_off[0]);
+    RunWriter rw{P.cigar, run_base, min(P.cigar_cap, run_base + (uint64_t)pc.m + (uint64_t)pc.n), 0,
+                 0, 0, false};
+    int64_t score = 0;
+    uint32_t nwin = 0;
+    u64 st_wops = 0, st_cells = 0, st_table = 0, st_tb = 0, st_steps = 0;
+    bool failed = false, internal = false;
+    // Every window commits at least one base, so a pair has at most m + n
+    // windows; the cap keeps the loop finite even if that ever failed.
+    const uint32_t max_windows = (uint32_t)pc.m + (uint32_t)pc.n + 1u;
+    while (pc.pj < pc.m) {
+        if (nwin >= max_windows) { failed = true; internal = true; break; }
+        const int mw = min(P.W, pc.m - pc.pj);
+        const int nw = min(P.W, pc.n - pc.ti);
+        const int Lc = min(nw, P.L);
+        ++nwin;
+        load_window<G>(lds, gl, P.reads, pc.rb + pc.pj, mw, P.refs, pc.fb + pc.ti, nw);
+        // rows that need computing; row mw always solves. With an empty text
+        // window every column is the initial one and row mw is the first hit.
+        const int Kr = nw > 0 ? min(P.K, mw - 1) : -1;
+        int dstar = -1;
+        st_cells += (u64)mw * nw;
+        for (int c = 0; c * G <= Kr; ++c) {
+            st_steps += (u64)G * (nw + G - 1);
+            const bool spill_pass = c * G >= P.lds_rows;
+            if (spill_pass) {
+                dc_pass<G, true>(lds, spill, gl, c, nw, Lc, P.stride, P.lds_rows);
+                mem_sync();
+            } else {
+                dc_pass<G, false>(lds, spill, gl, c, nw, Lc, P.stride, P.lds_rows);
+                wave_sync();
+            }
+            const int d = c * G + gl;
+            const u64 r0 = spill_pass ? load_coherent(spill + (size_t)(d - P.lds_rows) * P.stride + 1)
+                                      : lds[OFF_TAB + d * P.stride + 1];
+            const bool sol = d <= Kr && !((r0 >> (mw - 1)) & 1ull);
+            const u64 bits = group_ballot(sol, G, lane);
+            if (bits) { dstar = c * G + __builtin_ctzll(bits); break; }
+        }
+        if (dstar < 0) {
+            if (mw <= P.K) dstar = mw;  // no row below mw solves: d* = mw
+            else { failed = true; break; }
+        }
+        if (gl == 0) {
+            TbOut t = traceback(lds, spill, mw, nw, dstar, P.L, P.lds_rows, P.stride, rw);
+            internal |= t.internal;
+            score += t.edits;
+            st_tb += t.reads;
+            st_wops += (u64)nw * (2 + 6 * dstar);
+            st_table += (u64)(dstar + 1) * (Lc + 1);
+            lds[OFF_BC + 1] = ((u64)(unsigned)t.i_end << 32) | (unsigned)t.j_end;
+            lds[OFF_BC + 2] = t.internal ? 1ull : 0ull;
+        }
+        wave_sync();
+        const u64 adv = lds[OFF_BC + 1];
+        const bool bad = lds[OFF_BC + 2] != 0;
+        wave_sync();
+        if (bad) { failed = true; internal = true; break; }
+        pc.ti += (int)(adv >> 32);
+        pc.pj += (int)(unsigned)adv;
+    }
+    if (gl == 0) {
+        genasm_result r;
+        if (failed) {
+            r.edit_distance = -1;
+            r.ref_begin = r.ref_end = 0;
+            r.cigar_len = 0;
+        } else {
+            rw.flush();
+            r.edit_distance = (int32_t)score;
+            r.ref_begin = (uint32_t)s;
+            r.ref_end = (uint32_t)pc.ti;
+            r.cigar_len = rw.overflow ? 0u : rw.n;
+        }
+        r.n_windows = nwin;
+        r.cigar_off = run_base;
+        r.flags = (rw.overflow && !failed ? GENASM_FLAG_CIGAR_OVERFLOW : 0u) |
+                  (internal ? GENASM_FLAG_INTERNAL : 0u);
+        *res = r;
+        if (P.stats) {
+            u64* st = P.stats + pair * kStatCount;
+            st[kStatWindowWordOps] = st_wops;
+            st[kStatWindowCells] = st_cells;
+            st[kStatTableWords] = st_table;
+            st[kStatTbReads] = st_tb;
+            st[kStatWindowLaneSteps] = st_steps;
+        }
+    }
+}
+
+// Start-search counters of one pair (lane 0); `row` is the hit row or, when
+// no row hit, the last row computed. Lane-steps add up over search stages.
+__device__ __forceinline__ void search_stats(const AlignParams& P, uint64_t pair, int n, int m1,
+                                             int row, u64 lane_steps, bool first_stage) {
+    if (!P.stats) return;
+    u64* st = P.stats + pair * kStatCount;
+    st[kStatSearchWordOps] = (u64)n * (2 + 6 * (u64)max(row, 0));
+    st[kStatSearchCells] = (u64)m1 * n;
+    st[kStatSearchLaneSteps] = (first_stage ? 0ull : st[kStatSearchLaneSteps]) + lane_steps;
+}
+
+__device__ __forceinline__ void write_simple_result(genasm_result* res, int32_t score,
+                                                    uint64_t run_base) {
+    genasm_result r;
+    r.edit_distance = score;
+    r.ref_begin = r.ref_end = 0;
+    r.n_windows = 0;
+    r.cigar_off = run_base;
+    r.cigar_len = 0;
+    r.flags = 0;
+    *res = r;
+}
+
+__device__ __forceinline__ PairCursor pair_cursor(const AlignParams& P, uint64_t pair) {
+    PairCursor pc;
+    pc.rb = P.read_off[pair];
+    pc.fb = P.ref_off[pair];
+    pc.m = (int)(P.read_off[pair + 1] - pc.rb);
+    pc.n = (int)(P.ref_off[pair + 1] - pc.fb);
+    pc.ti = pc.pj = 0;
+    return pc;
+}
+
+__device__ __forceinline__ uint64_t pair_run_base(const AlignParams& P, uint64_t pair) {
+    return (P.read_off[pair] - P.read_off[0]) + (P.ref_off[pair] - P.ref_off[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Plain form: one pair per workgroup, 64 lanes = 64 rows
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(64) void k_plain(AlignParams P) {
+    extern __shared__ u64 smem[];
+    const int lane = threadIdx.x;
+    const uint64_t pair = blockIdx.x;
+    if (pair >= P.n_pairs) return;
+    const PairCursor pc = pair_cursor(P, pair);
+    genasm_result* res = P.out + pair;
+    if (pc.m == 0) {
+        if (lane == 0) write_simple_result(res, 0, pair_run_base(P, pair));
+        return;
+    }
+    const int m1 = min(P.W, pc.m);
+    const int Kr = min(P.K, m1 - 1);
+    build_pm<64>(smem, lane, P.reads, pc.rb, m1, false);
+    int row, col;
+    search_rows<64, 1>(smem, lane, lane, P.refs, pc.fb, pc.n, m1, Kr, &row, &col);
+    if (lane == 0)
+        search_stats(P, pair, pc.n, m1, row >= 0 ? row : (m1 <= P.K ? m1 : Kr), 64ull * (pc.n + 63), true);
+    if (row < 0) {
+        if (m1 <= P.K) { row = m1; col = 0; }   // row m1 hits in every column
+        else {
+            if (lane == 0) write_simple_result(res, -1, pair_run_base(P, pair));
+            return;
+        }
+    }
+    align_windows<64>(P, smem, nullptr, lane, lane, pair, pc, col, res);
+}
+
+// ---------------------------------------------------------------------------
+// Batched form: start search with a retry list, then a persistent window kernel
+// ---------------------------------------------------------------------------
+
+// Pops one item per group from a device queue; returns the same value in all
+// lanes of the group.
+__device__ __forceinline__ uint32_t group_pop(uint32_t* head, u64* lds, int gl) {
+    if (gl == 0) lds[OFF_BC + 3] = atomicAdd(head, 1u);
+    wave_sync();
+    const uint32_t v = (uint32_t)lds[OFF_BC + 3];
+    wave_sync();
+    return v;
+}
+
+template <int G, int RS>
+__global__ __launch_bounds__(64) void k_search(AlignParams P) {
+    extern __shared__ u64 smem[];
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    u64* lds = smem + (threadIdx.x / G) * kSearchGroupWords;
+    uint32_t* len_in = P.counters + kCounterListBase + 2 * P.list_slot;
+    uint32_t* head = len_in + 1;
+    uint32_t* len_out = len_in + 2;
+    const uint32_t n_items = P.list_in ? __hip_atomic_load(len_in, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                                       : (uint32_t)P.n_pairs;
+    // A group takes at most n_items items, which bounds the loop.
+    for (uint32_t iter = 0; iter <= n_items; ++iter) {
+        const uint32_t item = group_pop(head, lds, gl);
+        if (item >= n_items) break;
+        const uint64_t pair = P.list_in ? P.list_in[item] : item;
+        const PairCursor pc = pair_cursor(P, pair);
+        if (pc.m == 0) {
+            if (gl == 0) {
+                write_simple_result(P.out + pair, 0, pair_run_base(P, pair));
+                P.search[pair] = SearchOut{kSearchDone, 0};
+            }
+            continue;
+        }
+        const int m1 = min(P.W, pc.m);
+        const int Kr = min(P.K, m1 - 1);
+        build_pm<G>(lds, gl, P.reads, pc.rb, m1, false);
+        int row, col;
+        search_rows<G, RS>(lds, gl, lane, P.refs, pc.fb, pc.n, m1, Kr, &row, &col);
+        if (gl == 0) {
+            const bool final = row >= 0 || Kr < RS * G;
+            const int srow = row >= 0 ? row : (m1 <= P.K ? m1 : Kr);
+            search_stats(P, pair, pc.n, m1, final ? srow : 0, (u64)G * RS * (pc.n + RS * G - 1),
+                         P.list_slot == 0);
+            if (row >= 0) {
+                P.search[pair] = SearchOut{row, (uint32_t)col};
+            } else if (Kr < RS * G) {
+                // every needed row was computed without a hit
+                if (m1 <= P.K) P.search[pair] = SearchOut{m1, 0u};
+                else {
+                    write_simple_result(P.out + pair, -1, pair_run_base(P, pair));
+                    P.search[pair] = SearchOut{kSearchFailed, 0};
+                }
+            } else {
+                const uint32_t pos = atomicAdd(len_out, 1u);
+                P.list_out[pos] = (uint32_t)pair;
+                P.search[pair] = SearchOut{kSearchPending, 0};
+            }
+        }
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(64) void k_windows(AlignParams P, int groups_per_block) {
+    extern __shared__ u64 smem[];
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (G - 1);
+    const int grp = threadIdx.x / G;
+    const int words = window_group_words(P.lds_rows, P.stride);
+    u64* lds = smem + grp * words;
+    const uint64_t worker = (uint64_t)blockIdx.x * groups_per_block + grp;
+    const int spill_rows = 64 - P.lds_rows;
+    u64* spill = spill_rows > 0 ? P.spill + worker * (uint64_t)spill_rows * P.stride : nullptr;
+    for (uint64_t iter = 0; iter <= P.n_pairs; ++iter) {
+        const uint32_t item = group_pop(P.counters + kCounterWindowHead, lds, gl);
+        if (item >= P.n_pairs) break;
+        const uint64_t pair = P.order ? P.order[item] : item;
+        const SearchOut so = P.search[pair];
+        if (so.row < 0) continue;  // result already written by the search
+        const PairCursor pc = pair_cursor(P, pair);
+        align_windows<G>(P, lds, spill, gl, lane, pair, pc, (int)so.col, P.out + pair);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Packing, ordering, compaction
+// ---------------------------------------------------------------------------
+
+__global__ void k_pack(const char* ascii, uint64_t n, uint8_t* packed, uint32_t* bad) {
+    const uint64_t byte = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (byte * 4 >= n) return;
+    unsigned v = 0, nbad = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const uint64_t b = byte * 4 + u;
+        if (b < n) {
+            const unsigned ch = (unsigned char)ascii[b] & ~0x20u;  // fold case
+            unsigned code;
+            switch (ch) {
+                case 'A': code = 0; break;
+                case 'C': code = 1; break;
+                case 'G': code = 2; break;
+                case 'T': code = 3; break;
+                default: code = 0; ++nbad;
+            }
+            v |= code << (2 * u);
+        }
+    }
+    packed[byte] = (uint8_t)v;
+    if (nbad) atomicAdd(bad, nbad);
+}
+
+// Resets the queue heads and list lengths; stage 0's list length is set when
+// stage 0 walks an explicit list. A kernel rather than a memset so that the
+// whole pipeline can be captured in a graph.
+__global__ void k_init_counters(uint32_t* counters, uint32_t stage0_len) {
+    const int i = threadIdx.x;
+    if (i < kCounterCount) counters[i] = i == kCounterListBase ? stage0_len : 0u;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Sort keys for longest-read-first scheduling: key = ~read length (ascending
+// radix sort then puts long reads first), value = pair index.
+__global__ void k_lpt_keys(const uint64_t* read_off, uint64_t n_pairs, uint32_t* keys,
+                           uint32_t* vals) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pairs) return;
+    keys[i] = ~(uint32_t)(read_off[i + 1] - read_off[i]);
+    vals[i] = (uint32_t)i;
+}
+
+// Copies each pair's CIGAR elements to dst + dst_off[pair] (one block per pair).
+__global__ void k_compact(const genasm_result* out, const uint64_t* dst_off, uint64_t n_pairs,
+                          const uint32_t* cigar, uint32_t* dst) {
+    const uint64_t pair = blockIdx.x;
+    if (pair >= n_pairs) return;
+    const genasm_result r = out[pair];
+    for (uint32_t e = threadIdx.x; e < r.cigar_len; e += blockDim.x)
+        dst[dst_off[pair] + e] = cigar[r.cigar_off + e];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+int plain_lds_bytes(int stride) { return window_group_words(64, stride) * 8; }
+int window_lds_bytes(int group_lanes, int lds_rows, int stride) {
+    return (64 / group_lanes) * window_group_words(lds_rows, stride) * 8;
+}
+int search_lds_bytes(int group_lanes) { return (64 / group_lanes) * kSearchGroupWords * 8; }
+
+hipError_t launch_plain(const AlignParams& p, hipStream_t s) {
+    if (p.n_pairs == 0) return hipSuccess;
+    const int lds = plain_lds_bytes(p.stride);
+    hipLaunchKernelGGL(k_plain, dim3((unsigned)p.n_pairs), dim3(64), lds, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_search(const AlignParams& p, int group_lanes, int rows_per_lane, int blocks,
+                         hipStream_t s) {
+    const int lds = search_lds_bytes(group_lanes);
+    if (group_lanes == 64) {
+        hipLaunchKernelGGL((k_search<64, 1>), dim3(blocks), dim3(64), lds, s, p);
+    } else if (group_lanes == 16) {
+        if (rows_per_lane == 1) hipLaunchKernelGGL((k_search<16, 1>), dim3(blocks), dim3(64), lds, s, p);
+        else if (rows_per_lane == 2) hipLaunchKernelGGL((k_search<16, 2>), dim3(blocks), dim3(64), lds, s, p);
+        else if (rows_per_lane == 4) hipLaunchKernelGGL((k_search<16, 4>), dim3(blocks), dim3(64), lds, s, p);
+        else return hipErrorInvalidValue;
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_windows(const AlignParams& p, int group_lanes, int blocks, hipStream_t s) {
+    const int lds = window_lds_bytes(group_lanes, p.lds_rows, p.stride);
+    if (group_lanes == 64) hipLaunchKernelGGL(k_windows<64>, dim3(blocks), dim3(64), lds, s, p, 1);
+    else if (group_lanes == 16) hipLaunchKernelGGL(k_windows<16>, dim3(blocks), dim3(64), lds, s, p, 4);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const char* ascii, uint64_t n, uint8_t* packed, uint32_t* bad,
+                       hipStream_t s) {
+    const uint64_t bytes = (n + 3) / 4;
+    if (bytes == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((bytes + 255) / 256);
+    hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(256), 0, s, ascii, n, packed, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_counters(uint32_t* counters, uint32_t stage0_len, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, s, counters, stage0_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_lpt_keys(const uint64_t* read_off, uint64_t n_pairs, uint32_t* keys,
+                           uint32_t* vals, hipStream_t s) {
+    if (n_pairs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lpt_keys, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s,
+                       read_off, n_pairs, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_cigar(const genasm_result* d_out, const uint64_t* dst_off,
+                                uint64_t n_pairs, const uint32_t* cigar, uint32_t* dst,
+                                hipStream_t s) {
+    if (n_pairs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)n_pairs), dim3(64), 0, s, d_out, dst_off, n_pairs,
+                       cigar, dst);
+    return hipGetLastError();
+}
+
+}  // namespace genasm

@@ -1,0 +1,560 @@
+// Host runtime of the GenASM library: context, argument checks, device
+// scratch, launch orchestration for the plain and batched forms, and the
+// host-memory convenience call.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace genasm;
+
+struct genasm_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    int num_cus = 0;
+    std::string err;
+    // device scratch arena
+    char* scratch = nullptr;
+    size_t scratch_cap = 0;
+    // host-form staging (device)
+    char* stage = nullptr;
+    size_t stage_cap = 0;
+    // profiling
+    bool profiling = false;
+    bool have_profile = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    char* stats = nullptr;
+    size_t stats_cap = 0;
+    uint64_t prof_pairs = 0;
+    int prof_form = 0;
+};
+
+namespace {
+
+#define CHECK_HIP(ctx, expr)                                                              \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) return set_err(ctx, GENASM_E_DEVICE, #expr, e_);            \
+    } while (0)
+
+int set_err(genasm_ctx* ctx, int code, const char* what, hipError_t e = hipSuccess) {
+    if (ctx) {
+        ctx->err = what ? what : "";
+        if (e != hipSuccess) {
+            ctx->err += ": ";
+            ctx->err += hipGetErrorString(e);
+        }
+    }
+    return code;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Grows a device buffer to at least `need` bytes (contents are not kept).
+int ensure(genasm_ctx* ctx, char** buf, size_t* cap, size_t need) {
+    if (need <= *cap) return GENASM_OK;
+    if (*buf) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return set_err(ctx, GENASM_E_DEVICE, "hipStreamSynchronize", e);
+        (void)hipFree(*buf);
+        *buf = nullptr;
+        *cap = 0;
+    }
+    size_t want = align_up(std::max(need, (size_t)1 << 20), (size_t)1 << 20);
+    hipError_t e = hipMalloc((void**)buf, want);
+    if (e != hipSuccess) {
+        *buf = nullptr;
+        (void)hipGetLastError();
+        return set_err(ctx, GENASM_E_NOMEM, "hipMalloc scratch", e);
+    }
+    *cap = want;
+    return GENASM_OK;
+}
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count) {
+        off = align_up(off, 256);
+        T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+bool valid_wko(int32_t k, int32_t W, int32_t O) {
+    return W >= 2 && W <= 64 && O >= 0 && O < W && k >= 0;
+}
+
+int resolve_launch(const genasm_launch* in, genasm_launch* out) {
+    genasm_default_launch(in ? in->form : GENASM_FORM_BATCHED, out);
+    if (!in) return GENASM_OK;
+    if (in->form != GENASM_FORM_PLAIN && in->form != GENASM_FORM_BATCHED) return GENASM_E_INVAL;
+    if (in->group_lanes) out->group_lanes = in->group_lanes;
+    if (in->search_lanes) out->search_lanes = in->search_lanes;
+    if (in->lds_rows) out->lds_rows = in->lds_rows;
+    if (in->workers_per_cu) out->workers_per_cu = in->workers_per_cu;
+    if (in->lpt_order >= 0) out->lpt_order = in->lpt_order;
+    if (out->group_lanes != 16 && out->group_lanes != 64) return GENASM_E_INVAL;
+    if (out->search_lanes != 16 && out->search_lanes != 64) return GENASM_E_INVAL;
+    if (out->lds_rows < out->group_lanes || out->lds_rows > 64 || out->lds_rows % out->group_lanes)
+        return GENASM_E_INVAL;
+    if (out->workers_per_cu < 1 || out->workers_per_cu > 32) return GENASM_E_INVAL;
+    return GENASM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* genasm_version(void) { return "genasm-gfx950 0.1"; }
+
+const char* genasm_strerror(int code) {
+    switch (code) {
+        case GENASM_OK: return "ok";
+        case GENASM_E_INVAL: return "invalid argument";
+        case GENASM_E_ALPHABET: return "sequence byte outside ACGTacgt";
+        case GENASM_E_NOMEM: return "out of memory";
+        case GENASM_E_DEVICE: return "HIP device error";
+        case GENASM_E_NOSPACE: return "output buffer too small";
+        case GENASM_E_BUSY: return "request refused: admission budget exhausted";
+        case GENASM_E_TOOLONG: return "sequence longer than 2^31-1 bases";
+        default: return "unknown error";
+    }
+}
+
+int genasm_default_launch(int32_t form, genasm_launch* out) {
+    if (!out) return GENASM_E_INVAL;
+    std::memset(out, 0, sizeof(*out));
+    out->form = form;
+    out->group_lanes = 16;
+    out->search_lanes = 16;
+    out->lds_rows = 16;
+    out->workers_per_cu = 5;
+    out->lpt_order = 1;
+    return GENASM_OK;
+}
+
+// Reason of the last genasm_create failure on this thread.
+static thread_local std::string g_create_err;
+
+static int create_fail(int code, const char* what, hipError_t e) {
+    g_create_err = what;
+    if (e != hipSuccess) {
+        g_create_err += ": ";
+        g_create_err += hipGetErrorString(e);
+    }
+    (void)hipGetLastError();
+    return code;
+}
+
+int genasm_create(genasm_ctx** out, int hip_device) {
+    if (!out) return GENASM_E_INVAL;
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return create_fail(GENASM_E_DEVICE, "hipGetDeviceCount", e);
+    if (hip_device < 0 || hip_device >= count)
+        return create_fail(GENASM_E_DEVICE, "no such HIP device", hipSuccess);
+    int major = 0, minor = 0, cus = 0;
+    if ((e = hipDeviceGetAttribute(&major, hipDeviceAttributeComputeCapabilityMajor, hip_device)) ||
+        (e = hipDeviceGetAttribute(&minor, hipDeviceAttributeComputeCapabilityMinor, hip_device)) ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device)))
+        return create_fail(GENASM_E_DEVICE, "hipDeviceGetAttribute", e);
+    if (major != 9 || minor != 5)  // the code objects are built for gfx950 only
+        return create_fail(GENASM_E_DEVICE, "device is not gfx950", hipSuccess);
+    genasm_ctx* ctx = new (std::nothrow) genasm_ctx();
+    if (!ctx) return GENASM_E_NOMEM;
+    ctx->device = hip_device;
+    ctx->num_cus = cus;
+    if ((e = hipSetDevice(hip_device)) != hipSuccess) {
+        delete ctx;
+        return create_fail(GENASM_E_DEVICE, "hipSetDevice", e);
+    }
+    if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) {
+        delete ctx;
+        return create_fail(GENASM_E_DEVICE, "hipStreamCreateWithFlags", e);
+    }
+    *out = ctx;
+    return GENASM_OK;
+}
+
+void genasm_destroy(genasm_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->stage) (void)hipFree(ctx->stage);
+    if (ctx->stats) (void)hipFree(ctx->stats);
+    for (hipEvent_t e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char* genasm_last_error(const genasm_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+int genasm_pack(const char* ascii, uint64_t n, uint8_t* packed, uint64_t* bad_index) {
+    if ((!ascii || !packed) && n) return GENASM_E_INVAL;
+    for (uint64_t byte = 0; byte * 4 < n; ++byte) {
+        unsigned v = 0;
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t b = byte * 4 + u;
+            if (b >= n) break;
+            unsigned code;
+            switch (ascii[b]) {
+                case 'A': case 'a': code = 0; break;
+                case 'C': case 'c': code = 1; break;
+                case 'G': case 'g': code = 2; break;
+                case 'T': case 't': code = 3; break;
+                default:
+                    if (bad_index) *bad_index = b;
+                    return GENASM_E_ALPHABET;
+            }
+            v |= code << (2 * u);
+        }
+        packed[byte] = (uint8_t)v;
+    }
+    return GENASM_OK;
+}
+
+static int check_offsets(const uint64_t* off, uint64_t n_pairs, uint64_t stream_len) {
+    for (uint64_t i = 0; i < n_pairs; ++i) {
+        if (off[i + 1] < off[i]) return GENASM_E_INVAL;
+        if (off[i + 1] - off[i] > 0x7fffffffull) return GENASM_E_TOOLONG;
+    }
+    if (stream_len != UINT64_MAX && off[n_pairs] > stream_len) return GENASM_E_INVAL;
+    return GENASM_OK;
+}
+
+static bool ascii_ok(unsigned char c) {
+    switch (c) {
+        case 'A': case 'C': case 'G': case 'T': case 'a': case 'c': case 'g': case 't': return true;
+        default: return false;
+    }
+}
+
+int genasm_validate(const char* reads, uint64_t reads_len, const uint64_t* read_off,
+                    const char* refs, uint64_t refs_len, const uint64_t* ref_off,
+                    uint64_t n_pairs, int32_t k, int32_t W, int32_t O) {
+    if (!valid_wko(k, W, O)) return GENASM_E_INVAL;
+    if (!read_off || !ref_off) return GENASM_E_INVAL;
+    int rc = check_offsets(read_off, n_pairs, reads_len);
+    if (rc) return rc;
+    rc = check_offsets(ref_off, n_pairs, refs_len);
+    if (rc) return rc;
+    if ((!reads && read_off[n_pairs] > read_off[0]) || (!refs && ref_off[n_pairs] > ref_off[0]))
+        return GENASM_E_INVAL;
+    for (uint64_t b = read_off[0]; b < read_off[n_pairs]; ++b)
+        if (!ascii_ok((unsigned char)reads[b])) return GENASM_E_ALPHABET;
+    for (uint64_t b = ref_off[0]; b < ref_off[n_pairs]; ++b)
+        if (!ascii_ok((unsigned char)refs[b])) return GENASM_E_ALPHABET;
+    return GENASM_OK;
+}
+
+int genasm_pack_dev(genasm_ctx* ctx, const char* d_ascii, uint64_t n, uint8_t* d_packed,
+                    uint32_t* d_bad_count, void* stream) {
+    if (!ctx) return GENASM_E_INVAL;
+    if (n && (!d_ascii || !d_packed || !d_bad_count)) return set_err(ctx, GENASM_E_INVAL, "null pointer");
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    CHECK_HIP(ctx, launch_pack(d_ascii, n, d_packed, d_bad_count, s));
+    return GENASM_OK;
+}
+
+int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
+                           const uint8_t* d_refs2b, const uint64_t* d_ref_off, uint64_t n_pairs,
+                           uint64_t total_read_bases, uint64_t total_ref_bases,
+                           uint32_t max_ref_len, int32_t k, int32_t W, int32_t O,
+                           genasm_result* d_out, uint32_t* d_cigar, uint64_t cigar_cap,
+                           const genasm_launch* launch, void* stream) {
+    (void)max_ref_len;
+    if (!ctx) return GENASM_E_INVAL;
+    if (!valid_wko(k, W, O)) return set_err(ctx, GENASM_E_INVAL, "W must be in [2,64], O in [0,W-1], k >= 0");
+    if (n_pairs == 0) return GENASM_OK;
+    if (n_pairs > 0xffffffffull) return set_err(ctx, GENASM_E_INVAL, "too many pairs");
+    if (!d_read_off || !d_ref_off || !d_out || (!d_reads2b && total_read_bases) ||
+        (!d_refs2b && total_ref_bases) || (!d_cigar && cigar_cap))
+        return set_err(ctx, GENASM_E_INVAL, "null pointer");
+    if (cigar_cap < total_read_bases + total_ref_bases)
+        return set_err(ctx, GENASM_E_NOSPACE, "cigar_cap below total read + reference bases");
+    genasm_launch L;
+    int rc = resolve_launch(launch, &L);
+    if (rc) return set_err(ctx, rc, "bad launch parameters");
+    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device));
+
+    AlignParams p{};
+    p.reads = d_reads2b;
+    p.read_off = d_read_off;
+    p.refs = d_refs2b;
+    p.ref_off = d_ref_off;
+    p.n_pairs = n_pairs;
+    p.K = std::min(k, W);
+    p.W = W;
+    p.L = W - O;
+    p.stride = p.L + 3;
+    p.out = d_out;
+    p.cigar = d_cigar;
+    p.cigar_cap = cigar_cap;
+
+    if (ctx->profiling) {
+        const size_t words = (size_t)n_pairs * kStatCount;
+        rc = ensure(ctx, &ctx->stats, &ctx->stats_cap, words * 8);
+        if (rc) return rc;
+        p.stats = reinterpret_cast<unsigned long long*>(ctx->stats);
+        CHECK_HIP(ctx, launch_fill_u64(p.stats, words, 0ull, s));
+        ctx->prof_pairs = n_pairs;
+        ctx->prof_form = L.form;
+        ctx->have_profile = true;
+    }
+    auto mark = [&](int i) -> hipError_t {
+        return ctx->profiling ? hipEventRecord(ctx->ev[i], s) : hipSuccess;
+    };
+    if (L.form == GENASM_FORM_PLAIN) {
+        p.lds_rows = 64;
+        CHECK_HIP(ctx, mark(0));
+        CHECK_HIP(ctx, mark(1));
+        CHECK_HIP(ctx, mark(2));
+        CHECK_HIP(ctx, launch_plain(p, s));
+        CHECK_HIP(ctx, mark(3));
+        return GENASM_OK;
+    }
+
+    // Batched: scratch layout.
+    const int G = L.group_lanes;
+    const int groups_per_block = 64 / G;
+    const int win_blocks = ctx->num_cus * L.workers_per_cu;
+    const int search_blocks = ctx->num_cus * 8;
+    const uint64_t workers = (uint64_t)win_blocks * groups_per_block;
+    const int spill_rows = 64 - L.lds_rows;
+    size_t sort_tmp = 0;
+    if (L.lpt_order) {
+        hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           (uint32_t*)nullptr, (uint32_t*)nullptr, (int)n_pairs, 0, 32, s);
+    }
+    auto carve = [&](Carver& c) {
+        p.search = c.take<SearchOut>(n_pairs);
+        p.counters = c.take<uint32_t>(kCounterCount);
+        uint32_t* lists = c.take<uint32_t>(2 * n_pairs);
+        p.spill = spill_rows > 0 ? c.take<unsigned long long>(workers * spill_rows * p.stride) : nullptr;
+        uint32_t* keys = c.take<uint32_t>(n_pairs);
+        uint32_t* vals = c.take<uint32_t>(n_pairs);
+        uint32_t* keys2 = c.take<uint32_t>(n_pairs);
+        uint32_t* order = c.take<uint32_t>(n_pairs);
+        void* tmp = c.take<char>(sort_tmp);
+        return std::make_tuple(lists, keys, vals, keys2, order, tmp);
+    };
+    Carver dry{nullptr};
+    carve(dry);
+    rc = ensure(ctx, &ctx->scratch, &ctx->scratch_cap, dry.off + 256);
+    if (rc) return rc;
+    Carver real{ctx->scratch};
+    auto [lists, keys, vals, keys2, order, tmp] = carve(real);
+
+    CHECK_HIP(ctx, mark(0));
+    if (L.lpt_order) {
+        CHECK_HIP(ctx, launch_lpt_keys(d_read_off, n_pairs, keys, vals, s));
+        size_t t = sort_tmp;
+        CHECK_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(tmp, t, keys, keys2, vals, order,
+                                                          (int)n_pairs, 0, 32, s));
+        p.order = order;
+    }
+    // Start search: stage 0 over all pairs (longest first when ordered), then
+    // stages 1-2 retry the pairs that need more rows.
+    CHECK_HIP(ctx, mark(1));
+    const int SG = L.search_lanes;
+    p.list_in = p.order;
+    CHECK_HIP(ctx, launch_init_counters(p.counters, (uint32_t)n_pairs, s));
+    p.list_slot = 0;
+    p.list_out = lists;
+    if (SG == 64) {
+        CHECK_HIP(ctx, launch_search(p, 64, 1, search_blocks, s));
+    } else {
+        CHECK_HIP(ctx, launch_search(p, 16, 1, search_blocks, s));
+        p.list_in = lists;
+        p.list_out = lists + n_pairs;
+        p.list_slot = 1;
+        CHECK_HIP(ctx, launch_search(p, 16, 2, search_blocks, s));
+        p.list_in = lists + n_pairs;
+        p.list_out = lists;  // never written: 4 rows per lane cover all 64 rows
+        p.list_slot = 2;
+        CHECK_HIP(ctx, launch_search(p, 16, 4, search_blocks, s));
+    }
+    // Windows: persistent workers pull pairs (longest first) from the queue.
+    CHECK_HIP(ctx, mark(2));
+    p.list_in = nullptr;
+    p.list_out = nullptr;
+    p.lds_rows = L.lds_rows;
+    CHECK_HIP(ctx, launch_windows(p, G, win_blocks, s));
+    CHECK_HIP(ctx, mark(3));
+    return GENASM_OK;
+}
+
+int genasm_profile_enable(genasm_ctx* ctx, int on) {
+    if (!ctx) return GENASM_E_INVAL;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    if (on) {
+        for (hipEvent_t& e : ctx->ev)
+            if (!e) CHECK_HIP(ctx, hipEventCreate(&e));
+    }
+    ctx->profiling = on != 0;
+    return GENASM_OK;
+}
+
+int genasm_profile_read(genasm_ctx* ctx, genasm_profile* out) {
+    if (!ctx || !out) return GENASM_E_INVAL;
+    if (!ctx->have_profile) return set_err(ctx, GENASM_E_INVAL, "no profiled call yet");
+    CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    CHECK_HIP(ctx, hipEventSynchronize(ctx->ev[3]));
+    std::memset(out, 0, sizeof(*out));
+    CHECK_HIP(ctx, hipEventElapsedTime(&out->total_ms, ctx->ev[0], ctx->ev[3]));
+    CHECK_HIP(ctx, hipEventElapsedTime(&out->order_ms, ctx->ev[0], ctx->ev[1]));
+    CHECK_HIP(ctx, hipEventElapsedTime(&out->search_ms, ctx->ev[1], ctx->ev[2]));
+    CHECK_HIP(ctx, hipEventElapsedTime(&out->windows_ms, ctx->ev[2], ctx->ev[3]));
+    const size_t words = (size_t)ctx->prof_pairs * kStatCount;
+    std::vector<unsigned long long> st(words);
+    if (words)
+        CHECK_HIP(ctx, hipMemcpy(st.data(), ctx->stats, words * 8, hipMemcpyDeviceToHost));
+    uint64_t sum[kStatCount] = {0};
+    for (size_t i = 0; i < words; ++i) sum[i % kStatCount] += st[i];
+    out->n_pairs = ctx->prof_pairs;
+    out->window_word_ops = sum[kStatWindowWordOps];
+    out->search_word_ops = sum[kStatSearchWordOps];
+    out->window_cells = sum[kStatWindowCells];
+    out->search_cells = sum[kStatSearchCells];
+    out->table_words = sum[kStatTableWords];
+    out->tb_reads = sum[kStatTbReads];
+    out->window_lane_steps = sum[kStatWindowLaneSteps];
+    out->search_lane_steps = sum[kStatSearchLaneSteps];
+    return GENASM_OK;
+}
+
+int genasm_batch_align(genasm_ctx* ctx, const char* reads, const uint64_t* read_off,
+                       const char* refs, const uint64_t* ref_off, uint64_t n_pairs,
+                       int32_t k, int32_t W, int32_t O, genasm_result* out, char* cigar_buf,
+                       uint64_t cigar_cap, uint64_t* cigar_needed, const genasm_launch* launch) {
+    if (!ctx) return GENASM_E_INVAL;
+    if (!valid_wko(k, W, O)) return set_err(ctx, GENASM_E_INVAL, "W must be in [2,64], O in [0,W-1], k >= 0");
+    if (!read_off || !ref_off || (!out && n_pairs) || !cigar_needed || (!cigar_buf && cigar_cap))
+        return set_err(ctx, GENASM_E_INVAL, "null pointer");
+    int rc = check_offsets(read_off, n_pairs, UINT64_MAX);
+    if (!rc) rc = check_offsets(ref_off, n_pairs, UINT64_MAX);
+    if (rc) return set_err(ctx, rc, "bad offsets");
+    *cigar_needed = 0;
+    if (n_pairs == 0) return GENASM_OK;
+    if ((!reads && read_off[n_pairs] > read_off[0]) || (!refs && ref_off[n_pairs] > ref_off[0]))
+        return set_err(ctx, GENASM_E_INVAL, "null sequence pointer");
+    genasm_launch L;
+    rc = resolve_launch(launch, &L);
+    if (rc) return set_err(ctx, rc, "bad launch parameters");
+    CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+
+    const uint64_t nr = read_off[n_pairs] - read_off[0];
+    const uint64_t nf = ref_off[n_pairs] - ref_off[0];
+    std::vector<uint64_t> roff(n_pairs + 1), foff(n_pairs + 1);
+    uint32_t max_ref = 0;
+    for (uint64_t i = 0; i <= n_pairs; ++i) {
+        roff[i] = read_off[i] - read_off[0];
+        foff[i] = ref_off[i] - ref_off[0];
+        if (i) max_ref = std::max<uint32_t>(max_ref, (uint32_t)(foff[i] - foff[i - 1]));
+    }
+    Carver dry{nullptr};
+    auto carve = [&](Carver& c) {
+        struct B {
+            char *ar, *af;
+            uint8_t *pr, *pf;
+            uint64_t *or_, *of, *dst_off;
+            genasm_result* res;
+            uint32_t *cig, *cig2, *bad;
+        } b;
+        b.ar = c.take<char>(nr + 1);
+        b.af = c.take<char>(nf + 1);
+        b.pr = c.take<uint8_t>(nr / 4 + 2);
+        b.pf = c.take<uint8_t>(nf / 4 + 2);
+        b.or_ = c.take<uint64_t>(n_pairs + 1);
+        b.of = c.take<uint64_t>(n_pairs + 1);
+        b.dst_off = c.take<uint64_t>(n_pairs + 1);
+        b.res = c.take<genasm_result>(n_pairs);
+        b.cig = c.take<uint32_t>(nr + nf + 1);
+        b.cig2 = c.take<uint32_t>(nr + nf + 1);
+        b.bad = c.take<uint32_t>(2);
+        return b;
+    };
+    carve(dry);
+    rc = ensure(ctx, &ctx->stage, &ctx->stage_cap, dry.off + 256);
+    if (rc) return rc;
+    Carver real{ctx->stage};
+    auto b = carve(real);
+
+    CHECK_HIP(ctx, hipMemsetAsync(b.bad, 0, 2 * sizeof(uint32_t), s));
+    if (nr) CHECK_HIP(ctx, hipMemcpyAsync(b.ar, reads + read_off[0], nr, hipMemcpyHostToDevice, s));
+    if (nf) CHECK_HIP(ctx, hipMemcpyAsync(b.af, refs + ref_off[0], nf, hipMemcpyHostToDevice, s));
+    CHECK_HIP(ctx, hipMemcpyAsync(b.or_, roff.data(), (n_pairs + 1) * 8, hipMemcpyHostToDevice, s));
+    CHECK_HIP(ctx, hipMemcpyAsync(b.of, foff.data(), (n_pairs + 1) * 8, hipMemcpyHostToDevice, s));
+    CHECK_HIP(ctx, launch_pack(b.ar, nr, b.pr, b.bad, s));
+    CHECK_HIP(ctx, launch_pack(b.af, nf, b.pf, b.bad, s));
+    uint32_t bad = 0;
+    CHECK_HIP(ctx, hipMemcpyAsync(&bad, b.bad, sizeof(bad), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(ctx, hipStreamSynchronize(s));
+    if (bad) return set_err(ctx, GENASM_E_ALPHABET, "sequence byte outside ACGTacgt");
+
+    rc = genasm_batch_align_dev(ctx, b.pr, b.or_, b.pf, b.of, n_pairs, nr, nf, max_ref, k, W, O,
+                                b.res, b.cig, nr + nf + 1, &L, s);
+    if (rc) return rc;
+    CHECK_HIP(ctx, hipMemcpyAsync(out, b.res, n_pairs * sizeof(genasm_result),
+                                  hipMemcpyDeviceToHost, s));
+    CHECK_HIP(ctx, hipStreamSynchronize(s));
+    // Gather the CIGAR elements of all pairs into one dense buffer.
+    std::vector<uint64_t> dst(n_pairs + 1, 0);
+    for (uint64_t i = 0; i < n_pairs; ++i) dst[i + 1] = dst[i] + out[i].cigar_len;
+    const uint64_t n_elems = dst[n_pairs];
+    std::vector<uint32_t> elems(n_elems);
+    if (n_elems) {
+        CHECK_HIP(ctx, hipMemcpyAsync(b.dst_off, dst.data(), (n_pairs + 1) * 8,
+                                      hipMemcpyHostToDevice, s));
+        CHECK_HIP(ctx, launch_compact_cigar(b.res, b.dst_off, n_pairs, b.cig, b.cig2, s));
+        CHECK_HIP(ctx, hipMemcpyAsync(elems.data(), b.cig2, n_elems * 4, hipMemcpyDeviceToHost, s));
+        CHECK_HIP(ctx, hipStreamSynchronize(s));
+    }
+    // Format the text CIGARs.
+    static const char kOp[4] = {'=', 'X', 'I', 'D'};
+    uint64_t need = 0;
+    for (uint64_t e = 0; e < n_elems; ++e) {
+        uint32_t len = GENASM_CIGAR_LEN(elems[e]);
+        int digits = 1;
+        while (len >= 10) { len /= 10; ++digits; }
+        need += digits + 1;
+    }
+    *cigar_needed = need;
+    const bool fits = need <= cigar_cap;
+    uint64_t pos = 0;
+    for (uint64_t i = 0; i < n_pairs; ++i) {
+        const uint64_t start = pos;
+        for (uint64_t e = dst[i]; e < dst[i + 1]; ++e) {
+            char tmp[16];
+            int len = std::snprintf(tmp, sizeof tmp, "%u%c", GENASM_CIGAR_LEN(elems[e]),
+                                    kOp[GENASM_CIGAR_OP(elems[e])]);
+            if (fits) std::memcpy(cigar_buf + pos, tmp, len);
+            pos += len;
+        }
+        out[i].cigar_off = start;
+        out[i].cigar_len = (uint32_t)(pos - start);
+    }
+    if (!fits) return set_err(ctx, GENASM_E_NOSPACE, "cigar_cap below the CIGAR text size");
+    return GENASM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Host-side debugging driver: runs the unmodified GenASM kernels through the
+// CPU emulation in tests/emu/hip/hip_runtime.h (plain or batched pipeline).
+//
+//   emu_driver IN OUT
+// IN : int64 form, group_lanes, search_lanes, lds_rows, k, W, O, n_pairs,
+//      read_bytes, ref_bytes; then the packed read bytes, the packed reference
+//      bytes, read_off[n+1], ref_off[n+1] (uint64).
+// OUT: n genasm_result records, then (read bases + ref bases) CIGAR elements.
+#include "../../paper_2203_15561_amd/csrc/kernels.hip"
+
+#include <algorithm>
+#include <cstdio>
+#include <numeric>
+#include <vector>
+
+namespace genasm { unsigned long long smem[kEmuLdsWords]; }
+
+using namespace genasm;
+
+static bool read_all(FILE* f, void* p, size_t n) { return n == 0 || fread(p, 1, n, f) == n; }
+
+int main(int argc, char** argv) {
+    if (argc != 3) { fprintf(stderr, "usage: emu_driver IN OUT\n"); return 2; }
+    FILE* f = fopen(argv[1], "rb");
+    if (!f) { perror("open IN"); return 2; }
+    int64_t h[10];
+    if (!read_all(f, h, sizeof h)) return 2;
+    const int form = (int)h[0], G = (int)h[1], SG = (int)h[2], lds_rows = (int)h[3];
+    const int k = (int)h[4], W = (int)h[5], O = (int)h[6];
+    const uint64_t n = (uint64_t)h[7], nrb = (uint64_t)h[8], nfb = (uint64_t)h[9];
+    std::vector<uint8_t> reads(nrb + 8), refs(nfb + 8);
+    std::vector<uint64_t> roff(n + 1), foff(n + 1);
+    if (!read_all(f, reads.data(), nrb) || !read_all(f, refs.data(), nfb) ||
+        !read_all(f, roff.data(), 8 * (n + 1)) || !read_all(f, foff.data(), 8 * (n + 1))) {
+        fprintf(stderr, "short input\n");
+        return 2;
+    }
+    fclose(f);
+    reads.resize(nrb);  // exact sizes so that ASan sees reads past the end
+    refs.resize(nfb);
+    const uint64_t cap = (roff[n] - roff[0]) + (foff[n] - foff[0]);
+    std::vector<genasm_result> out(n);
+    std::vector<uint32_t> cigar(std::max<uint64_t>(cap, 1), 0xFFFFFFFFu);
+
+    AlignParams p{};
+    p.reads = reads.data();
+    p.read_off = roff.data();
+    p.refs = refs.data();
+    p.ref_off = foff.data();
+    p.n_pairs = n;
+    p.K = std::min(k, W);
+    p.W = W;
+    p.L = W - O;
+    p.stride = p.L + 3;
+    p.out = out.data();
+    p.cigar = cigar.data();
+    p.cigar_cap = cap;
+    if (form == GENASM_FORM_PLAIN) {
+        emu::group_lanes = 64;
+        p.lds_rows = 64;
+        launch_plain(p, nullptr);
+    } else {
+        const int blocks = 2;
+        const uint64_t workers = (uint64_t)blocks * (64 / G);
+        const int spill_rows = 64 - lds_rows;
+        std::vector<SearchOut> search(n, SearchOut{kSearchPending, 0});
+        std::vector<uint32_t> counters(kCounterCount, 0), lists(2 * n + 1), order(n);
+        std::vector<unsigned long long> spill(std::max<uint64_t>(workers * spill_rows * p.stride, 1));
+        std::iota(order.begin(), order.end(), 0u);
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+            return roff[a + 1] - roff[a] > roff[b + 1] - roff[b];
+        });
+        p.search = search.data();
+        p.counters = counters.data();
+        p.spill = spill_rows > 0 ? spill.data() : nullptr;
+        p.order = order.data();
+        launch_init_counters(p.counters, (uint32_t)n, nullptr);
+        p.list_in = p.order;
+        p.list_out = lists.data();
+        p.list_slot = 0;
+        emu::group_lanes = SG;
+        if (SG == 64) {
+            launch_search(p, 64, 1, blocks, nullptr);
+        } else {
+            launch_search(p, 16, 1, blocks, nullptr);
+            p.list_in = lists.data();
+            p.list_out = lists.data() + n;
+            p.list_slot = 1;
+            launch_search(p, 16, 2, blocks, nullptr);
+            p.list_in = lists.data() + n;
+            p.list_out = lists.data();
+            p.list_slot = 2;
+            launch_search(p, 16, 4, blocks, nullptr);
+        }
+        for (uint64_t i = 0; i < n; ++i) {
+            if (search[i].row == kSearchPending) {
+                fprintf(stderr, "pair %llu left pending by the search\n", (unsigned long long)i);
+                return 3;
+            }
+        }
+        p.list_in = nullptr;
+        p.list_out = nullptr;
+        p.lds_rows = lds_rows;
+        emu::group_lanes = G;
+        launch_windows(p, G, blocks, nullptr);
+    }
+    FILE* g = fopen(argv[2], "wb");
+    if (!g) { perror("open OUT"); return 2; }
+    fwrite(out.data(), sizeof(genasm_result), n, g);
+    fwrite(cigar.data(), 4, cigar.size(), g);
+    fclose(g);
+    return 0;
+}

@@ -1,0 +1,54 @@
+"""Runs the GenASM kernels on the CPU through the HIP emulation (host-side
+debugging of kernel logic; no GPU involved)."""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+RESULT_DTYPE = np.dtype([("edit_distance", "<i4"), ("ref_begin", "<u4"), ("ref_end", "<u4"),
+                         ("n_windows", "<u4"), ("cigar_off", "<u8"), ("cigar_len", "<u4"),
+                         ("flags", "<u4")])
+
+
+def build(out_path: str, sanitize: bool = True) -> str:
+    cmd = ["g++", "-std=c++20", "-O1", "-g", "-fno-omit-frame-pointer", "-I", HERE,
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2203_15561_amd", "csrc"),
+           "-x", "c++", os.path.join(HERE, "emu_driver.cpp"), "-o", out_path, "-lpthread"]
+    if sanitize:
+        cmd[1:1] = ["-fsanitize=address,undefined"]
+    subprocess.check_call(cmd)
+    return out_path
+
+
+def pack2b(codes: np.ndarray) -> np.ndarray:
+    codes = np.asarray(codes, dtype=np.uint8)
+    n = len(codes)
+    pad = np.zeros((n + 3) // 4 * 4, dtype=np.uint8)
+    pad[:n] = codes
+    q = pad.reshape(-1, 4).astype(np.uint8)
+    return (q[:, 0] | (q[:, 1] << 2) | (q[:, 2] << 4) | (q[:, 3] << 6)).astype(np.uint8)
+
+
+def run(driver: str, ps, form: int, group_lanes=16, search_lanes=16, lds_rows=16, timeout=600):
+    """Returns (results, list of (op char, length) runs per pair)."""
+    reads2b, refs2b = pack2b(ps.reads), pack2b(ps.refs)
+    hdr = np.array([form, group_lanes, search_lanes, lds_rows, ps.k, ps.W, ps.O, ps.n_pairs,
+                    len(reads2b), len(refs2b)], dtype=np.int64)
+    with tempfile.TemporaryDirectory() as tmp:
+        fin, fout = os.path.join(tmp, "in.bin"), os.path.join(tmp, "out.bin")
+        with open(fin, "wb") as f:
+            for a in (hdr, reads2b, refs2b, ps.read_off.astype(np.uint64), ps.ref_off.astype(np.uint64)):
+                f.write(np.ascontiguousarray(a).tobytes())
+        subprocess.run([driver, fin, fout], check=True, timeout=timeout)
+        raw = open(fout, "rb").read()
+    n = ps.n_pairs
+    res = np.frombuffer(raw[: 32 * n], dtype=RESULT_DTYPE)
+    cig = np.frombuffer(raw[32 * n:], dtype=np.uint32)
+    out = []
+    for r in res:
+        e = cig[int(r["cigar_off"]):int(r["cigar_off"]) + int(r["cigar_len"])]
+        out.append("".join(f"{int(x) >> 2}{'=XID'[int(x) & 3]}" for x in e))
+    return res, out

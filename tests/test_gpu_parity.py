@@ -1,0 +1,185 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, pair by
+pair, on score, reference span, window count and CIGAR. The bar is bit-exact
+(integer work)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2203_15561_amd as ga
+from tests._helpers import load_hand_examples, rle, codes_to_str
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    c = ga.Context(0)
+    yield c
+    c.close()
+
+
+def expected(ps, k=None, W=None, O=None):
+    res, ops, _, _ = oracle.batch(ps, k=k, W=W, O=O)
+    assert (res["status"] == 0).all()
+    out = []
+    for i in range(ps.n_pairs):
+        sc = int(res["score"][i])
+        cig = rle(oracle.pair_ops(ps, res, ops, i)) if sc >= 0 else ""
+        out.append((sc, int(res["ref_begin"][i]) if sc >= 0 else 0,
+                    int(res["ref_end"][i]) if sc >= 0 else 0, int(res["n_windows"][i]), cig))
+    return out
+
+
+def on_gpu(ctx, ps, launch=None, k=None, W=None, O=None):
+    reads = [ps.read(i) for i in range(ps.n_pairs)]
+    refs = [ps.ref(i) for i in range(ps.n_pairs)]
+    res, cig = ctx.align(reads, refs, ps.k if k is None else k, ps.W if W is None else W,
+                         ps.O if O is None else O, launch)
+    assert (res["flags"] == 0).all(), np.nonzero(res["flags"])[0][:10]
+    return [(int(r["edit_distance"]), int(r["ref_begin"]), int(r["ref_end"]), int(r["n_windows"]),
+             c) for r, c in zip(res, cig)]
+
+
+def assert_same(ps, want, got, label=""):
+    assert len(want) == len(got)
+    bad = [i for i in range(len(want)) if want[i] != got[i]]
+    if bad:
+        i = bad[0]
+        raise AssertionError(
+            f"{label}: {len(bad)} of {len(want)} pairs differ; first pair {i} "
+            f"(m={len(ps.read(i))}, n={len(ps.ref(i))}):\n oracle {want[i][:4]} {want[i][4][:200]}\n"
+            f" gpu    {got[i][:4]} {got[i][4][:200]}")
+
+
+FORMS = {
+    "plain": ga.make_launch(ga.FORM_PLAIN),
+    "batched": None,
+}
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_hand_examples(ctx, form):
+    for ex in load_hand_examples():
+        res, cig = ctx.align([ex["P"]], [ex["T"]], ex["k"], ex["W"], ex["O"], FORMS[form])
+        got = (int(res["edit_distance"][0]), cig[0], int(res["ref_begin"][0]),
+               int(res["ref_end"][0]), int(res["n_windows"][0]))
+        assert got == (ex["score"], ex["cigar"], ex["begin"], ex["end"], ex["windows"]), ex
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_short100_all_pairs(ctx, form):
+    ps = gen.make("short100")
+    assert_same(ps, expected(ps), on_gpu(ctx, ps, FORMS[form]), f"short100/{form}")
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_short250_subset(ctx, form):
+    ps = gen.make("short250", 3000)
+    assert_same(ps, expected(ps), on_gpu(ctx, ps, FORMS[form]), f"short250/{form}")
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_long10k_subset(ctx, form):
+    ps = gen.make("long10k", 48)
+    assert ps.decoy.any() and not ps.decoy.all()
+    assert_same(ps, expected(ps), on_gpu(ctx, ps, FORMS[form]), f"long10k/{form}")
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_uneven_subset(ctx, form):
+    ps = gen.make("uneven", 300)
+    assert_same(ps, expected(ps), on_gpu(ctx, ps, FORMS[form]), f"uneven/{form}")
+
+
+LAUNCH_VARIANTS = {
+    "g64": dict(group_lanes=64, lds_rows=64),
+    "g16_rows32": dict(group_lanes=16, lds_rows=32),
+    "g16_rows64": dict(group_lanes=16, lds_rows=64),
+    "search64": dict(search_lanes=64),
+    "input_order": dict(lpt_order=0),
+    "one_worker": dict(workers_per_cu=1),
+}
+
+
+@pytest.mark.parametrize("variant", sorted(LAUNCH_VARIANTS))
+def test_batched_launch_variants(ctx, variant):
+    L = ga.make_launch(ga.FORM_BATCHED, **LAUNCH_VARIANTS[variant])
+    ps = gen.make("long10k", 24, start=100)
+    assert_same(ps, expected(ps), on_gpu(ctx, ps, L), f"long10k/{variant}")
+    ps = gen.make("uneven", 200, start=500)
+    assert_same(ps, expected(ps), on_gpu(ctx, ps, L), f"uneven/{variant}")
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_fuzz_windows_and_caps(ctx, form):
+    rng = np.random.default_rng(21)
+    pairs = gen.fuzz(777, 600, max_len=400)
+    for chunk in range(6):
+        W = int(rng.choice([2, 4, 8, 16, 33, 63, 64]))
+        O = int(rng.choice(sorted({0, 1, W // 2, W - 1})))
+        k = int(rng.choice([0, 1, 5, 15, 64, 100]))
+        sub = pairs[chunk * 100:(chunk + 1) * 100]
+        ps = gen.from_lists("fuzz", [p[0] for p in sub], [p[1] for p in sub], k, W, O)
+        assert_same(ps, expected(ps), on_gpu(ctx, ps, FORMS[form]), f"fuzz W={W} O={O} k={k}/{form}")
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_edge_cases(ctx, form):
+    cases = [
+        ("", ""), ("", "ACGT"), ("ACGT", ""), ("A", "A"), ("A", "C"), ("A" * 64, "C" * 64),
+        ("A" * 64, "C" * 200), ("ACGT" * 16, "ACGT" * 16), ("ACGT" * 40, "T" + "ACGT" * 40),
+        ("G" * 130, "G" * 90), ("T" * 65, ""), ("ACGTTGCA" * 100, "ACGTTGCA" * 100),
+    ]
+    for k in (0, 3, 64):
+        ps = gen.from_lists("edge", [c[0] for c in cases], [c[1] for c in cases], k)
+        assert_same(ps, expected(ps), on_gpu(ctx, ps, FORMS[form]), f"edge k={k}/{form}")
+
+
+def test_device_form_matches_host_form(ctx):
+    import torch
+    ps = gen.make("uneven", 64)
+    res_h, cig_h = ctx.align([ps.read(i) for i in range(ps.n_pairs)],
+                             [ps.ref(i) for i in range(ps.n_pairs)], ps.k)
+    dev = torch.device("cuda:0")
+    reads2b = torch.from_numpy(ga.pack(ps.reads)).to(dev)
+    refs2b = torch.from_numpy(ga.pack(ps.refs)).to(dev)
+    roff = torch.from_numpy(ps.read_off.astype(np.int64)).to(dev)
+    foff = torch.from_numpy(ps.ref_off.astype(np.int64)).to(dev)
+    for launch in (None, ga.make_launch(ga.FORM_PLAIN)):
+        out, cigar = ctx.align_dev(reads2b, roff, refs2b, foff, ps.k, launch=launch)
+        torch.cuda.synchronize()
+        res = out.cpu().numpy().view(ga.RESULT_DTYPE).reshape(-1)
+        elems = cigar.cpu().numpy().view(np.uint32)
+        for i in range(ps.n_pairs):
+            assert res["edit_distance"][i] == res_h["edit_distance"][i]
+            o, n = int(res["cigar_off"][i]), int(res["cigar_len"][i])
+            assert ga.decode_cigar(elems[o:o + n]) == cig_h[i]
+
+
+def test_device_pack_matches_host_pack(ctx):
+    import torch
+    rng = np.random.default_rng(5)
+    codes = rng.integers(0, 4, 100_003).astype(np.uint8)
+    text = gen.to_ascii(codes)
+    dev = torch.device("cuda:0")
+    a = torch.frombuffer(bytearray(text), dtype=torch.uint8).to(dev)
+    packed = torch.zeros((len(text) + 3) // 4, dtype=torch.uint8, device=dev)
+    bad = torch.zeros(1, dtype=torch.int32, device=dev)
+    ctx.pack_dev(a, packed, bad)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 0
+    assert (packed.cpu().numpy() == ga.pack(text)).all()
+    bad.zero_()
+    a[7] = ord("N")
+    ctx.pack_dev(a, packed, bad)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 1
+
+
+def test_alphabet_error_is_reported(ctx):
+    with pytest.raises(ga.GenasmError) as e:
+        ctx.align(["ACGT"], ["ACNT"], 5)
+    assert e.value.code == ga.capi.E_ALPHABET
