@@ -137,7 +137,7 @@ int genasm_batch_align(genasm_ctx* ctx, const char* reads, const uint64_t* read_
 
 /*
  * Device-memory form, asynchronous on `stream` (a hipStream_t; NULL = the
- * context's stream).
+ * null stream).
  *   d_reads2b,       2-bit packed sequences in device memory: base b of the
  *   d_refs2b         stream is bits 2*(b%4)..2*(b%4)+1 of byte b/4, codes
  *                    A=0, C=1, G=2, T=3 (see genasm_pack).
@@ -175,7 +175,8 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
 int genasm_pack(const char* ascii, uint64_t n, uint8_t* packed, uint64_t* bad_index);
 
 /*
- * Device version of genasm_pack, asynchronous on `stream`: packs d_ascii[0..n)
+ * Device version of genasm_pack, asynchronous on `stream` (NULL = the null
+ * stream): packs d_ascii[0..n)
  * into d_packed[0..(n+3)/4) and adds the number of non-ACGT bytes to
  * *d_bad_count (device memory, caller-initialised).
  */

@@ -127,11 +127,24 @@ class GenasmError(RuntimeError):
         super().__init__(f"genasm error {code} ({strerror(code)}){': ' + msg if msg else ''}")
 
 
+def _share_torch_hip_runtime():
+    """PyTorch-ROCm ships its own HIP runtime. Importing torch first makes the
+    dynamic linker resolve this library's libamdhip64.so.7 to torch's copy (same
+    soname), so the process holds one HIP runtime and torch device memory is
+    valid for the kernels. Loaded in the other order, torch would map a second
+    runtime, which then finds no device."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2203_15561_amd.build`")
+        _share_torch_hip_runtime()
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)

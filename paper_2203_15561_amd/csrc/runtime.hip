@@ -62,8 +62,9 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int ensure(genasm_ctx* ctx, char** buf, size_t* cap, size_t need) {
     if (need <= *cap) return GENASM_OK;
     if (*buf) {
-        hipError_t e = hipStreamSynchronize(ctx->stream);
-        if (e != hipSuccess) return set_err(ctx, GENASM_E_DEVICE, "hipStreamSynchronize", e);
+        // the buffer may be in use by earlier calls on any stream
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return set_err(ctx, GENASM_E_DEVICE, "hipDeviceSynchronize", e);
         (void)hipFree(*buf);
         *buf = nullptr;
         *cap = 0;
@@ -267,7 +268,7 @@ int genasm_pack_dev(genasm_ctx* ctx, const char* d_ascii, uint64_t n, uint8_t* d
                     uint32_t* d_bad_count, void* stream) {
     if (!ctx) return GENASM_E_INVAL;
     if (n && (!d_ascii || !d_packed || !d_bad_count)) return set_err(ctx, GENASM_E_INVAL, "null pointer");
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;  // NULL: the null stream
     CHECK_HIP(ctx, hipSetDevice(ctx->device));
     CHECK_HIP(ctx, launch_pack(d_ascii, n, d_packed, d_bad_count, s));
     return GENASM_OK;
@@ -292,7 +293,7 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     genasm_launch L;
     int rc = resolve_launch(launch, &L);
     if (rc) return set_err(ctx, rc, "bad launch parameters");
-    hipStream_t s = stream ? (hipStream_t)stream : ctx->stream;
+    hipStream_t s = (hipStream_t)stream;  // NULL: the null stream
     CHECK_HIP(ctx, hipSetDevice(ctx->device));
 
     AlignParams p{};
