@@ -59,6 +59,7 @@ def main():
     ap.add_argument("--group-lanes", type=int, default=0)
     ap.add_argument("--lds-rows", type=int, default=0)
     ap.add_argument("--workers-per-cu", type=int, default=0)
+    ap.add_argument("--hard-row", type=int, default=0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -95,6 +96,8 @@ def main():
         kw["lds_rows"] = args.lds_rows
     if args.workers_per_cu:
         kw["workers_per_cu"] = args.workers_per_cu
+    if args.hard_row:
+        kw["hard_row"] = args.hard_row
     batched = ga.make_launch(ga.FORM_BATCHED, **kw)
     plain = ga.make_launch(ga.FORM_PLAIN)
 
@@ -170,7 +173,7 @@ def main():
         "config": {"workload": f"{args.workload}: {gen.DESCRIPTIONS[args.workload]}",
                    "pairs": ps.n_pairs, "k": ps.k, "W": ps.W, "O": ps.O, "form": "batched",
                    "group_lanes": batched.group_lanes, "lds_rows": batched.lds_rows,
-                   "workers_per_cu": batched.workers_per_cu},
+                   "workers_per_cu": batched.workers_per_cu, "hard_row": batched.hard_row},
         "gcups": cells / (ms_step / 1e3) / 1e9,
         "window_kernel_ms": float(np.mean(win_ms)),
         "search_ms": float(np.mean(search_ms)),

@@ -83,13 +83,18 @@ typedef struct {
 typedef struct {
     int32_t form;            /* GENASM_FORM_* */
     int32_t group_lanes;     /* batched: lanes (= DP rows per pass) per pair in the window
-                                kernel, 16 or 64; 0 = default */
+                                kernel for ordinary pairs, 16 or 64 (64 sends every pair to
+                                the whole-wavefront path); 0 = default */
     int32_t search_lanes;    /* batched: lanes per pair in the start search, 16 or 64; 0 = default */
-    int32_t lds_rows;        /* batched: window-table rows kept in LDS per pair (multiple of
-                                group_lanes, <= 64); rows above spill to device memory; 0 = default */
-    int32_t workers_per_cu;  /* batched: resident workgroups per compute unit; 0 = default */
+    int32_t lds_rows;        /* batched: window-table rows kept in LDS per 16-lane group
+                                (16, 32, 48 or 64); rows above spill to device memory; 0 = default */
+    int32_t workers_per_cu;  /* batched: resident window workgroups per compute unit; 0 = as many
+                                as LDS allows */
     int32_t lpt_order;       /* batched: 1 = longest reads first, 0 = input order; -1 = default */
-    int32_t reserved[2];
+    int32_t hard_row;        /* batched: pairs whose start search needs this many edit rows or
+                                more run one pair per wavefront with the whole 64-row table in
+                                LDS; 0 = default (65: never), 16 suits decoy-rich batches */
+    int32_t reserved;
 } genasm_launch;
 
 typedef struct genasm_ctx genasm_ctx;

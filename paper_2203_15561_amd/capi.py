@@ -58,7 +58,8 @@ class Launch(ctypes.Structure):
         ("lds_rows", ctypes.c_int32),
         ("workers_per_cu", ctypes.c_int32),
         ("lpt_order", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("hard_row", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

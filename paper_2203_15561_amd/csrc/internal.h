@@ -39,6 +39,9 @@ struct AlignParams {
     int32_t lds_rows;
     int32_t list_slot;          // which counters[] pair this search stage uses
     unsigned long long* stats;  // optional, kStatCount counters per pair (null = off)
+    uint32_t* easy_list;        // pairs for the 16-lane window groups (filled by the search)
+    uint32_t* hard_list;        // pairs for whole-wavefront windows (start row >= hard_row)
+    int32_t hard_row;
 };
 
 // Per-pair work counters written when AlignParams::stats is set.
@@ -53,8 +56,11 @@ constexpr int kStatSearchLaneSteps = 7; // lane-steps issued by the start search
 constexpr int kStatCount = 8;
 
 // counters[] layout: queue heads and list lengths for the batched pipeline.
-constexpr int kCounterWindowHead = 0;
-constexpr int kCounterListBase = 2;  // stage s: counters[2 + 2s] = list length, [3 + 2s] = head
+constexpr int kCounterListBase = 2;  // search stage s: counters[2 + 2s] = list length, [3 + 2s] = head
+constexpr int kCounterEasyLen = 10;
+constexpr int kCounterEasyHead = 11;
+constexpr int kCounterHardLen = 12;
+constexpr int kCounterHardHead = 13;
 constexpr int kCounterCount = 16;
 
 // LDS words per group, by kernel.
@@ -68,7 +74,7 @@ constexpr int kSearchGroupWords = kGroupHeaderWords;  // PM, ring, broadcast slo
 hipError_t launch_plain(const AlignParams& p, hipStream_t s);
 hipError_t launch_search(const AlignParams& p, int group_lanes, int rows_per_lane, int blocks,
                          hipStream_t s);
-hipError_t launch_windows(const AlignParams& p, int group_lanes, int blocks, hipStream_t s);
+hipError_t launch_windows(const AlignParams& p, int blocks, hipStream_t s);
 hipError_t launch_pack(const char* ascii, uint64_t n, uint8_t* packed, uint32_t* bad,
                        hipStream_t s);
 hipError_t launch_init_counters(uint32_t* counters, uint32_t stage0_len, hipStream_t s);
@@ -81,7 +87,7 @@ hipError_t launch_compact_cigar(const genasm_result* d_out, const uint64_t* dst_
 
 // Occupancy helpers.
 int plain_lds_bytes(int stride);
-int window_lds_bytes(int group_lanes, int lds_rows, int stride);
+int window_lds_bytes(int lds_rows, int stride);
 int search_lds_bytes(int group_lanes);
 
 }  // namespace genasm

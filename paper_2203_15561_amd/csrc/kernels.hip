@@ -171,9 +171,11 @@ __device__ void load_window(u64* lds, int gl, const uint8_t* reads, uint64_t rb,
 
 // Computes rows c*G .. c*G+G-1 (this lane: row c*G+gl) over columns nw-1..0.
 // Stores columns 0..Lc of the row (slots 1..Lc+1 of its table row; slot 0 and
-// Lc+2 absorb the out-of-window steps). Lane G-1 writes its row into the
-// boundary row, which lane 0 of the next pass reads as the row above.
-template <int G, bool SPILL>
+// Lc+2 absorb the out-of-window steps), including column nw (its initial
+// value) when nw <= W-O, so that the traceback never special-cases it. Lane
+// G-1 writes its row into the boundary row, which lane 0 of the next pass
+// reads as the row above. FIRST: pass 0, whose row above is all ones.
+template <int G, bool SPILL, bool FIRST>
 __device__ void dc_pass(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int stride,
                         int lds_rows) {
     const u64* pmt = lds + OFF_PMT;
@@ -183,7 +185,7 @@ __device__ void dc_pass(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int
     u64 R = init_word(d);
     u64 Dp = d == 0 ? ~0ull : init_word(d - 1);
     const u64 lowin = d == 0 ? 1ull : 0ull;
-    const bool first = (c == 0);
+    if (Lc == nw) trow[1 + nw] = R;  // lane 0 of a pass never computes column nw
     const int steps = nw + G - 1;
     constexpr int U = 4;
     u64 qpm[U], qov[U];
@@ -191,7 +193,7 @@ __device__ void dc_pass(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int
     for (int u = 0; u < U; ++u) {
         const int i = nw - 1 - u + gl;
         qpm[u] = pmt[clampi(i, 0, nw)];
-        qov[u] = first ? ~0ull : brow[1 + clampi(i, -1, nw + 1)];
+        qov[u] = FIRST ? ~0ull : brow[1 + clampi(i, -1, nw + 1)];
     }
     for (int t0 = 0; t0 < steps; t0 += U) {
 #pragma unroll
@@ -203,7 +205,7 @@ __device__ void dc_pass(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int
             // reads is written by lane G-1 only G-1+U steps later
             const int ip = i - U;
             qpm[u] = pmt[clampi(ip, 0, nw)];
-            qov[u] = first ? ~0ull : brow[1 + clampi(ip, -1, nw + 1)];
+            if (!FIRST) qov[u] = brow[1 + clampi(ip, -1, nw + 1)];
             const u64 up = LaneShift<G>::up(ov, R);
             const u64 x = Dp & (((Dp & up) << 1) | lowin);
             R = x & ((R << 1) | pm_t);
@@ -335,37 +337,82 @@ __device__ __forceinline__ u64 read_r(const u64* lds, const u64* spill, int row,
     return load_coherent(spill + (size_t)(row - lds_rows) * stride + 1 + col);
 }
 
-// CIGAR run writer, held by lane 0 of a group.
-struct RunWriter {
-    uint32_t* cigar;
-    uint64_t base, limit;  // element range of this pair
-    uint32_t n;
+// Run-length CIGAR under construction, held by lane 0 of a group. The runs of
+// the current window go to an LDS array (`runs`, the boundary-row area, free
+// during the traceback): slot nr holds the open run and is rewritten at every
+// step, and nr moves on when the op changes, so a step needs no branch. At the
+// end of each window the group copies the closed runs to device memory; the
+// open run is carried into the next window's slot 0, so runs merge across
+// window seams.
+struct RunState {
+    int cur_op;         // op of the open run, -1 before the pair's first op
     uint32_t cur_len;
-    int cur_op;
-    bool overflow;
-    __device__ void flush() {
-        if (cur_len) {
-            const uint64_t idx = base + n;
-            if (idx < limit) cigar[idx] = (cur_len << 2) | (uint32_t)cur_op;
-            else overflow = true;
-            ++n;
-        }
-        cur_len = 0;
-    }
-    __device__ void push(int op) {
-        if (op == cur_op && cur_len) {
-            ++cur_len;
-        } else {
-            flush();
-            cur_op = op;
-            cur_len = 1;
-        }
-    }
+    int nr;             // LDS slot of the open run, -1 before the pair's first op
 };
 
+__device__ __forceinline__ void run_push(uint32_t* runs, RunState& rs, int op, uint32_t count) {
+    const bool changed = op != rs.cur_op;
+    rs.nr += changed ? 1 : 0;
+    rs.cur_len = changed ? count : rs.cur_len + count;
+    rs.cur_op = op;
+    runs[rs.nr] = (rs.cur_len << 2) | (uint32_t)op;
+}
+
+// Before a window's traceback: the open run moves to slot 0.
+__device__ __forceinline__ void run_window_start(uint32_t* runs, RunState& rs) {
+    if (rs.nr >= 0) {
+        runs[0] = (rs.cur_len << 2) | (uint32_t)rs.cur_op;
+        rs.nr = 0;
+    }
+}
+
+// Traceback of one window from (i=0, p=mw-1, d=dstar) when every row it can
+// read, 0..min(d*, mw-1), is in LDS; lane 0 of the group only. Rows at or above
+// mw read as 0 (all their used bits are 0). Bit p of the four edge words is
+// tested directly: match (A << 1) | PM, substitution B << 1, insertion C << 1,
+// deletion B, with A = R[d][i+1], B = R[d-1][i+1], C = R[d-1][i]; the shifted
+// words give "p == 0 or bit p-1 is 0" in one test.
+__device__ TbOut traceback_lds(const u64* lds, uint32_t* runs, RunState& rs, int mw, int nw,
+                               int dstar, int L, int stride, int rows) {
+    const uint8_t* pch = reinterpret_cast<const uint8_t*>(lds + OFF_CH);
+    const uint8_t* tch = pch + 64;
+    const u64* tab = lds + OFF_TAB + 1;  // column c of a row sits in slot c + 1
+    const int top = min(mw, rows) - 1;
+    int i = 0, p = mw - 1, d = dstar;
+    TbOut o{0, 0, 0, 0u, false};
+    while (p >= 0 && i < L && mw - 1 - p < L) {
+        const int j = mw - 1 - p;
+        const int rb = max(d - 1, 0);
+        const u64 A0 = tab[min(d, top) * stride + i + 1];
+        const u64 B = tab[rb * stride + i + 1];
+        const u64 C = tab[rb * stride + i];
+        const u64 A = d < mw ? A0 : 0ull;  // d <= mw, so only row d can be past the window
+        const bool intext = i < nw;
+        const bool up = d >= 1;
+        const bool m_ok = intext && pch[j] == tch[i] && !(((A << 1) >> p) & 1ull);
+        const bool s_ok = up && intext && !(((B << 1) >> p) & 1ull);
+        const bool i_ok = up && !(((C << 1) >> p) & 1ull);
+        const bool d_ok = up && intext && !((B >> p) & 1ull);
+        const bool any = m_ok || s_ok || i_ok || d_ok;  // always: bit p of R[d][i] is 0
+        const int op = m_ok ? GENASM_OP_MATCH
+                     : s_ok ? GENASM_OP_MISMATCH : i_ok ? GENASM_OP_INS : GENASM_OP_DEL;
+        run_push(runs, rs, op, 1u);
+        o.reads += up ? 3u : 1u;
+        o.internal |= !any;
+        i += op != GENASM_OP_INS;
+        d -= op != GENASM_OP_MATCH;
+        p = any ? p - (op != GENASM_OP_DEL) : -1;
+    }
+    o.i_end = i;
+    o.j_end = mw - 1 - p;
+    o.edits = dstar - d;
+    return o;
+}
+
 // Traceback of one window from (i=0, p=mw-1, d=dstar); lane 0 of the group only.
-__device__ TbOut traceback(const u64* lds, const u64* spill, int mw, int nw, int dstar, int L,
-                           int lds_rows, int stride, RunWriter& rw) {
+// General form: rows at or above `lds_rows` come from the device-memory spill.
+__device__ TbOut traceback(const u64* lds, const u64* spill, uint32_t* runs, RunState& rs, int mw,
+                           int nw, int dstar, int L, int lds_rows, int stride) {
     const uint8_t* pch = reinterpret_cast<const uint8_t*>(lds + OFF_CH);
     const uint8_t* tch = pch + 64;
     int i = 0, p = mw - 1, d = dstar, j = 0;
@@ -389,7 +436,7 @@ __device__ TbOut traceback(const u64* lds, const u64* spill, int mw, int nw, int
         else if (i_ok) op = GENASM_OP_INS;
         else if (d_ok) op = GENASM_OP_DEL;
         else { o.internal = true; break; }
-        rw.push(op);
+        run_push(runs, rs, op, 1u);
         o.reads += d >= 1 ? 3u : 1u;
         i += op != GENASM_OP_INS;
         p -= op != GENASM_OP_DEL;
@@ -402,17 +449,35 @@ __device__ TbOut traceback(const u64* lds, const u64* spill, int mw, int nw, int
     return o;
 }
 
+// Copies runs [0, count) of the group's LDS run array to the pair's CIGAR in
+// device memory at element `written`; all lanes of the group take part.
+template <int G>
+__device__ __forceinline__ bool copy_runs(const uint32_t* runs, int count, uint32_t* cigar,
+                                          uint64_t base, uint64_t limit, uint32_t written, int gl) {
+    bool overflow = false;
+    for (int k = gl; k < count; k += G) {
+        const uint64_t idx = base + written + (uint64_t)k;
+        if (idx < limit) cigar[idx] = runs[k];
+        else overflow = true;
+    }
+    return overflow;
+}
+
 // Aligns the windows of one pair whose start search gave column `s`.
 // All G lanes of the group call this together; returns in lane 0 the result.
 template <int G>
-__device__ void align_windows(const AlignParams& P, u64* lds, u64* spill, int gl, int lane,
-                              uint64_t pair, const PairCursor& pc0, int s, genasm_result* res) {
+__device__ void align_windows(const AlignParams& P, u64* lds, u64* spill, int lds_rows, int gl,
+                              int lane, uint64_t pair, const PairCursor& pc0, int s,
+                              genasm_result* res) {
     PairCursor pc = pc0;
     pc.ti = s;
     pc.pj = 0;
     const uint64_t run_base = (P.read_off[pair] - P.read_off[0]) + (P.ref_off[pair] - P.ref_off[0]);
-    RunWriter rw{P.cigar, run_base, min(P.cigar_cap, run_base + (uint64_t)pc.m + (uint64_t)pc.n), 0,
-                 0, 0, false};
+    const uint64_t run_limit = min(P.cigar_cap, run_base + (uint64_t)pc.m + (uint64_t)pc.n);
+    uint32_t* runs = reinterpret_cast<uint32_t*>(lds + OFF_BROW);
+    RunState rs{-1, 0u, -1};
+    uint32_t written = 0;  // closed runs already in device memory
+    bool overflow = false;
     int64_t score = 0;
     uint32_t nwin = 0;
     u64 st_wops = 0, st_cells = 0, st_table = 0, st_tb = 0, st_steps = 0;
@@ -434,16 +499,17 @@ __device__ void align_windows(const AlignParams& P, u64* lds, u64* spill, int gl
         st_cells += (u64)mw * nw;
         for (int c = 0; c * G <= Kr; ++c) {
             st_steps += (u64)G * (nw + G - 1);
-            const bool spill_pass = c * G >= P.lds_rows;
+            const bool spill_pass = c * G >= lds_rows;
             if (spill_pass) {
-                dc_pass<G, true>(lds, spill, gl, c, nw, Lc, P.stride, P.lds_rows);
+                dc_pass<G, true, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
                 mem_sync();
             } else {
-                dc_pass<G, false>(lds, spill, gl, c, nw, Lc, P.stride, P.lds_rows);
+                if (c == 0) dc_pass<G, false, true>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                else dc_pass<G, false, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
                 wave_sync();
             }
             const int d = c * G + gl;
-            const u64 r0 = spill_pass ? load_coherent(spill + (size_t)(d - P.lds_rows) * P.stride + 1)
+            const u64 r0 = spill_pass ? load_coherent(spill + (size_t)(d - lds_rows) * P.stride + 1)
                                       : lds[OFF_TAB + d * P.stride + 1];
             const bool sol = d <= Kr && !((r0 >> (mw - 1)) & 1ull);
             const u64 bits = group_ballot(sol, G, lane);
@@ -454,23 +520,46 @@ __device__ void align_windows(const AlignParams& P, u64* lds, u64* spill, int gl
             else { failed = true; break; }
         }
         if (gl == 0) {
-            TbOut t = traceback(lds, spill, mw, nw, dstar, P.L, P.lds_rows, P.stride, rw);
+            TbOut t;
+            run_window_start(runs, rs);
+            if (nw == 0) {
+                // empty text window: every step of the traceback is an insertion
+                const int k = min(mw, P.L);
+                run_push(runs, rs, GENASM_OP_INS, (uint32_t)k);
+                t = TbOut{0, k, k, 0u, false};
+            } else if (min(dstar, mw - 1) < lds_rows) {
+                t = traceback_lds(lds, runs, rs, mw, nw, dstar, P.L, P.stride, lds_rows);
+            } else {
+                t = traceback(lds, spill, runs, rs, mw, nw, dstar, P.L, lds_rows, P.stride);
+            }
             internal |= t.internal;
             score += t.edits;
             st_tb += t.reads;
             st_wops += (u64)nw * (2 + 6 * dstar);
             st_table += (u64)(dstar + 1) * (Lc + 1);
             lds[OFF_BC + 1] = ((u64)(unsigned)t.i_end << 32) | (unsigned)t.j_end;
-            lds[OFF_BC + 2] = t.internal ? 1ull : 0ull;
+            lds[OFF_BC + 2] = ((u64)(unsigned)max(rs.nr, 0) << 1) | (t.internal ? 1ull : 0ull);
         }
         wave_sync();
         const u64 adv = lds[OFF_BC + 1];
-        const bool bad = lds[OFF_BC + 2] != 0;
-        wave_sync();
+        const u64 flags = lds[OFF_BC + 2];
+        const bool bad = (flags & 1ull) != 0;
         if (bad) { failed = true; internal = true; break; }
+        // closed runs of this window (slots below the open run) go to device memory
+        const int closed = (int)(flags >> 1);
+        overflow |= copy_runs<G>(runs, closed, P.cigar, run_base, run_limit, written, gl);
+        written += (uint32_t)closed;
+        wave_sync();
         pc.ti += (int)(adv >> 32);
         pc.pj += (int)(unsigned)adv;
     }
+    // the open run closes with the pair
+    if (!failed && gl == 0 && rs.nr >= 0) {
+        const uint64_t idx = run_base + written;
+        if (idx < run_limit) P.cigar[idx] = (rs.cur_len << 2) | (uint32_t)rs.cur_op;
+        else overflow = true;
+    }
+    const bool any_overflow = group_ballot(overflow, G, lane) != 0;
     if (gl == 0) {
         genasm_result r;
         if (failed) {
@@ -478,15 +567,14 @@ __device__ void align_windows(const AlignParams& P, u64* lds, u64* spill, int gl
             r.ref_begin = r.ref_end = 0;
             r.cigar_len = 0;
         } else {
-            rw.flush();
             r.edit_distance = (int32_t)score;
             r.ref_begin = (uint32_t)s;
             r.ref_end = (uint32_t)pc.ti;
-            r.cigar_len = rw.overflow ? 0u : rw.n;
+            r.cigar_len = any_overflow ? 0u : written + (rs.nr >= 0 ? 1u : 0u);
         }
         r.n_windows = nwin;
         r.cigar_off = run_base;
-        r.flags = (rw.overflow && !failed ? GENASM_FLAG_CIGAR_OVERFLOW : 0u) |
+        r.flags = (any_overflow && !failed ? GENASM_FLAG_CIGAR_OVERFLOW : 0u) |
                   (internal ? GENASM_FLAG_INTERNAL : 0u);
         *res = r;
         if (P.stats) {
@@ -566,7 +654,7 @@ __global__ __launch_bounds__(64) void k_plain(AlignParams P) {
             return;
         }
     }
-    align_windows<64>(P, smem, nullptr, lane, lane, pair, pc, col, res);
+    align_windows<64>(P, smem, nullptr, 64, lane, lane, pair, pc, col, res);
 }
 
 // ---------------------------------------------------------------------------
@@ -618,43 +706,61 @@ __global__ __launch_bounds__(64) void k_search(AlignParams P) {
             const int srow = row >= 0 ? row : (m1 <= P.K ? m1 : Kr);
             search_stats(P, pair, pc.n, m1, final ? srow : 0, (u64)G * RS * (pc.n + RS * G - 1),
                          P.list_slot == 0);
-            if (row >= 0) {
-                P.search[pair] = SearchOut{row, (uint32_t)col};
-            } else if (Kr < RS * G) {
-                // every needed row was computed without a hit
-                if (m1 <= P.K) P.search[pair] = SearchOut{m1, 0u};
-                else {
-                    write_simple_result(P.out + pair, -1, pair_run_base(P, pair));
-                    P.search[pair] = SearchOut{kSearchFailed, 0};
-                }
-            } else {
+            if (row < 0 && !final) {
                 const uint32_t pos = atomicAdd(len_out, 1u);
                 P.list_out[pos] = (uint32_t)pair;
                 P.search[pair] = SearchOut{kSearchPending, 0};
+            } else if (row < 0 && m1 > P.K) {
+                // every needed row was computed without a hit: the pair fails
+                write_simple_result(P.out + pair, -1, pair_run_base(P, pair));
+                P.search[pair] = SearchOut{kSearchFailed, 0};
+            } else {
+                // a hit, or row m1 (every column hits there); route to a window queue
+                const int r = row >= 0 ? row : m1;
+                P.search[pair] = SearchOut{r, row >= 0 ? (uint32_t)col : 0u};
+                const bool hard = r >= P.hard_row;
+                uint32_t* len = P.counters + (hard ? kCounterHardLen : kCounterEasyLen);
+                const uint32_t pos = atomicAdd(len, 1u);
+                (hard ? P.hard_list : P.easy_list)[pos] = (uint32_t)pair;
             }
         }
     }
 }
 
-template <int G>
-__global__ __launch_bounds__(64) void k_windows(AlignParams P, int groups_per_block) {
+// Window kernel of the batched form. Each workgroup is one wavefront. It first
+// takes pairs from the hard queue (start row >= hard_row: decoy-like pairs whose
+// windows need most of the 64 rows), one pair per wavefront with all 64 lanes
+// as rows and the full table in LDS; when that queue is empty it takes pairs
+// from the easy queue, four at a time in 16-lane groups with `lds_rows` table
+// rows in LDS (rows above spill to device memory).
+__global__ __launch_bounds__(64) void k_windows(AlignParams P) {
     extern __shared__ u64 smem[];
     const int lane = threadIdx.x & 63;
-    const int gl = lane & (G - 1);
-    const int grp = threadIdx.x / G;
-    const int words = window_group_words(P.lds_rows, P.stride);
-    u64* lds = smem + grp * words;
-    const uint64_t worker = (uint64_t)blockIdx.x * groups_per_block + grp;
-    const int spill_rows = 64 - P.lds_rows;
-    u64* spill = spill_rows > 0 ? P.spill + worker * (uint64_t)spill_rows * P.stride : nullptr;
-    for (uint64_t iter = 0; iter <= P.n_pairs; ++iter) {
-        const uint32_t item = group_pop(P.counters + kCounterWindowHead, lds, gl);
-        if (item >= P.n_pairs) break;
-        const uint64_t pair = P.order ? P.order[item] : item;
+    const uint32_t n_hard = __hip_atomic_load(P.counters + kCounterHardLen, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t n_easy = __hip_atomic_load(P.counters + kCounterEasyLen, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t iter = 0; iter <= n_hard; ++iter) {
+        const uint32_t item = group_pop(P.counters + kCounterHardHead, smem, lane);
+        if (item >= n_hard) break;
+        const uint64_t pair = P.hard_list[item];
         const SearchOut so = P.search[pair];
-        if (so.row < 0) continue;  // result already written by the search
-        const PairCursor pc = pair_cursor(P, pair);
-        align_windows<G>(P, lds, spill, gl, lane, pair, pc, (int)so.col, P.out + pair);
+        align_windows<64>(P, smem, nullptr, 64, lane, lane, pair, pair_cursor(P, pair),
+                          (int)so.col, P.out + pair);
+    }
+    const int gl = lane & 15;
+    const int grp = lane >> 4;
+    u64* lds = smem + grp * window_group_words(P.lds_rows, P.stride);
+    const int spill_rows = 64 - P.lds_rows;
+    u64* spill = spill_rows > 0
+        ? P.spill + ((uint64_t)blockIdx.x * 4 + grp) * (uint64_t)spill_rows * P.stride : nullptr;
+    for (uint32_t iter = 0; iter <= n_easy; ++iter) {
+        const uint32_t item = group_pop(P.counters + kCounterEasyHead, lds, gl);
+        if (item >= n_easy) break;
+        const uint64_t pair = P.easy_list[item];
+        const SearchOut so = P.search[pair];
+        align_windows<16>(P, lds, spill, P.lds_rows, gl, lane, pair, pair_cursor(P, pair),
+                          (int)so.col, P.out + pair);
     }
 }
 
@@ -724,8 +830,10 @@ __global__ void k_compact(const genasm_result* out, const uint64_t* dst_off, uin
 // ---------------------------------------------------------------------------
 
 int plain_lds_bytes(int stride) { return window_group_words(64, stride) * 8; }
-int window_lds_bytes(int group_lanes, int lds_rows, int stride) {
-    return (64 / group_lanes) * window_group_words(lds_rows, stride) * 8;
+int window_lds_bytes(int lds_rows, int stride) {
+    const int easy = 4 * window_group_words(lds_rows, stride);
+    const int hard = window_group_words(64, stride);
+    return (easy > hard ? easy : hard) * 8;
 }
 int search_lds_bytes(int group_lanes) { return (64 / group_lanes) * kSearchGroupWords * 8; }
 
@@ -752,11 +860,9 @@ hipError_t launch_search(const AlignParams& p, int group_lanes, int rows_per_lan
     return hipGetLastError();
 }
 
-hipError_t launch_windows(const AlignParams& p, int group_lanes, int blocks, hipStream_t s) {
-    const int lds = window_lds_bytes(group_lanes, p.lds_rows, p.stride);
-    if (group_lanes == 64) hipLaunchKernelGGL(k_windows<64>, dim3(blocks), dim3(64), lds, s, p, 1);
-    else if (group_lanes == 16) hipLaunchKernelGGL(k_windows<16>, dim3(blocks), dim3(64), lds, s, p, 4);
-    else return hipErrorInvalidValue;
+hipError_t launch_windows(const AlignParams& p, int blocks, hipStream_t s) {
+    const int lds = window_lds_bytes(p.lds_rows, p.stride);
+    hipLaunchKernelGGL(k_windows, dim3(blocks), dim3(64), lds, s, p);
     return hipGetLastError();
 }
 

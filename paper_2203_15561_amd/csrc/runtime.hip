@@ -103,13 +103,15 @@ int resolve_launch(const genasm_launch* in, genasm_launch* out) {
     if (in->group_lanes) out->group_lanes = in->group_lanes;
     if (in->search_lanes) out->search_lanes = in->search_lanes;
     if (in->lds_rows) out->lds_rows = in->lds_rows;
-    if (in->workers_per_cu) out->workers_per_cu = in->workers_per_cu;
+    out->workers_per_cu = in->workers_per_cu;
     if (in->lpt_order >= 0) out->lpt_order = in->lpt_order;
+    if (in->hard_row) out->hard_row = in->hard_row;
     if (out->group_lanes != 16 && out->group_lanes != 64) return GENASM_E_INVAL;
     if (out->search_lanes != 16 && out->search_lanes != 64) return GENASM_E_INVAL;
-    if (out->lds_rows < out->group_lanes || out->lds_rows > 64 || out->lds_rows % out->group_lanes)
-        return GENASM_E_INVAL;
-    if (out->workers_per_cu < 1 || out->workers_per_cu > 32) return GENASM_E_INVAL;
+    if (out->lds_rows < 16 || out->lds_rows > 64 || out->lds_rows % 16) return GENASM_E_INVAL;
+    if (out->workers_per_cu < 0 || out->workers_per_cu > 32) return GENASM_E_INVAL;
+    if (out->hard_row < 0 || out->hard_row > 65) return GENASM_E_INVAL;
+    if (out->group_lanes == 64) out->hard_row = 0;
     return GENASM_OK;
 }
 
@@ -140,8 +142,9 @@ int genasm_default_launch(int32_t form, genasm_launch* out) {
     out->group_lanes = 16;
     out->search_lanes = 16;
     out->lds_rows = 16;
-    out->workers_per_cu = 5;
+    out->workers_per_cu = 0;
     out->lpt_order = 1;
+    out->hard_row = 65;
     return GENASM_OK;
 }
 
@@ -334,11 +337,16 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     }
 
     // Batched: scratch layout.
-    const int G = L.group_lanes;
-    const int groups_per_block = 64 / G;
-    const int win_blocks = ctx->num_cus * L.workers_per_cu;
+    p.lds_rows = L.lds_rows;
+    p.hard_row = L.hard_row;
+    const int win_lds = window_lds_bytes(p.lds_rows, p.stride);
+    int per_cu = L.workers_per_cu;
+    if (per_cu == 0) {
+        per_cu = std::max(1, std::min(8, (160 * 1024) / win_lds));
+    }
+    const int win_blocks = ctx->num_cus * per_cu;
     const int search_blocks = ctx->num_cus * 8;
-    const uint64_t workers = (uint64_t)win_blocks * groups_per_block;
+    const uint64_t workers = (uint64_t)win_blocks * 4;
     const int spill_rows = 64 - L.lds_rows;
     size_t sort_tmp = 0;
     if (L.lpt_order) {
@@ -349,6 +357,8 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
         p.search = c.take<SearchOut>(n_pairs);
         p.counters = c.take<uint32_t>(kCounterCount);
         uint32_t* lists = c.take<uint32_t>(2 * n_pairs);
+        p.easy_list = c.take<uint32_t>(n_pairs);
+        p.hard_list = c.take<uint32_t>(n_pairs);
         p.spill = spill_rows > 0 ? c.take<unsigned long long>(workers * spill_rows * p.stride) : nullptr;
         uint32_t* keys = c.take<uint32_t>(n_pairs);
         uint32_t* vals = c.take<uint32_t>(n_pairs);
@@ -397,8 +407,7 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     CHECK_HIP(ctx, mark(2));
     p.list_in = nullptr;
     p.list_out = nullptr;
-    p.lds_rows = L.lds_rows;
-    CHECK_HIP(ctx, launch_windows(p, G, win_blocks, s));
+    CHECK_HIP(ctx, launch_windows(p, win_blocks, s));
     CHECK_HIP(ctx, mark(3));
     return GENASM_OK;
 }

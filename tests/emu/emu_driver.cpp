@@ -3,7 +3,7 @@
 //
 //   emu_driver IN OUT
 // IN : int64 form, group_lanes, search_lanes, lds_rows, k, W, O, n_pairs,
-//      read_bytes, ref_bytes; then the packed read bytes, the packed reference
+//      read_bytes, ref_bytes, hard_row; then the packed read bytes, the packed reference
 //      bytes, read_off[n+1], ref_off[n+1] (uint64).
 // OUT: n genasm_result records, then (read bases + ref bases) CIGAR elements.
 #include "../../paper_2203_15561_amd/csrc/kernels.hip"
@@ -23,11 +23,12 @@ int main(int argc, char** argv) {
     if (argc != 3) { fprintf(stderr, "usage: emu_driver IN OUT\n"); return 2; }
     FILE* f = fopen(argv[1], "rb");
     if (!f) { perror("open IN"); return 2; }
-    int64_t h[10];
+    int64_t h[11];
     if (!read_all(f, h, sizeof h)) return 2;
     const int form = (int)h[0], G = (int)h[1], SG = (int)h[2], lds_rows = (int)h[3];
     const int k = (int)h[4], W = (int)h[5], O = (int)h[6];
     const uint64_t n = (uint64_t)h[7], nrb = (uint64_t)h[8], nfb = (uint64_t)h[9];
+    const int hard_row = (int)h[10];
     std::vector<uint8_t> reads(nrb + 8), refs(nfb + 8);
     std::vector<uint64_t> roff(n + 1), foff(n + 1);
     if (!read_all(f, reads.data(), nrb) || !read_all(f, refs.data(), nfb) ||
@@ -61,10 +62,11 @@ int main(int argc, char** argv) {
         launch_plain(p, nullptr);
     } else {
         const int blocks = 2;
-        const uint64_t workers = (uint64_t)blocks * (64 / G);
+        const uint64_t workers = (uint64_t)blocks * 4;
         const int spill_rows = 64 - lds_rows;
         std::vector<SearchOut> search(n, SearchOut{kSearchPending, 0});
         std::vector<uint32_t> counters(kCounterCount, 0), lists(2 * n + 1), order(n);
+        std::vector<uint32_t> easy(n + 1), hard(n + 1);
         std::vector<unsigned long long> spill(std::max<uint64_t>(workers * spill_rows * p.stride, 1));
         std::iota(order.begin(), order.end(), 0u);
         std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
@@ -74,6 +76,10 @@ int main(int argc, char** argv) {
         p.counters = counters.data();
         p.spill = spill_rows > 0 ? spill.data() : nullptr;
         p.order = order.data();
+        p.easy_list = easy.data();
+        p.hard_list = hard.data();
+        p.hard_row = G == 64 ? 0 : hard_row;
+        p.lds_rows = lds_rows;
         launch_init_counters(p.counters, (uint32_t)n, nullptr);
         p.list_in = p.order;
         p.list_out = lists.data();
@@ -100,9 +106,18 @@ int main(int argc, char** argv) {
         }
         p.list_in = nullptr;
         p.list_out = nullptr;
-        p.lds_rows = lds_rows;
-        emu::group_lanes = G;
-        launch_windows(p, G, blocks, nullptr);
+        // The window kernel changes lane-group width between its two queues; the
+        // emulation runs it once per queue with the matching group width.
+        const uint32_t n_easy = counters[kCounterEasyLen], n_hard = counters[kCounterHardLen];
+        counters[kCounterEasyLen] = 0;
+        emu::group_lanes = 64;
+        launch_windows(p, blocks, nullptr);
+        counters[kCounterEasyLen] = n_easy;
+        counters[kCounterEasyHead] = 0;  // the first launch's easy loop popped past the end
+        counters[kCounterHardLen] = 0;
+        emu::group_lanes = 16;
+        launch_windows(p, blocks, nullptr);
+        fprintf(stderr, "emu: %u easy pairs, %u hard pairs\n", n_easy, n_hard);
     }
     FILE* g = fopen(argv[2], "wb");
     if (!g) { perror("open OUT"); return 2; }

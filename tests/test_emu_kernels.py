@@ -1,0 +1,87 @@
+"""The GPU kernels' logic on the CPU: kernels.hip is built unmodified with g++
+against the HIP emulation in tests/emu (lanes as threads, lane-group
+barriers for DPP moves, ballots and wave barriers; host AddressSanitizer and
+UBSan on) and its outputs are compared with the oracle. No GPU is involved;
+this catches indexing and control-flow mistakes in the kernels before they
+run on hardware."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from tests._helpers import load_hand_examples, rle
+from tests.emu import run as emu
+from workloads import gen
+
+pytestmark = pytest.mark.slow
+
+
+@pytest.fixture(scope="module")
+def driver():
+    with tempfile.TemporaryDirectory() as tmp:
+        yield emu.build(os.path.join(tmp, "emu_driver"))
+
+
+def expected(ps):
+    res, ops, _, _ = oracle.batch(ps)
+    return [(int(res["score"][i]), rle(oracle.pair_ops(ps, res, ops, i)) if res["score"][i] >= 0 else "",
+             int(res["ref_begin"][i]) if res["score"][i] >= 0 else 0,
+             int(res["ref_end"][i]) if res["score"][i] >= 0 else 0, int(res["n_windows"][i]))
+            for i in range(ps.n_pairs)]
+
+
+def emulated(driver, ps, form, hard_row=16):
+    res, cig = emu.run(driver, ps, form, 16, 16, 16, hard_row=hard_row)
+    assert (res["flags"] == 0).all()
+    return [(int(r["edit_distance"]), c, int(r["ref_begin"]), int(r["ref_end"]), int(r["n_windows"]))
+            for r, c in zip(res, cig)]
+
+
+def check(driver, ps, form, hard_row=16):
+    want, got = expected(ps), emulated(driver, ps, form, hard_row)
+    bad = [i for i in range(ps.n_pairs) if want[i] != got[i]]
+    assert not bad, (bad[:5], want[bad[0]], got[bad[0]])
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_hand_examples(driver, form):
+    for ex in load_hand_examples():
+        ps = gen.from_lists("hand", [ex["P"]], [ex["T"]], ex["k"], ex["W"], ex["O"])
+        check(driver, ps, form)
+
+
+@pytest.mark.parametrize("hard_row", [16, 0, 65])
+def test_fuzz_batched(driver, hard_row):
+    # hard_row 0 sends every pair through the whole-wavefront path, whose
+    # 64-lane emulation is slow: fewer and shorter pairs there
+    rng = np.random.default_rng(31 + hard_row)
+    n, max_len = (8, 120) if hard_row == 0 else (40, 250)
+    pairs = gen.fuzz(4242 + hard_row, 2 * n, max_len=max_len)
+    for chunk in range(2):
+        W = int(rng.choice([4, 8, 33, 64]))
+        O = int(rng.choice(sorted({0, 1, W // 2, W - 1})))
+        k = int(rng.choice([1, 5, 64]))
+        sub = pairs[chunk * n:(chunk + 1) * n]
+        ps = gen.from_lists("fuzz", [p[0] for p in sub], [p[1] for p in sub], k, W, O)
+        check(driver, ps, 1, hard_row)
+
+
+def test_edge_cases_batched(driver):
+    cases = [("", ""), ("", "ACGT"), ("ACGT", ""), ("A" * 64, "C" * 64), ("G" * 130, "G" * 90),
+             ("T" * 65, ""), ("ACGT" * 16, "ACGT" * 16)]
+    for k in (0, 3, 64):
+        ps = gen.from_lists("edge", [c[0] for c in cases], [c[1] for c in cases], k)
+        check(driver, ps, 1)
+
+
+@pytest.mark.parametrize("hard_row", [16, 65])
+def test_long_read_prefixes_with_decoy(driver, hard_row):
+    # 1,200-base prefixes of a true pair and a decoy pair: the decoy's windows
+    # need most of the 64 rows (hard path, or spilled rows when hard_row=65)
+    ps = gen.make("long10k", 2, start=4)  # pair 4 is a decoy, pair 5 is not
+    assert ps.decoy.tolist() == [True, False]
+    cut = gen.from_lists("long-prefix", [ps.read(i)[:1200] for i in range(2)],
+                         [ps.ref(i)[:1300] for i in range(2)], 64)
+    check(driver, cut, 1, hard_row)

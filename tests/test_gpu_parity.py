@@ -101,6 +101,9 @@ LAUNCH_VARIANTS = {
     "search64": dict(search_lanes=64),
     "input_order": dict(lpt_order=0),
     "one_worker": dict(workers_per_cu=1),
+    "all_hard": dict(hard_row=0),
+    "no_hard": dict(hard_row=65),
+    "hard_from_8": dict(hard_row=8),
 }
 
 
