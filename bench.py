@@ -44,6 +44,93 @@ def rle(ops: str) -> str:
     return "".join(out)
 
 
+def serving_leg(ga, gen, ctx, args):
+    """Serving form on the request mix: a saturated run (every request queued
+    at once) gives the sustainable rate; an open-loop run with Poisson arrivals
+    at a fraction of it gives latency percentiles, measured from each request's
+    scheduled arrival to its completion."""
+    def requests(n, start):
+        ps = gen.make("serving", n, start=start)
+        asc = [(ga.capi._ascii(ps.read(i)), ga.capi._ascii(ps.ref(i))) for i in range(n)]
+        return ps, asc
+
+    def drain(srv, n, got, deadline_s=300.0):
+        t_end = time.time() + deadline_s
+        t_log = time.time() + 10
+        while len(got) < n:
+            if time.time() > t_end:
+                raise RuntimeError(f"serving: {n - len(got)} requests did not complete")
+            for c in srv.poll(timeout_ms=20):
+                got[c["tag"]] = c
+            if time.time() > t_log:
+                log(f"serving: {len(got)} of {n} requests completed")
+                t_log = time.time() + 10
+
+    ps, asc = requests(args.serving_requests, 0)
+    out = {"mix": gen.DESCRIPTIONS["serving"], "k": ps.k, "W": ps.W, "O": ps.O}
+    with ga.Server(ctx, ps.k, ps.W, ps.O) as srv:
+        # warm-up: a few requests through the graph
+        for i in range(64):
+            assert srv.submit(asc[i][0], asc[i][1], i) == 0
+        drain(srv, 64, {})
+        st0 = srv.stats()
+        got = {}
+        t0 = ga.now_ns()
+        for i, (r, f) in enumerate(asc):
+            while srv.submit(r, f, i) == ga.capi.E_BUSY:
+                for c in srv.poll(timeout_ms=1):
+                    got[c["tag"]] = c
+        drain(srv, len(asc), got)
+        t1 = max(c["done_ns"] for c in got.values())
+        st1 = srv.stats()
+        assert all(c["flags"] == 0 for c in got.values())
+        sat = len(asc) / ((t1 - t0) / 1e9)
+        iters = st1["iterations"] - st0["iterations"]
+        out["saturated"] = {"requests": len(asc), "requests_per_s": sat, "seconds": (t1 - t0) / 1e9,
+                            "iterations": iters,
+                            "device_ms_per_iteration": (st1["device_ms"] - st0["device_ms"]) / max(iters, 1)}
+        log(f"serving saturated: {sat:.0f} req/s over {len(asc)} requests, {iters} iterations")
+
+        rate = args.serving_load * sat
+        n_open = max(100, int(rate * args.serving_seconds))
+        ps2, asc2 = requests(n_open, args.serving_requests)
+        rng = np.random.default_rng(2203)
+        gaps = rng.exponential(1.0 / rate, n_open)
+        got = {}
+        t_start = ga.now_ns() + 1_000_000
+        sched = t_start + np.cumsum(gaps * 1e9).astype(np.int64)
+        i = 0
+        while i < n_open:
+            now = ga.now_ns()
+            while i < n_open and sched[i] <= now:
+                while srv.submit(asc2[i][0], asc2[i][1], i) == ga.capi.E_BUSY:
+                    time.sleep(0.0005)
+                i += 1
+            for c in srv.poll(timeout_ms=0):
+                got[c["tag"]] = c
+            if i < n_open:
+                wait = (sched[i] - ga.now_ns()) / 1e9
+                if wait > 0.0002:
+                    time.sleep(min(wait, 0.002))
+        drain(srv, n_open, got)
+        lat = np.array([(got[t]["done_ns"] - sched[t]) / 1e6 for t in range(n_open)])
+        short = np.array([len(ps2.read(t)) <= 1000 for t in range(n_open)])
+        t_last = max(c["done_ns"] for c in got.values())
+        out["open_loop"] = {
+            "arrival_rate_per_s": rate, "requests": n_open,
+            "completed_per_s": n_open / ((t_last - t_start) / 1e9),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()),
+            "short_p50_ms": float(np.percentile(lat[short], 50)) if short.any() else None,
+            "short_p99_ms": float(np.percentile(lat[short], 99)) if short.any() else None,
+            "long_p50_ms": float(np.percentile(lat[~short], 50)) if (~short).any() else None,
+            "long_p99_ms": float(np.percentile(lat[~short], 99)) if (~short).any() else None,
+        }
+        log(f"serving open loop at {rate:.0f} req/s: p50 {out['open_loop']['p50_ms']:.2f} ms, "
+            f"p99 {out['open_loop']['p99_ms']:.2f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +147,13 @@ def main():
     ap.add_argument("--lds-rows", type=int, default=0)
     ap.add_argument("--workers-per-cu", type=int, default=0)
     ap.add_argument("--hard-row", type=int, default=0)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serving-requests", type=int, default=20000,
+                    help="requests of the serving mix for the saturated run")
+    ap.add_argument("--serving-load", type=float, default=0.5,
+                    help="open-loop arrival rate as a fraction of the saturated rate")
+    ap.add_argument("--serving-seconds", type=float, default=4.0,
+                    help="length of the open-loop arrival schedule")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -198,6 +292,9 @@ def main():
         line["plain"] = {"alignments_per_s": ps.n_pairs / (pm / 1e3), "ms": pm,
                          "gcups": cells / (pm / 1e3) / 1e9}
         log(f"plain: {pm:.2f} ms/step")
+
+    if not args.no_serving:
+        line["serving"] = serving_leg(ga, gen, ctx, args)
 
     if not args.no_cpu_baseline:
         import oracle

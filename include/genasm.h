@@ -226,6 +226,86 @@ typedef struct {
 int genasm_profile_enable(genasm_ctx* ctx, int on);
 int genasm_profile_read(genasm_ctx* ctx, genasm_profile* out);
 
+/*
+ * Serving form: continuous batching of single-pair requests.
+ *
+ * A server owns an engine thread and device-resident state: a pool of packed
+ * read and reference bases, a pool of CIGAR elements, and per-slot window
+ * state. Each device iteration:
+ *   1. admits waiting requests into free slots while the slot count and both
+ *      pools have room (admission by device-memory budget);
+ *   2. runs the start search for the newly admitted pairs and, concurrently,
+ *      advances every resident pair whose search has finished by at most
+ *      `window_budget` windows (the window work of all resident pairs
+ *      overlaps on the device; one captured HIP graph per iteration);
+ *   3. returns finished pairs to the completion queue and frees their slots.
+ * Requests that arrive while others are on the device join at the next
+ * iteration. A request's result does not depend on the other requests in
+ * flight: each pair's windows run exactly as in genasm_batch_align.
+ * All requests of one server use its k, W and O.
+ */
+typedef struct genasm_server genasm_server;
+
+typedef struct {
+    int32_t k, W, O;          /* alignment parameters of every request */
+    uint32_t max_slots;       /* pairs resident on the device at once; 0 = 8192 */
+    uint64_t pool_bases;      /* device pool for resident reads and references, in bases;
+                                 0 = 2^28 */
+    uint32_t max_pending;     /* requests waiting on the host before genasm_submit returns
+                                 GENASM_E_BUSY; 0 = 65536 */
+    uint32_t window_budget;   /* windows a resident pair advances per iteration; 0 = 32 */
+    int32_t use_graph;        /* 1 = replay one captured hipGraph per iteration, 0 = launch the
+                                 kernels directly; -1 or 0-initialised config: 1 */
+    int32_t reserved[3];
+} genasm_server_config;
+
+typedef struct {
+    uint64_t tag;             /* the submitter's tag */
+    genasm_result result;     /* cigar_off = 0; cigar_len = characters of `cigar` */
+    char* cigar;              /* NUL-terminated CIGAR text, owned by the completion */
+    uint64_t submit_ns;       /* genasm_now_ns() at genasm_submit */
+    uint64_t admit_ns;        /* when the request entered a device slot */
+    uint64_t done_ns;         /* when its result and CIGAR reached host memory */
+} genasm_completion;
+
+typedef struct {
+    uint64_t iterations;      /* device iterations run */
+    uint64_t submitted, admitted, completed, refused;
+    uint32_t resident;        /* requests in device slots now */
+    uint32_t pending;         /* requests waiting on the host now */
+    uint64_t pool_bases_used;
+    double device_ms;         /* summed wall time of the iterations' device work */
+} genasm_server_stats;
+
+/* Creates a server on `ctx` (which it then uses exclusively until destroyed).
+ * Returns GENASM_E_INVAL for bad parameters, GENASM_E_NOMEM/GENASM_E_DEVICE on
+ * allocation or device failure. */
+int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg, genasm_server** out);
+
+/* Queues one request (ASCII read of m bases, reference of n bases, copied
+ * before return). k, W and O must equal the server's (else GENASM_E_INVAL).
+ * Returns GENASM_E_BUSY when max_pending requests already wait,
+ * GENASM_E_ALPHABET for a non-ACGT byte, GENASM_E_TOOLONG when the pair can
+ * never fit the pools. Thread-safe. */
+int genasm_submit(genasm_server* srv, const char* read, uint64_t m, const char* ref, uint64_t n,
+                  int32_t k, int32_t W, int32_t O, uint64_t tag);
+
+/* Moves up to `max` completions into out[], waiting up to timeout_ms for the
+ * first one (0 = do not wait). Returns the number moved, or a negative error
+ * (GENASM_E_DEVICE: the engine stopped on a device error). Thread-safe. */
+int genasm_poll(genasm_server* srv, genasm_completion* out, int max, int timeout_ms);
+
+/* Frees the CIGAR text of a completion. */
+void genasm_completion_release(genasm_completion* c);
+
+int genasm_server_stats_read(genasm_server* srv, genasm_server_stats* out);
+
+/* Stops the engine (requests still waiting are dropped) and frees the server. */
+void genasm_server_destroy(genasm_server* srv);
+
+/* Monotonic clock used by the completion timestamps, in nanoseconds. */
+uint64_t genasm_now_ns(void);
+
 /* Library version string. */
 const char* genasm_version(void);
 

@@ -7,4 +7,5 @@ include/genasm.h); this package only marshals arguments.
 from .capi import (  # noqa: F401
     Context, GenasmError, Launch, RESULT_DTYPE, FORM_PLAIN, FORM_BATCHED, EXPORTS,
     default_launch, make_launch, pack, validate, decode_cigar, version, lib, LIB_PATH,
+    Server, now_ns,
 )

@@ -84,12 +84,57 @@ class Profile(ctypes.Structure):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int32),
+        ("W", ctypes.c_int32),
+        ("O", ctypes.c_int32),
+        ("max_slots", ctypes.c_uint32),
+        ("pool_bases", ctypes.c_uint64),
+        ("max_pending", ctypes.c_uint32),
+        ("window_budget", ctypes.c_uint32),
+        ("use_graph", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
+    ]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [
+        ("tag", ctypes.c_uint64),
+        ("result", Result),
+        ("cigar", ctypes.c_void_p),
+        ("submit_ns", ctypes.c_uint64),
+        ("admit_ns", ctypes.c_uint64),
+        ("done_ns", ctypes.c_uint64),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_uint64),
+        ("submitted", ctypes.c_uint64),
+        ("admitted", ctypes.c_uint64),
+        ("completed", ctypes.c_uint64),
+        ("refused", ctypes.c_uint64),
+        ("resident", ctypes.c_uint32),
+        ("pending", ctypes.c_uint32),
+        ("pool_bases_used", ctypes.c_uint64),
+        ("device_ms", ctypes.c_double),
+    ]
+
+
+assert ctypes.sizeof(ServerConfig) == 48 and ctypes.sizeof(Completion) == 72
+assert ctypes.sizeof(ServerStats) == 64
+
+
 # Every symbol include/genasm.h declares.
 EXPORTS = [
     "genasm_create", "genasm_destroy", "genasm_last_error", "genasm_strerror",
     "genasm_default_launch", "genasm_batch_align", "genasm_batch_align_dev", "genasm_pack",
     "genasm_pack_dev", "genasm_validate", "genasm_version", "genasm_profile_enable",
-    "genasm_profile_read",
+    "genasm_profile_read", "genasm_server_create", "genasm_submit", "genasm_poll",
+    "genasm_completion_release", "genasm_server_stats_read", "genasm_server_destroy",
+    "genasm_now_ns",
 ]
 
 _c = ctypes
@@ -117,6 +162,15 @@ _SIGS = {
     "genasm_version": (_c.c_char_p, []),
     "genasm_profile_enable": (_c.c_int, [_c.c_void_p, _c.c_int]),
     "genasm_profile_read": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "genasm_server_create": (_c.c_int, [_c.c_void_p, _c.POINTER(ServerConfig),
+                                        _c.POINTER(_c.c_void_p)]),
+    "genasm_submit": (_c.c_int, [_c.c_void_p, _c.c_char_p, _c.c_uint64, _c.c_char_p, _c.c_uint64,
+                                 _c.c_int32, _c.c_int32, _c.c_int32, _c.c_uint64]),
+    "genasm_poll": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int, _c.c_int]),
+    "genasm_completion_release": (None, [_c.POINTER(Completion)]),
+    "genasm_server_stats_read": (_c.c_int, [_c.c_void_p, _c.POINTER(ServerStats)]),
+    "genasm_server_destroy": (None, [_c.c_void_p]),
+    "genasm_now_ns": (_c.c_uint64, []),
 }
 
 _lib = None
@@ -317,3 +371,67 @@ class Context:
         rc = lib().genasm_pack_dev(self._ctx, ascii_dev.data_ptr(), ascii_dev.numel(),
                                    packed_dev.data_ptr(), bad_dev.data_ptr(), stream)
         self._check(rc, "genasm_pack_dev")
+
+
+def now_ns() -> int:
+    return int(lib().genasm_now_ns())
+
+
+class Server:
+    """Serving form: continuous batching of single-pair requests on one
+    context (see genasm_server_create)."""
+
+    def __init__(self, ctx: Context, k: int, W: int = 64, O: int = 24, max_slots: int = 0,
+                 pool_bases: int = 0, max_pending: int = 0, window_budget: int = 0,
+                 use_graph: int = 1):
+        cfg = ServerConfig(k, W, O, max_slots, pool_bases, max_pending, window_budget, use_graph)
+        self._srv = ctypes.c_void_p()
+        rc = lib().genasm_server_create(ctx._ctx, ctypes.byref(cfg), ctypes.byref(self._srv))
+        if rc:
+            raise GenasmError(rc, "genasm_server_create")
+        self.ctx = ctx
+        self.k, self.W, self.O = k, W, O
+        self._buf = (Completion * 1024)()
+
+    def submit(self, read, ref, tag: int) -> int:
+        """Queues one request; returns 0 or a GENASM_E_* code (E_BUSY: back-pressure)."""
+        r, f = _ascii(read), _ascii(ref)
+        return lib().genasm_submit(self._srv, r, len(r), f, len(f), self.k, self.W, self.O, tag)
+
+    def poll(self, max_n: int = 1024, timeout_ms: int = 0) -> list:
+        n = lib().genasm_poll(self._srv, self._buf, min(max_n, len(self._buf)), timeout_ms)
+        if n < 0:
+            raise GenasmError(n, "genasm_poll")
+        out = []
+        for c in self._buf[:n]:
+            r = c.result
+            out.append({"tag": c.tag, "edit_distance": r.edit_distance, "ref_begin": r.ref_begin,
+                        "ref_end": r.ref_end, "n_windows": r.n_windows, "flags": r.flags,
+                        "cigar": ctypes.string_at(c.cigar).decode() if c.cigar else "",
+                        "submit_ns": c.submit_ns, "admit_ns": c.admit_ns, "done_ns": c.done_ns})
+            lib().genasm_completion_release(ctypes.byref(c))
+        return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        rc = lib().genasm_server_stats_read(self._srv, ctypes.byref(st))
+        if rc:
+            raise GenasmError(rc, "genasm_server_stats_read")
+        return {f[0]: getattr(st, f[0]) for f in ServerStats._fields_}
+
+    def close(self):
+        if self._srv:
+            lib().genasm_server_destroy(self._srv)
+            self._srv = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass

@@ -4,9 +4,50 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "genasm.h"
 
+// Library context (opaque in the C ABI).
+struct genasm_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    int num_cus = 0;
+    std::string err;
+    // device scratch arena
+    char* scratch = nullptr;
+    size_t scratch_cap = 0;
+    // host-form staging (device)
+    char* stage = nullptr;
+    size_t stage_cap = 0;
+    // profiling
+    bool profiling = false;
+    bool have_profile = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    char* stats = nullptr;
+    size_t stats_cap = 0;
+    uint64_t prof_pairs = 0;
+    int prof_form = 0;
+};
+
 namespace genasm {
+
+// Resumable per-pair window state (serving: pairs advance a few windows per
+// iteration and keep their state in device memory between iterations).
+struct PairState {
+    int32_t ti, pj;       // reference / read cursor
+    int32_t score;        // committed edits
+    uint32_t nwin;        // windows processed
+    uint32_t written;     // CIGAR elements already in device memory
+    int32_t cur_op;       // op of the open CIGAR run, -1 before the first op
+    uint32_t cur_len;
+    uint32_t flags;       // kState* bits
+};
+constexpr uint32_t kStateStarted = 1u;
+constexpr uint32_t kStateDone = 2u;       // result written
+constexpr uint32_t kStateFailed = 4u;
+constexpr uint32_t kStateInternal = 8u;
+constexpr uint32_t kStateOverflow = 16u;
 
 // Per-pair start-search outcome kept in device scratch.
 struct SearchOut {
@@ -42,6 +83,13 @@ struct AlignParams {
     uint32_t* easy_list;        // pairs for the 16-lane window groups (filled by the search)
     uint32_t* hard_list;        // pairs for whole-wavefront windows (start row >= hard_row)
     int32_t hard_row;
+    int32_t route;              // search: append finished pairs to the window lists
+    // Optional per-pair layout (serving: sequences sit anywhere in a device pool).
+    const uint32_t* read_len;   // if set, pair i's read is [read_off[i], read_off[i] + read_len[i])
+    const uint32_t* ref_len;
+    const uint64_t* run_base;   // if set, first CIGAR element of pair i; else from the offsets
+    PairState* state;           // if set, window state persists here between launches
+    uint32_t window_budget;     // windows a pair may advance per launch (0 = to the end)
 };
 
 // Per-pair work counters written when AlignParams::stats is set.
@@ -78,11 +126,25 @@ hipError_t launch_windows(const AlignParams& p, int blocks, hipStream_t s);
 hipError_t launch_pack(const char* ascii, uint64_t n, uint8_t* packed, uint32_t* bad,
                        hipStream_t s);
 hipError_t launch_init_counters(uint32_t* counters, uint32_t stage0_len, hipStream_t s);
+// Serving: stage-0 search list length and the easy window list length come
+// from a device parameter block (set by a copy before the launch or a replay).
+hipError_t launch_init_counters_dev(uint32_t* counters, const uint32_t* params, hipStream_t s);
+hipError_t launch_reset_states(PairState* state, const uint32_t* list, const uint32_t* params,
+                               uint32_t max_n, hipStream_t s);
+hipError_t launch_gather_runs(const genasm_result* out, const uint32_t* list, uint32_t n,
+                              const uint64_t* dst_off, const uint32_t* cigar, uint32_t* dst,
+                              hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_lpt_keys(const uint64_t* read_off, uint64_t n_pairs, uint32_t* keys,
                            uint32_t* vals, hipStream_t s);
 hipError_t launch_compact_cigar(const genasm_result* d_out, const uint64_t* dst_off,
                                 uint64_t n_pairs, const uint32_t* cigar, uint32_t* dst,
+                                hipStream_t s);
+
+// Scatters byte ranges: for k < n, copies len[k] bytes from src + src_off[k]
+// to dst + dst_off[k] (serving: packed sequences into the device pool).
+hipError_t launch_scatter_bytes(const uint8_t* src, const uint64_t* src_off, uint8_t* dst,
+                                const uint64_t* dst_off, const uint32_t* len, uint32_t n,
                                 hipStream_t s);
 
 // Occupancy helpers.

@@ -463,35 +463,53 @@ __device__ __forceinline__ bool copy_runs(const uint32_t* runs, int count, uint3
     return overflow;
 }
 
-// Aligns the windows of one pair whose start search gave column `s`.
-// All G lanes of the group call this together; returns in lane 0 the result.
+__device__ __forceinline__ PairCursor pair_cursor(const AlignParams& P, uint64_t pair) {
+    PairCursor pc;
+    pc.rb = P.read_off[pair];
+    pc.fb = P.ref_off[pair];
+    pc.m = (int)(P.read_len ? P.read_len[pair] : P.read_off[pair + 1] - pc.rb);
+    pc.n = (int)(P.ref_len ? P.ref_len[pair] : P.ref_off[pair + 1] - pc.fb);
+    pc.ti = pc.pj = 0;
+    return pc;
+}
+
+__device__ __forceinline__ uint64_t pair_run_base(const AlignParams& P, uint64_t pair) {
+    return P.run_base ? P.run_base[pair]
+                      : (P.read_off[pair] - P.read_off[0]) + (P.ref_off[pair] - P.ref_off[0]);
+}
+
+__device__ __forceinline__ PairState fresh_state(int s) {
+    return PairState{s, 0, 0, 0u, 0u, -1, 0u, kStateStarted};
+}
+
+// Advances one pair whose window state is `st` by at most `budget` windows
+// (0: to the end). All G lanes of the group call this together; lane 0 holds
+// the traceback-side fields (score, open run). When the pair ends (read
+// consumed, or a window without a solution within K) the result and the last
+// CIGAR run are written and st gets kStateDone.
 template <int G>
-__device__ void align_windows(const AlignParams& P, u64* lds, u64* spill, int lds_rows, int gl,
-                              int lane, uint64_t pair, const PairCursor& pc0, int s,
-                              genasm_result* res) {
-    PairCursor pc = pc0;
-    pc.ti = s;
-    pc.pj = 0;
-    const uint64_t run_base = (P.read_off[pair] - P.read_off[0]) + (P.ref_off[pair] - P.ref_off[0]);
+__device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds_rows, int gl,
+                             int lane, uint64_t pair, const PairCursor& pc, int s, PairState& st,
+                             uint32_t budget) {
+    const uint64_t run_base = pair_run_base(P, pair);
     const uint64_t run_limit = min(P.cigar_cap, run_base + (uint64_t)pc.m + (uint64_t)pc.n);
     uint32_t* runs = reinterpret_cast<uint32_t*>(lds + OFF_BROW);
-    RunState rs{-1, 0u, -1};
-    uint32_t written = 0;  // closed runs already in device memory
-    bool overflow = false;
-    int64_t score = 0;
-    uint32_t nwin = 0;
-    u64 st_wops = 0, st_cells = 0, st_table = 0, st_tb = 0, st_steps = 0;
+    RunState rs{st.cur_op, st.cur_len, st.cur_op >= 0 ? 0 : -1};
+    bool overflow = (st.flags & kStateOverflow) != 0;
     bool failed = false, internal = false;
+    u64 st_wops = 0, st_cells = 0, st_table = 0, st_tb = 0, st_steps = 0;
     // Every window commits at least one base, so a pair has at most m + n
     // windows; the cap keeps the loop finite even if that ever failed.
     const uint32_t max_windows = (uint32_t)pc.m + (uint32_t)pc.n + 1u;
-    while (pc.pj < pc.m) {
-        if (nwin >= max_windows) { failed = true; internal = true; break; }
-        const int mw = min(P.W, pc.m - pc.pj);
-        const int nw = min(P.W, pc.n - pc.ti);
+    uint32_t done_here = 0;
+    while (st.pj < pc.m && (budget == 0 || done_here < budget)) {
+        if (st.nwin >= max_windows) { failed = true; internal = true; break; }
+        const int mw = min(P.W, pc.m - st.pj);
+        const int nw = min(P.W, pc.n - st.ti);
         const int Lc = min(nw, P.L);
-        ++nwin;
-        load_window<G>(lds, gl, P.reads, pc.rb + pc.pj, mw, P.refs, pc.fb + pc.ti, nw);
+        ++st.nwin;
+        ++done_here;
+        load_window<G>(lds, gl, P.reads, pc.rb + st.pj, mw, P.refs, pc.fb + st.ti, nw);
         // rows that need computing; row mw always solves. With an empty text
         // window every column is the initial one and row mw is the first hit.
         const int Kr = nw > 0 ? min(P.K, mw - 1) : -1;
@@ -532,8 +550,7 @@ __device__ void align_windows(const AlignParams& P, u64* lds, u64* spill, int ld
             } else {
                 t = traceback(lds, spill, runs, rs, mw, nw, dstar, P.L, lds_rows, P.stride);
             }
-            internal |= t.internal;
-            score += t.edits;
+            st.score += t.edits;
             st_tb += t.reads;
             st_wops += (u64)nw * (2 + 6 * dstar);
             st_table += (u64)(dstar + 1) * (Lc + 1);
@@ -543,49 +560,73 @@ __device__ void align_windows(const AlignParams& P, u64* lds, u64* spill, int ld
         wave_sync();
         const u64 adv = lds[OFF_BC + 1];
         const u64 flags = lds[OFF_BC + 2];
-        const bool bad = (flags & 1ull) != 0;
-        if (bad) { failed = true; internal = true; break; }
+        if (flags & 1ull) { failed = true; internal = true; break; }
         // closed runs of this window (slots below the open run) go to device memory
         const int closed = (int)(flags >> 1);
-        overflow |= copy_runs<G>(runs, closed, P.cigar, run_base, run_limit, written, gl);
-        written += (uint32_t)closed;
+        overflow |= copy_runs<G>(runs, closed, P.cigar, run_base, run_limit, st.written, gl);
+        st.written += (uint32_t)closed;
         wave_sync();
-        pc.ti += (int)(adv >> 32);
-        pc.pj += (int)(unsigned)adv;
+        st.ti += (int)(adv >> 32);
+        st.pj += (int)(unsigned)adv;
     }
+    st.cur_op = rs.cur_op;
+    st.cur_len = rs.cur_len;
+    const bool finished = failed || st.pj >= pc.m;
     // the open run closes with the pair
-    if (!failed && gl == 0 && rs.nr >= 0) {
-        const uint64_t idx = run_base + written;
+    if (finished && !failed && gl == 0 && rs.cur_op >= 0) {
+        const uint64_t idx = run_base + st.written;
         if (idx < run_limit) P.cigar[idx] = (rs.cur_len << 2) | (uint32_t)rs.cur_op;
         else overflow = true;
     }
-    const bool any_overflow = group_ballot(overflow, G, lane) != 0;
-    if (gl == 0) {
+    if (group_ballot(overflow, G, lane) != 0) st.flags |= kStateOverflow;
+    if (failed) st.flags |= kStateFailed;
+    if (internal) st.flags |= kStateInternal;
+    if (finished) st.flags |= kStateDone;
+    if (gl == 0 && finished) {
+        const bool ovf = (st.flags & kStateOverflow) != 0;
         genasm_result r;
         if (failed) {
             r.edit_distance = -1;
             r.ref_begin = r.ref_end = 0;
             r.cigar_len = 0;
         } else {
-            r.edit_distance = (int32_t)score;
+            r.edit_distance = st.score;
             r.ref_begin = (uint32_t)s;
-            r.ref_end = (uint32_t)pc.ti;
-            r.cigar_len = any_overflow ? 0u : written + (rs.nr >= 0 ? 1u : 0u);
+            r.ref_end = (uint32_t)st.ti;
+            r.cigar_len = ovf ? 0u : st.written + (rs.cur_op >= 0 ? 1u : 0u);
         }
-        r.n_windows = nwin;
+        r.n_windows = st.nwin;
         r.cigar_off = run_base;
-        r.flags = (any_overflow && !failed ? GENASM_FLAG_CIGAR_OVERFLOW : 0u) |
+        r.flags = (ovf && !failed ? GENASM_FLAG_CIGAR_OVERFLOW : 0u) |
                   (internal ? GENASM_FLAG_INTERNAL : 0u);
-        *res = r;
-        if (P.stats) {
-            u64* st = P.stats + pair * kStatCount;
-            st[kStatWindowWordOps] = st_wops;
-            st[kStatWindowCells] = st_cells;
-            st[kStatTableWords] = st_table;
-            st[kStatTbReads] = st_tb;
-            st[kStatWindowLaneSteps] = st_steps;
-        }
+        P.out[pair] = r;
     }
+    if (gl == 0 && P.stats) {
+        u64* stp = P.stats + pair * kStatCount;
+        stp[kStatWindowWordOps] += st_wops;
+        stp[kStatWindowCells] += st_cells;
+        stp[kStatTableWords] += st_table;
+        stp[kStatTbReads] += st_tb;
+        stp[kStatWindowLaneSteps] += st_steps;
+    }
+}
+
+// Runs (or resumes, when window state persists in P.state) the windows of a
+// pair whose start search hit at column s.
+template <int G>
+__device__ void run_pair(const AlignParams& P, u64* lds, u64* spill, int lds_rows, int gl,
+                         int lane, uint64_t pair, int s) {
+    const PairCursor pc = pair_cursor(P, pair);
+    if (!P.state) {
+        PairState st = fresh_state(s);
+        advance_pair<G>(P, lds, spill, lds_rows, gl, lane, pair, pc, s, st, 0u);
+        return;
+    }
+    PairState st = P.state[pair];
+    if (st.flags & kStateDone) return;
+    if (!(st.flags & kStateStarted)) st = fresh_state(s);
+    advance_pair<G>(P, lds, spill, lds_rows, gl, lane, pair, pc, s, st, P.window_budget);
+    if (gl == 0) P.state[pair] = st;
 }
 
 // Start-search counters of one pair (lane 0); `row` is the hit row or, when
@@ -599,30 +640,23 @@ __device__ __forceinline__ void search_stats(const AlignParams& P, uint64_t pair
     st[kStatSearchLaneSteps] = (first_stage ? 0ull : st[kStatSearchLaneSteps]) + lane_steps;
 }
 
-__device__ __forceinline__ void write_simple_result(genasm_result* res, int32_t score,
-                                                    uint64_t run_base) {
+// Result of a pair that ends before any window: an empty read (score 0) or a
+// start search without a hit within K (score -1).
+__device__ __forceinline__ void finish_without_windows(const AlignParams& P, uint64_t pair,
+                                                       int32_t score) {
     genasm_result r;
     r.edit_distance = score;
     r.ref_begin = r.ref_end = 0;
     r.n_windows = 0;
-    r.cigar_off = run_base;
+    r.cigar_off = pair_run_base(P, pair);
     r.cigar_len = 0;
     r.flags = 0;
-    *res = r;
-}
-
-__device__ __forceinline__ PairCursor pair_cursor(const AlignParams& P, uint64_t pair) {
-    PairCursor pc;
-    pc.rb = P.read_off[pair];
-    pc.fb = P.ref_off[pair];
-    pc.m = (int)(P.read_off[pair + 1] - pc.rb);
-    pc.n = (int)(P.ref_off[pair + 1] - pc.fb);
-    pc.ti = pc.pj = 0;
-    return pc;
-}
-
-__device__ __forceinline__ uint64_t pair_run_base(const AlignParams& P, uint64_t pair) {
-    return (P.read_off[pair] - P.read_off[0]) + (P.ref_off[pair] - P.ref_off[0]);
+    P.out[pair] = r;
+    if (P.state) {
+        PairState st = fresh_state(0);
+        st.flags |= kStateDone | (score < 0 ? kStateFailed : 0u);
+        P.state[pair] = st;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -635,9 +669,8 @@ __global__ __launch_bounds__(64) void k_plain(AlignParams P) {
     const uint64_t pair = blockIdx.x;
     if (pair >= P.n_pairs) return;
     const PairCursor pc = pair_cursor(P, pair);
-    genasm_result* res = P.out + pair;
     if (pc.m == 0) {
-        if (lane == 0) write_simple_result(res, 0, pair_run_base(P, pair));
+        if (lane == 0) finish_without_windows(P, pair, 0);
         return;
     }
     const int m1 = min(P.W, pc.m);
@@ -650,11 +683,11 @@ __global__ __launch_bounds__(64) void k_plain(AlignParams P) {
     if (row < 0) {
         if (m1 <= P.K) { row = m1; col = 0; }   // row m1 hits in every column
         else {
-            if (lane == 0) write_simple_result(res, -1, pair_run_base(P, pair));
+            if (lane == 0) finish_without_windows(P, pair, -1);
             return;
         }
     }
-    align_windows<64>(P, smem, nullptr, 64, lane, lane, pair, pc, col, res);
+    run_pair<64>(P, smem, nullptr, 64, lane, lane, pair, col);
 }
 
 // ---------------------------------------------------------------------------
@@ -691,7 +724,7 @@ __global__ __launch_bounds__(64) void k_search(AlignParams P) {
         const PairCursor pc = pair_cursor(P, pair);
         if (pc.m == 0) {
             if (gl == 0) {
-                write_simple_result(P.out + pair, 0, pair_run_base(P, pair));
+                finish_without_windows(P, pair, 0);
                 P.search[pair] = SearchOut{kSearchDone, 0};
             }
             continue;
@@ -712,16 +745,18 @@ __global__ __launch_bounds__(64) void k_search(AlignParams P) {
                 P.search[pair] = SearchOut{kSearchPending, 0};
             } else if (row < 0 && m1 > P.K) {
                 // every needed row was computed without a hit: the pair fails
-                write_simple_result(P.out + pair, -1, pair_run_base(P, pair));
+                finish_without_windows(P, pair, -1);
                 P.search[pair] = SearchOut{kSearchFailed, 0};
             } else {
                 // a hit, or row m1 (every column hits there); route to a window queue
                 const int r = row >= 0 ? row : m1;
                 P.search[pair] = SearchOut{r, row >= 0 ? (uint32_t)col : 0u};
-                const bool hard = r >= P.hard_row;
-                uint32_t* len = P.counters + (hard ? kCounterHardLen : kCounterEasyLen);
-                const uint32_t pos = atomicAdd(len, 1u);
-                (hard ? P.hard_list : P.easy_list)[pos] = (uint32_t)pair;
+                if (P.route) {
+                    const bool hard = r >= P.hard_row;
+                    uint32_t* len = P.counters + (hard ? kCounterHardLen : kCounterEasyLen);
+                    const uint32_t pos = atomicAdd(len, 1u);
+                    (hard ? P.hard_list : P.easy_list)[pos] = (uint32_t)pair;
+                }
             }
         }
     }
@@ -745,8 +780,8 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
         if (item >= n_hard) break;
         const uint64_t pair = P.hard_list[item];
         const SearchOut so = P.search[pair];
-        align_windows<64>(P, smem, nullptr, 64, lane, lane, pair, pair_cursor(P, pair),
-                          (int)so.col, P.out + pair);
+        if (so.row < 0) continue;  // ended in the search (result already written)
+        run_pair<64>(P, smem, nullptr, 64, lane, lane, pair, (int)so.col);
     }
     const int gl = lane & 15;
     const int grp = lane >> 4;
@@ -759,8 +794,8 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
         if (item >= n_easy) break;
         const uint64_t pair = P.easy_list[item];
         const SearchOut so = P.search[pair];
-        align_windows<16>(P, lds, spill, P.lds_rows, gl, lane, pair, pair_cursor(P, pair),
-                          (int)so.col, P.out + pair);
+        if (so.row < 0) continue;  // ended in the search (result already written)
+        run_pair<16>(P, lds, spill, P.lds_rows, gl, lane, pair, (int)so.col);
     }
 }
 
@@ -803,6 +838,42 @@ __global__ void k_init_counters(uint32_t* counters, uint32_t stage0_len) {
 __global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// One block per range; see launch_scatter_bytes.
+__global__ void k_scatter_bytes(const uint8_t* src, const uint64_t* src_off, uint8_t* dst,
+                                const uint64_t* dst_off, const uint32_t* len, uint32_t n) {
+    const uint32_t k = blockIdx.x;
+    if (k >= n) return;
+    const uint8_t* a = src + src_off[k];
+    uint8_t* b = dst + dst_off[k];
+    for (uint32_t e = threadIdx.x; e < len[k]; e += blockDim.x) b[e] = a[e];
+}
+
+// Serving form: zeroes the window state of newly admitted pairs
+// (list[0..params[0])), so that the window kernel starts them afresh.
+__global__ void k_reset_states(PairState* state, const uint32_t* list, const uint32_t* params) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < params[0]) state[list[i]] = PairState{0, 0, 0, 0u, 0u, -1, 0u, 0u};
+}
+
+// Serving form: copies the CIGAR elements of the pairs list[0..n) to dst, one
+// block per listed pair, at dst_off[k] for the k-th listed pair.
+__global__ void k_gather_runs(const genasm_result* out, const uint32_t* list, uint32_t n,
+                              const uint64_t* dst_off, const uint32_t* cigar, uint32_t* dst) {
+    const uint32_t k = blockIdx.x;
+    if (k >= n) return;
+    const genasm_result r = out[list[k]];
+    for (uint32_t e = threadIdx.x; e < r.cigar_len; e += blockDim.x)
+        dst[dst_off[k] + e] = cigar[r.cigar_off + e];
+}
+
+// Serving form: params[0] = stage-0 search list length, params[1] = easy
+// window list length (written by a host copy before each launch).
+__global__ void k_init_counters_dev(uint32_t* counters, const uint32_t* params) {
+    const int i = threadIdx.x;
+    if (i < kCounterCount)
+        counters[i] = i == kCounterListBase ? params[0] : i == kCounterEasyLen ? params[1] : 0u;
 }
 
 // Sort keys for longest-read-first scheduling: key = ~read length (ascending
@@ -877,6 +948,34 @@ hipError_t launch_pack(const char* ascii, uint64_t n, uint8_t* packed, uint32_t*
 
 hipError_t launch_init_counters(uint32_t* counters, uint32_t stage0_len, hipStream_t s) {
     hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, s, counters, stage0_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_counters_dev(uint32_t* counters, const uint32_t* params, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_counters_dev, dim3(1), dim3(64), 0, s, counters, params);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_states(PairState* state, const uint32_t* list, const uint32_t* params,
+                               uint32_t max_n, hipStream_t s) {
+    if (max_n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reset_states, dim3((max_n + 255) / 256), dim3(256), 0, s, state, list, params);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_runs(const genasm_result* out, const uint32_t* list, uint32_t n,
+                              const uint64_t* dst_off, const uint32_t* cigar, uint32_t* dst,
+                              hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_runs, dim3(n), dim3(64), 0, s, out, list, n, dst_off, cigar, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_bytes(const uint8_t* src, const uint64_t* src_off, uint8_t* dst,
+                                const uint64_t* dst_off, const uint32_t* len, uint32_t n,
+                                hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_bytes, dim3(n), dim3(256), 0, s, src, src_off, dst, dst_off, len, n);
     return hipGetLastError();
 }
 

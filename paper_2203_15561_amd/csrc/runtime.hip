@@ -16,27 +16,6 @@
 
 using namespace genasm;
 
-struct genasm_ctx {
-    int device = -1;
-    hipStream_t stream = nullptr;
-    int num_cus = 0;
-    std::string err;
-    // device scratch arena
-    char* scratch = nullptr;
-    size_t scratch_cap = 0;
-    // host-form staging (device)
-    char* stage = nullptr;
-    size_t stage_cap = 0;
-    // profiling
-    bool profiling = false;
-    bool have_profile = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    char* stats = nullptr;
-    size_t stats_cap = 0;
-    uint64_t prof_pairs = 0;
-    int prof_form = 0;
-};
-
 namespace {
 
 #define CHECK_HIP(ctx, expr)                                                              \
@@ -339,6 +318,7 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     // Batched: scratch layout.
     p.lds_rows = L.lds_rows;
     p.hard_row = L.hard_row;
+    p.route = 1;
     const int win_lds = window_lds_bytes(p.lds_rows, p.stride);
     int per_cu = L.workers_per_cu;
     if (per_cu == 0) {
@@ -350,8 +330,9 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     const int spill_rows = 64 - L.lds_rows;
     size_t sort_tmp = 0;
     if (L.lpt_order) {
-        hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                                           (uint32_t*)nullptr, (uint32_t*)nullptr, (int)n_pairs, 0, 32, s);
+        (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, (uint32_t*)nullptr,
+                                                 (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                                 (uint32_t*)nullptr, (int)n_pairs, 0, 32, s);
     }
     auto carve = [&](Carver& c) {
         p.search = c.take<SearchOut>(n_pairs);

@@ -1,10 +1,12 @@
 // Host-side debugging driver: runs the unmodified GenASM kernels through the
-// CPU emulation in tests/emu/hip/hip_runtime.h (plain or batched pipeline).
+// CPU emulation in tests/emu/hip/hip_runtime.h (plain or batched pipeline, or
+// the device side of the serving loop).
 //
 //   emu_driver IN OUT
-// IN : int64 form, group_lanes, search_lanes, lds_rows, k, W, O, n_pairs,
-//      read_bytes, ref_bytes, hard_row; then the packed read bytes, the packed reference
-//      bytes, read_off[n+1], ref_off[n+1] (uint64).
+// IN : int64 form (0 plain, 1 batched, 2 serving loop), group_lanes, search_lanes,
+//      lds_rows, k, W, O, n_pairs, read_bytes, ref_bytes, hard_row, window_budget,
+//      slots, admit_per_iteration; then the packed read bytes, the packed
+//      reference bytes, read_off[n+1], ref_off[n+1] (uint64).
 // OUT: n genasm_result records, then (read bases + ref bases) CIGAR elements.
 #include "../../paper_2203_15561_amd/csrc/kernels.hip"
 
@@ -23,12 +25,13 @@ int main(int argc, char** argv) {
     if (argc != 3) { fprintf(stderr, "usage: emu_driver IN OUT\n"); return 2; }
     FILE* f = fopen(argv[1], "rb");
     if (!f) { perror("open IN"); return 2; }
-    int64_t h[11];
+    int64_t h[14];
     if (!read_all(f, h, sizeof h)) return 2;
     const int form = (int)h[0], G = (int)h[1], SG = (int)h[2], lds_rows = (int)h[3];
     const int k = (int)h[4], W = (int)h[5], O = (int)h[6];
     const uint64_t n = (uint64_t)h[7], nrb = (uint64_t)h[8], nfb = (uint64_t)h[9];
     const int hard_row = (int)h[10];
+    const uint32_t budget = (uint32_t)h[11], n_slots = (uint32_t)h[12], per_iter = (uint32_t)h[13];
     std::vector<uint8_t> reads(nrb + 8), refs(nfb + 8);
     std::vector<uint64_t> roff(n + 1), foff(n + 1);
     if (!read_all(f, reads.data(), nrb) || !read_all(f, refs.data(), nfb) ||
@@ -56,7 +59,101 @@ int main(int argc, char** argv) {
     p.out = out.data();
     p.cigar = cigar.data();
     p.cigar_cap = cap;
-    if (form == GENASM_FORM_PLAIN) {
+    if (form == 2) {
+        // Serving loop, device side: slots are reused; each iteration admits
+        // up to per_iter pairs into free slots, resets their state, advances the
+        // searched slots by at most `budget` windows and searches the new ones.
+        const int blocks = 2;
+        const uint64_t workers = (uint64_t)blocks * 4;
+        const int spill_rows = 64 - lds_rows;
+        std::vector<SearchOut> search(n_slots, SearchOut{kSearchPending, 0});
+        std::vector<uint32_t> counters(kCounterCount, 0), lists(2 * n_slots + 1);
+        std::vector<uint32_t> fresh_list(n_slots + 1), active(n_slots + 1), params(4, 0);
+        std::vector<unsigned long long> spill(std::max<uint64_t>(workers * spill_rows * p.stride, 1));
+        std::vector<uint64_t> s_roff(n_slots), s_foff(n_slots), s_base(n_slots);
+        std::vector<uint32_t> s_rlen(n_slots), s_flen(n_slots);
+        std::vector<PairState> state(n_slots);
+        std::vector<genasm_result> s_out(n_slots);
+        std::vector<int64_t> owner(n_slots, -1);
+        std::vector<uint32_t> free_slots, searched;
+        for (uint32_t q = n_slots; q-- > 0;) free_slots.push_back(q);
+        p.read_off = s_roff.data();
+        p.ref_off = s_foff.data();
+        p.read_len = s_rlen.data();
+        p.ref_len = s_flen.data();
+        p.run_base = s_base.data();
+        p.n_pairs = n_slots;
+        p.out = s_out.data();
+        p.search = search.data();
+        p.counters = counters.data();
+        p.spill = spill_rows > 0 ? spill.data() : nullptr;
+        p.lds_rows = lds_rows;
+        p.hard_row = 65;
+        p.route = 0;
+        p.state = state.data();
+        p.window_budget = budget;
+        p.easy_list = active.data();
+        p.hard_list = active.data();
+        uint64_t next = 0, finished_n = 0, iters = 0;
+        std::vector<uint32_t> fresh;
+        while (finished_n < n) {
+            if (++iters > 100000) { fprintf(stderr, "serving loop does not finish\n"); return 3; }
+            fresh.clear();
+            while (next < n && !free_slots.empty() && fresh.size() < per_iter) {
+                const uint32_t q = free_slots.back();
+                free_slots.pop_back();
+                s_roff[q] = roff[next];
+                s_rlen[q] = (uint32_t)(roff[next + 1] - roff[next]);
+                s_foff[q] = foff[next];
+                s_flen[q] = (uint32_t)(foff[next + 1] - foff[next]);
+                s_base[q] = (roff[next] - roff[0]) + (foff[next] - foff[0]);
+                owner[q] = (int64_t)next++;
+                fresh.push_back(q);
+            }
+            std::copy(fresh.begin(), fresh.end(), fresh_list.begin());
+            std::copy(searched.begin(), searched.end(), active.begin());
+            params[0] = (uint32_t)fresh.size();
+            params[1] = (uint32_t)searched.size();
+            launch_init_counters_dev(counters.data(), params.data(), nullptr);
+            launch_reset_states(state.data(), fresh_list.data(), params.data(), n_slots, nullptr);
+            emu::group_lanes = 16;
+            launch_windows(p, blocks, nullptr);
+            AlignParams S = p;
+            S.list_in = fresh_list.data();
+            S.list_out = lists.data();
+            S.list_slot = 0;
+            launch_search(S, 16, 1, blocks, nullptr);
+            S.list_in = lists.data();
+            S.list_out = lists.data() + n_slots;
+            S.list_slot = 1;
+            launch_search(S, 16, 2, blocks, nullptr);
+            S.list_in = lists.data() + n_slots;
+            S.list_out = lists.data();
+            S.list_slot = 2;
+            launch_search(S, 16, 4, blocks, nullptr);
+            std::vector<uint32_t> still;
+            auto settle = [&](uint32_t q) {
+                if (state[q].flags & kStateDone) {
+                    out[owner[q]] = s_out[q];
+                    owner[q] = -1;
+                    free_slots.push_back(q);
+                    ++finished_n;
+                } else {
+                    still.push_back(q);
+                }
+            };
+            for (uint32_t q : searched) settle(q);
+            for (uint32_t q : fresh) {
+                if (search[q].row == kSearchPending) {
+                    fprintf(stderr, "slot %u left pending by the search\n", q);
+                    return 3;
+                }
+                settle(q);
+            }
+            searched.swap(still);
+        }
+        fprintf(stderr, "emu: serving loop finished in %llu iterations\n", (unsigned long long)iters);
+    } else if (form == GENASM_FORM_PLAIN) {
         emu::group_lanes = 64;
         p.lds_rows = 64;
         launch_plain(p, nullptr);
@@ -79,6 +176,7 @@ int main(int argc, char** argv) {
         p.easy_list = easy.data();
         p.hard_list = hard.data();
         p.hard_row = G == 64 ? 0 : hard_row;
+        p.route = 1;
         p.lds_rows = lds_rows;
         launch_init_counters(p.counters, (uint32_t)n, nullptr);
         p.list_in = p.order;

@@ -36,6 +36,7 @@ struct dim3 {
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
 typedef struct ihipStream_t* hipStream_t;
+typedef struct ihipEvent_t* hipEvent_t;
 inline hipError_t hipGetLastError() { return hipSuccess; }
 
 template <class A, class B>
@@ -49,8 +50,8 @@ struct BlockState {
     int lanes;
     int group_lanes;
     std::vector<std::unique_ptr<std::barrier<>>> bars;
-    unsigned long long slot[64];
-    bool pred[64];
+    unsigned long long slot[256];
+    bool pred[256];
 };
 
 struct LaneId {
@@ -121,7 +122,7 @@ constexpr unsigned long long kCanary = 0xC0FFEE11DEADBEEFull;
 template <class K, class... Args>
 void launch(K kernel, dim3 grid, dim3 block, size_t lds_bytes, unsigned long long* lds,
             size_t lds_words, Args... args) {
-    if (block.x > 64 || lds_bytes > lds_words * 8) {
+    if (block.x > 256 || lds_bytes > lds_words * 8) {
         std::fprintf(stderr, "emu: launch shape not supported (block %u, lds %zu)\n", block.x, lds_bytes);
         std::abort();
     }

@@ -85,3 +85,25 @@ def test_long_read_prefixes_with_decoy(driver, hard_row):
     cut = gen.from_lists("long-prefix", [ps.read(i)[:1200] for i in range(2)],
                          [ps.ref(i)[:1300] for i in range(2)], 64)
     check(driver, cut, 1, hard_row)
+
+
+@pytest.mark.parametrize("budget", [1, 3])
+def test_serving_loop(driver, budget):
+    # the serving form's device side: 6 slots reused by 40 requests, three
+    # admitted per iteration, each resident pair advancing at most `budget`
+    # windows per iteration (open CIGAR runs carried across iterations)
+    pairs = gen.fuzz(5150 + budget, 34, max_len=260)
+    cases = [("", ""), ("", "ACGT"), ("ACGT", ""), ("T" * 65, ""), ("A" * 64, "C" * 64),
+             ("G" * 130, "G" * 90)]
+    reads = [p[0] for p in pairs] + [c[0] for c in cases]
+    refs = [p[1] for p in pairs] + [c[1] for c in cases]
+    for k, W, O in ((64, 64, 24), (5, 16, 8)):
+        ps = gen.from_lists("serve", reads, refs, k, W, O)
+        want = expected(ps)
+        res, cig = emu.run(driver, ps, emu.SERVE, 16, 16, 16, window_budget=budget, slots=6,
+                           admit_per_iteration=3)
+        assert (res["flags"] == 0).all()
+        got = [(int(r["edit_distance"]), c, int(r["ref_begin"]), int(r["ref_end"]),
+                int(r["n_windows"])) for r, c in zip(res, cig)]
+        bad = [i for i in range(ps.n_pairs) if want[i] != got[i]]
+        assert not bad, (k, W, O, bad[:5], want[bad[0]], got[bad[0]])
