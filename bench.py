@@ -148,6 +148,9 @@ def main():
     ap.add_argument("--workers-per-cu", type=int, default=0)
     ap.add_argument("--hard-row", type=int, default=0)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="after the timed region, run one plain device copy of this many MiB "
+                         "(reference kernel for scaling HBM byte counters)")
     ap.add_argument("--serving-requests", type=int, default=20000,
                     help="requests of the serving mix for the saturated run")
     ap.add_argument("--serving-load", type=float, default=0.5,
@@ -230,6 +233,17 @@ def main():
 
     res = out.cpu().numpy().view(ga.RESULT_DTYPE).reshape(-1)
     assert (res["flags"] == 0).all()
+
+    if args.copy_calibration_mb:
+        # one elementwise kernel that reads and writes exactly this many bytes
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.add(src, 1, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy calibration: read {nbytes} B, wrote {nbytes} B")
+        del src, dst
 
     # spot-check results against the oracle
     verified = 0

@@ -17,6 +17,9 @@ struct genasm_ctx {
     // device scratch arena
     char* scratch = nullptr;
     size_t scratch_cap = 0;
+    // bit planes of the current call's streams (device)
+    char* planes = nullptr;
+    size_t planes_cap = 0;
     // host-form staging (device)
     char* stage = nullptr;
     size_t stage_cap = 0;
@@ -63,6 +66,16 @@ struct AlignParams {
     const uint64_t* read_off;   // n_pairs + 1 base offsets
     const uint8_t* refs;        // 2-bit packed reference stream
     const uint64_t* ref_off;
+    // The same streams as bit planes (see launch_planes), read by the window
+    // kernels. Word w of a plane holds bit 0 (lo) or bit 1 (hi) of the codes of
+    // bases origin + 64w .. origin + 64w + 63, where origin is read_off[0]
+    // (ref_off[0]) rounded down to a multiple of 64 when planes_from_off0 is
+    // set, else 0.
+    const unsigned long long* read_lo;
+    const unsigned long long* read_hi;
+    const unsigned long long* ref_lo;
+    const unsigned long long* ref_hi;
+    int32_t planes_from_off0;
     uint64_t n_pairs;
     int32_t K;                  // min(k, W)
     int32_t W;
@@ -146,6 +159,22 @@ hipError_t launch_compact_cigar(const genasm_result* d_out, const uint64_t* dst_
 hipError_t launch_scatter_bytes(const uint8_t* src, const uint64_t* src_off, uint8_t* dst,
                                 const uint64_t* dst_off, const uint32_t* len, uint32_t n,
                                 hipStream_t s);
+
+// Bit planes of bases [b0, b0 + n_bases) of a 2-bit packed stream, where b0 =
+// *d_first (device memory; 0 if d_first is null): with origin = b0 rounded
+// down to a multiple of 64, lo[w] / hi[w] bit k is bit 0 / bit 1 of the code
+// of base origin + 64w + k (0 past b0 + n_bases). Writes plane_words(n_bases)
+// words per plane; the last words are padding that the window kernels may
+// read ahead into.
+inline uint64_t plane_words(uint64_t n_bases) { return (n_bases + 63 + 63) / 64 + 3; }
+hipError_t launch_planes(const uint8_t* packed, const uint64_t* d_first, uint64_t n_bases,
+                         unsigned long long* lo, unsigned long long* hi, hipStream_t s);
+// Serving: converts n uploaded ranges of packed bases (range k: len[k] bases
+// at byte src_off[k] of src) into the plane pool at word dst_word[k] (ranges
+// start on a 64-base boundary).
+hipError_t launch_scatter_planes(const uint8_t* src, const uint64_t* src_off, const uint32_t* len,
+                                 unsigned long long* lo, unsigned long long* hi,
+                                 const uint64_t* dst_word, uint32_t n, hipStream_t s);
 
 // Occupancy helpers.
 int plain_lds_bytes(int stride);

@@ -145,24 +145,62 @@ __device__ void build_pm(u64* lds, int gl, const uint8_t* reads, uint64_t rb, in
     wave_sync();
 }
 
-// Loads a window: pattern bases, text bases, PM and PMT (PM[T[i]] per column).
+// Shifts a two-word bit window: bits [s, s+64) of the 128-bit value (hi:lo).
+__device__ __forceinline__ u64 funnel64(u64 lo, u64 hi, int s) {
+    return s == 0 ? lo : (lo >> s) | (hi << (64 - s));
+}
+
+// Read-ahead cursor over the two bit planes of one sequence: words q, q+1, q+2
+// of each plane. A window needs the 64 bits starting at some bit of word q;
+// the next window starts at most 64 bases later, so it needs at most word
+// q+2, whose load was issued one window earlier.
+struct SeqCursor {
+    u64 lo0, lo1, lo2, hi0, hi1, hi2;
+    uint64_t q;
+};
+
+__device__ __forceinline__ void seq_open(SeqCursor& c, const u64* lo, const u64* hi, uint64_t bit) {
+    c.q = bit >> 6;
+    c.lo0 = lo[c.q]; c.lo1 = lo[c.q + 1]; c.lo2 = lo[c.q + 2];
+    c.hi0 = hi[c.q]; c.hi1 = hi[c.q + 1]; c.hi2 = hi[c.q + 2];
+}
+
+// Moves the cursor to the window starting at `bit` (at most one word on) and
+// returns that window's 64 bases as (lo, hi) planes: bit k = base bit + k.
+__device__ __forceinline__ void seq_window(SeqCursor& c, const u64* lo, const u64* hi,
+                                           uint64_t bit, u64& wlo, u64& whi) {
+    if ((bit >> 6) != c.q) {
+        c.q += 1;
+        c.lo0 = c.lo1; c.lo1 = c.lo2; c.lo2 = lo[c.q + 2];
+        c.hi0 = c.hi1; c.hi1 = c.hi2; c.hi2 = hi[c.q + 2];
+    }
+    const int s = (int)(bit & 63);
+    wlo = funnel64(c.lo0, c.lo1, s);
+    whi = funnel64(c.hi0, c.hi1, s);
+}
+
+// Pattern masks of a read window from its planes: bit p of PM[c] is 0 iff
+// P[mw-1-p] == c (bits p >= mw are 1).
+__device__ __forceinline__ void pm_from_planes(u64 pl, u64 ph, int mw, u64 pm[4]) {
+    const int sh = 64 - mw;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const u64 eq = ((c & 1) ? pl : ~pl) & ((c & 2) ? ph : ~ph);
+        pm[c] = ~(__builtin_bitreverse64(eq) >> sh);
+    }
+}
+
+// Writes PMT (PM[T[i]] for the window's columns, ~0 at nw..64) into LDS.
 template <int G>
-__device__ void load_window(u64* lds, int gl, const uint8_t* reads, uint64_t rb, int mw,
-                           const uint8_t* refs, uint64_t fb, int nw) {
-    uint8_t* tch = reinterpret_cast<uint8_t*>(lds + OFF_CH) + 64;
-    build_pm<G>(lds, gl, reads, rb, mw, true);
-    const u64 p0 = lds[OFF_PM + 0], p1 = lds[OFF_PM + 1], p2 = lds[OFF_PM + 2],
-              p3 = lds[OFF_PM + 3];
+__device__ __forceinline__ void store_pmt(u64* lds, int gl, const u64 pm[4], u64 tl, u64 th, int nw) {
     u64* pmt = lds + OFF_PMT;
 #pragma unroll
     for (int u = 0; u < 64 / G; ++u) {
         const int i = gl + u * G;
-        const int c = i < nw ? base_at(refs, fb + i) : 0;
-        tch[i] = (uint8_t)c;
-        pmt[i] = i < nw ? pick_pm(p0, p1, p2, p3, c) : ~0ull;
+        const int c = (int)((tl >> i) & 1ull) | ((int)((th >> i) & 1ull) << 1);
+        pmt[i] = i < nw ? pick_pm(pm[0], pm[1], pm[2], pm[3], c) : ~0ull;
     }
     if (gl == 0) pmt[64] = ~0ull;
-    wave_sync();
 }
 
 // ---------------------------------------------------------------------------
@@ -328,120 +366,98 @@ struct TbOut {
     bool internal;
 };
 
-// Reads stored R[row][col] for the traceback.
-__device__ __forceinline__ u64 read_r(const u64* lds, const u64* spill, int row, int col, int nw,
-                                      int mw, int lds_rows, int stride) {
-    if (row >= mw) return 0ull;                  // rows >= mw: every used bit is 0
-    if (col == nw) return init_word(row);        // the column past the text end
-    if (row < lds_rows) return lds[OFF_TAB + row * stride + 1 + col];
-    return load_coherent(spill + (size_t)(row - lds_rows) * stride + 1 + col);
-}
-
-// Run-length CIGAR under construction, held by lane 0 of a group. The runs of
-// the current window go to an LDS array (`runs`, the boundary-row area, free
-// during the traceback): slot nr holds the open run and is rewritten at every
-// step, and nr moves on when the op changes, so a step needs no branch. At the
-// end of each window the group copies the closed runs to device memory; the
-// open run is carried into the next window's slot 0, so runs merge across
-// window seams.
+// Run-length CIGAR under construction, kept with the same values in every lane
+// of a group. The runs of the current window go to an LDS array (`runs`, the
+// boundary-row area, free during the traceback), written by one lane: slot nr
+// holds the open run and is rewritten at every step, and nr moves on when the
+// op changes, so a step needs no branch. At the end of each window the group
+// copies the closed runs to device memory; the open run is carried into the
+// next window's slot 0, so runs merge across window seams.
 struct RunState {
     int cur_op;         // op of the open run, -1 before the pair's first op
     uint32_t cur_len;
     int nr;             // LDS slot of the open run, -1 before the pair's first op
 };
 
-__device__ __forceinline__ void run_push(uint32_t* runs, RunState& rs, int op, uint32_t count) {
+__device__ __forceinline__ void run_push(uint32_t* runs, RunState& rs, int op, uint32_t count,
+                                         bool writer) {
     const bool changed = op != rs.cur_op;
     rs.nr += changed ? 1 : 0;
     rs.cur_len = changed ? count : rs.cur_len + count;
     rs.cur_op = op;
-    runs[rs.nr] = (rs.cur_len << 2) | (uint32_t)op;
+    if (writer) runs[rs.nr] = (rs.cur_len << 2) | (uint32_t)op;
 }
 
 // Before a window's traceback: the open run moves to slot 0.
-__device__ __forceinline__ void run_window_start(uint32_t* runs, RunState& rs) {
+__device__ __forceinline__ void run_window_start(uint32_t* runs, RunState& rs, bool writer) {
     if (rs.nr >= 0) {
-        runs[0] = (rs.cur_len << 2) | (uint32_t)rs.cur_op;
+        if (writer) runs[0] = (rs.cur_len << 2) | (uint32_t)rs.cur_op;
         rs.nr = 0;
     }
 }
 
-// Traceback of one window from (i=0, p=mw-1, d=dstar) when every row it can
-// read, 0..min(d*, mw-1), is in LDS; lane 0 of the group only. Rows at or above
-// mw read as 0 (all their used bits are 0). Bit p of the four edge words is
-// tested directly: match (A << 1) | PM, substitution B << 1, insertion C << 1,
-// deletion B, with A = R[d][i+1], B = R[d-1][i+1], C = R[d-1][i]; the shifted
-// words give "p == 0 or bit p-1 is 0" in one test.
-__device__ TbOut traceback_lds(const u64* lds, uint32_t* runs, RunState& rs, int mw, int nw,
-                               int dstar, int L, int stride, int rows) {
-    const uint8_t* pch = reinterpret_cast<const uint8_t*>(lds + OFF_CH);
-    const uint8_t* tch = pch + 64;
-    const u64* tab = lds + OFF_TAB + 1;  // column c of a row sits in slot c + 1
-    const int top = min(mw, rows) - 1;
-    int i = 0, p = mw - 1, d = dstar;
-    TbOut o{0, 0, 0, 0u, false};
-    while (p >= 0 && i < L && mw - 1 - p < L) {
-        const int j = mw - 1 - p;
-        const int rb = max(d - 1, 0);
-        const u64 A0 = tab[min(d, top) * stride + i + 1];
-        const u64 B = tab[rb * stride + i + 1];
-        const u64 C = tab[rb * stride + i];
-        const u64 A = d < mw ? A0 : 0ull;  // d <= mw, so only row d can be past the window
-        const bool intext = i < nw;
-        const bool up = d >= 1;
-        const bool m_ok = intext && pch[j] == tch[i] && !(((A << 1) >> p) & 1ull);
-        const bool s_ok = up && intext && !(((B << 1) >> p) & 1ull);
-        const bool i_ok = up && !(((C << 1) >> p) & 1ull);
-        const bool d_ok = up && intext && !((B >> p) & 1ull);
-        const bool any = m_ok || s_ok || i_ok || d_ok;  // always: bit p of R[d][i] is 0
-        const int op = m_ok ? GENASM_OP_MATCH
-                     : s_ok ? GENASM_OP_MISMATCH : i_ok ? GENASM_OP_INS : GENASM_OP_DEL;
-        run_push(runs, rs, op, 1u);
-        o.reads += up ? 3u : 1u;
-        o.internal |= !any;
-        i += op != GENASM_OP_INS;
-        d -= op != GENASM_OP_MATCH;
-        p = any ? p - (op != GENASM_OP_DEL) : -1;
-    }
-    o.i_end = i;
-    o.j_end = mw - 1 - p;
-    o.edits = dstar - d;
-    return o;
-}
+__device__ __forceinline__ int ctz64(u64 x) { return x ? __builtin_ctzll(x) : 64; }
 
-// Traceback of one window from (i=0, p=mw-1, d=dstar); lane 0 of the group only.
-// General form: rows at or above `lds_rows` come from the device-memory spill.
-__device__ TbOut traceback(const u64* lds, const u64* spill, uint32_t* runs, RunState& rs, int mw,
-                           int nw, int dstar, int L, int lds_rows, int stride) {
-    const uint8_t* pch = reinterpret_cast<const uint8_t*>(lds + OFF_CH);
-    const uint8_t* tch = pch + 64;
-    int i = 0, p = mw - 1, d = dstar, j = 0;
+// Traceback of one window from (i=0, j=0, d=dstar) (j = read bases consumed,
+// bit p = mw-1-j), run by every lane of the group on the same values; `writer`
+// marks the one lane that writes run records.
+//
+// Edge order M, S, I, D. The current cell is valid at every step (bit p of
+// R[d][i] is 0), and then the match edge is valid exactly when i < nw and the
+// two bases are equal: R[d][i] bit p = 0 says the read suffix from j aligns to
+// a prefix of the text suffix from i within d edits, and when the first bases
+// agree the suffixes after them align within the same d edits (the usual
+// equal-first-character property of edit distance, which also holds with a free
+// text end). So a run of matches is the common prefix of the read and text
+// from (j, i), found from the bit planes with one XOR and a trailing-zero
+// count, and only the other three edges read the table: substitution and
+// deletion test R[d-1][i+1] (bit p-1 and bit p), insertion tests R[d-1][i]
+// (bit p-1), with "p == 0 or bit p-1 is 0" taken as bit p of the word
+// shifted left by one.
+__device__ TbOut traceback_planes(const u64* lds, const u64* spill, uint32_t* runs, RunState& rs,
+                                  bool writer, u64 pl, u64 ph, u64 tl, u64 th, int mw, int nw,
+                                  int dstar, int L, int stride, int lds_rows) {
+    const u64* tab = lds + OFF_TAB + 1;  // column c of a row sits in slot c + 1
+    const int jmax = min(mw, L);
+    int i = 0, j = 0, d = dstar;
     TbOut o{0, 0, 0, 0u, false};
-    while (p >= 0 && i < L && j < L) {
-        const u64 A = read_r(lds, spill, d, i + 1, nw, mw, lds_rows, stride);
-        const u64 B = d >= 1 ? read_r(lds, spill, d - 1, i + 1, nw, mw, lds_rows, stride) : ~0ull;
-        const u64 C = d >= 1 ? read_r(lds, spill, d - 1, i, nw, mw, lds_rows, stride) : ~0ull;
+    // every pass of the loop consumes a read or text base, or leaves it
+    for (int it = 0; it <= 2 * L; ++it) {
+        if (j >= jmax || i >= L) break;
+        const int delta = i - j;
+        const u64 mis = delta >= 0 ? (((pl ^ (tl >> delta)) | (ph ^ (th >> delta))) >> j)
+                                   : ((((pl >> -delta) ^ tl) | ((ph >> -delta) ^ th)) >> i);
+        const int k = min(ctz64(mis), min(jmax - j, min(L - i, nw - i)));
+        if (k > 0) {
+            run_push(runs, rs, GENASM_OP_MATCH, (uint32_t)k, writer);
+            i += k;
+            j += k;
+            if (j >= jmax || i >= L) break;
+        }
+        // bases differ, or the text window is used up: an edit
+        if (d < 1) { o.internal = true; break; }
+        const int r = d - 1, p = mw - 1 - j;
+        u64 B, C;
+        if (r < lds_rows) {
+            const u64* row = tab + r * stride;
+            C = row[i];
+            B = row[i + 1];
+        } else {
+            const u64* row = spill + (size_t)(r - lds_rows) * stride + 1;
+            C = load_coherent(row + i);
+            B = load_coherent(row + i + 1);
+        }
         const bool intext = i < nw;
-        const int pc = pch[j];
-        const int tc = tch[i < 64 ? i : 63];
-        const bool p0 = p == 0;
-        const int q = p0 ? 0 : p - 1;
-        const bool m_ok = intext && pc == tc && (p0 || !((A >> q) & 1ull));
-        const bool s_ok = d >= 1 && intext && (p0 || !((B >> q) & 1ull));
-        const bool i_ok = d >= 1 && (p0 || !((C >> q) & 1ull));
-        const bool d_ok = d >= 1 && intext && !((B >> p) & 1ull);
-        int op;
-        if (m_ok) op = GENASM_OP_MATCH;
-        else if (s_ok) op = GENASM_OP_MISMATCH;
-        else if (i_ok) op = GENASM_OP_INS;
-        else if (d_ok) op = GENASM_OP_DEL;
-        else { o.internal = true; break; }
-        run_push(runs, rs, op, 1u);
-        o.reads += d >= 1 ? 3u : 1u;
+        const bool s_ok = intext && !(((B << 1) >> p) & 1ull);
+        const bool i_ok = !(((C << 1) >> p) & 1ull);
+        const bool d_ok = intext && !((B >> p) & 1ull);
+        if (!(s_ok || i_ok || d_ok)) { o.internal = true; break; }
+        const int op = s_ok ? GENASM_OP_MISMATCH : i_ok ? GENASM_OP_INS : GENASM_OP_DEL;
+        run_push(runs, rs, op, 1u, writer);
+        o.reads += 2u;
         i += op != GENASM_OP_INS;
-        p -= op != GENASM_OP_DEL;
-        d -= op != GENASM_OP_MATCH;
-        j = mw - 1 - p;
+        j += op != GENASM_OP_DEL;
+        d -= 1;
     }
     o.i_end = i;
     o.j_end = j;
@@ -502,6 +518,14 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
     // windows; the cap keeps the loop finite even if that ever failed.
     const uint32_t max_windows = (uint32_t)pc.m + (uint32_t)pc.n + 1u;
     uint32_t done_here = 0;
+    const bool writer = gl == 0;
+    const uint64_t rorg = P.planes_from_off0 ? (P.read_off[0] & ~63ull) : 0;
+    const uint64_t forg = P.planes_from_off0 ? (P.ref_off[0] & ~63ull) : 0;
+    SeqCursor rc, fc;
+    if (st.pj < pc.m) {
+        seq_open(rc, P.read_lo, P.read_hi, pc.rb - rorg + st.pj);
+        seq_open(fc, P.ref_lo, P.ref_hi, pc.fb - forg + st.ti);
+    }
     while (st.pj < pc.m && (budget == 0 || done_here < budget)) {
         if (st.nwin >= max_windows) { failed = true; internal = true; break; }
         const int mw = min(P.W, pc.m - st.pj);
@@ -509,10 +533,18 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
         const int Lc = min(nw, P.L);
         ++st.nwin;
         ++done_here;
-        load_window<G>(lds, gl, P.reads, pc.rb + st.pj, mw, P.refs, pc.fb + st.ti, nw);
+        u64 pl, ph, tl, th;
+        seq_window(rc, P.read_lo, P.read_hi, pc.rb - rorg + st.pj, pl, ph);
+        seq_window(fc, P.ref_lo, P.ref_hi, pc.fb - forg + st.ti, tl, th);
         // rows that need computing; row mw always solves. With an empty text
         // window every column is the initial one and row mw is the first hit.
         const int Kr = nw > 0 ? min(P.K, mw - 1) : -1;
+        if (Kr >= 0) {
+            u64 pm[4];
+            pm_from_planes(pl, ph, mw, pm);
+            store_pmt<G>(lds, gl, pm, tl, th, nw);
+            wave_sync();
+        }
         int dstar = -1;
         st_cells += (u64)mw * nw;
         for (int c = 0; c * G <= Kr; ++c) {
@@ -537,43 +569,37 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
             if (mw <= P.K) dstar = mw;  // no row below mw solves: d* = mw
             else { failed = true; break; }
         }
-        if (gl == 0) {
-            TbOut t;
-            run_window_start(runs, rs);
-            if (nw == 0) {
-                // empty text window: every step of the traceback is an insertion
-                const int k = min(mw, P.L);
-                run_push(runs, rs, GENASM_OP_INS, (uint32_t)k);
-                t = TbOut{0, k, k, 0u, false};
-            } else if (min(dstar, mw - 1) < lds_rows) {
-                t = traceback_lds(lds, runs, rs, mw, nw, dstar, P.L, P.stride, lds_rows);
-            } else {
-                t = traceback(lds, spill, runs, rs, mw, nw, dstar, P.L, lds_rows, P.stride);
-            }
-            st.score += t.edits;
-            st_tb += t.reads;
-            st_wops += (u64)nw * (2 + 6 * dstar);
-            st_table += (u64)(dstar + 1) * (Lc + 1);
-            lds[OFF_BC + 1] = ((u64)(unsigned)t.i_end << 32) | (unsigned)t.j_end;
-            lds[OFF_BC + 2] = ((u64)(unsigned)max(rs.nr, 0) << 1) | (t.internal ? 1ull : 0ull);
+        // traceback, in every lane of the group on the same values
+        TbOut t;
+        run_window_start(runs, rs, writer);
+        if (nw == 0) {
+            // empty text window: every step of the traceback is an insertion
+            const int k = min(mw, P.L);
+            run_push(runs, rs, GENASM_OP_INS, (uint32_t)k, writer);
+            t = TbOut{0, k, k, 0u, false};
+        } else {
+            t = traceback_planes(lds, spill, runs, rs, writer, pl, ph, tl, th, mw, nw, dstar, P.L,
+                                 P.stride, lds_rows);
         }
-        wave_sync();
-        const u64 adv = lds[OFF_BC + 1];
-        const u64 flags = lds[OFF_BC + 2];
-        if (flags & 1ull) { failed = true; internal = true; break; }
+        st.score += t.edits;
+        st_tb += t.reads;
+        st_wops += (u64)nw * (2 + 6 * dstar);
+        st_table += (u64)(dstar + 1) * (Lc + 1);
+        if (t.internal) { failed = true; internal = true; break; }
+        wave_sync();  // run records written by the writer lane
         // closed runs of this window (slots below the open run) go to device memory
-        const int closed = (int)(flags >> 1);
+        const int closed = max(rs.nr, 0);
         overflow |= copy_runs<G>(runs, closed, P.cigar, run_base, run_limit, st.written, gl);
         st.written += (uint32_t)closed;
-        wave_sync();
-        st.ti += (int)(adv >> 32);
-        st.pj += (int)(unsigned)adv;
+        wave_sync();  // the next window's traceback rewrites the run slots
+        st.ti += t.i_end;
+        st.pj += t.j_end;
     }
     st.cur_op = rs.cur_op;
     st.cur_len = rs.cur_len;
     const bool finished = failed || st.pj >= pc.m;
     // the open run closes with the pair
-    if (finished && !failed && gl == 0 && rs.cur_op >= 0) {
+    if (finished && !failed && writer && rs.cur_op >= 0) {
         const uint64_t idx = run_base + st.written;
         if (idx < run_limit) P.cigar[idx] = (rs.cur_len << 2) | (uint32_t)rs.cur_op;
         else overflow = true;
@@ -840,6 +866,64 @@ __global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long
     if (i < n) p[i] = v;
 }
 
+// Bits 0, 2, 4, ... of x, packed into bits 0..15.
+__device__ __forceinline__ uint32_t even_bits(uint32_t x) {
+    x &= 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+    x = (x | (x >> 4)) & 0x00FF00FFu;
+    x = (x | (x >> 8)) & 0x0000FFFFu;
+    return x;
+}
+
+// Bases [64w, 64w+64) of a packed stream whose bytes below nbytes may be
+// read: four 16-base chunks, bytes at or past nbytes read as 0.
+__device__ __forceinline__ void plane_word(const uint8_t* packed, uint64_t nbytes, uint64_t w,
+                                           u64& lo, u64& hi) {
+    lo = 0;
+    hi = 0;
+    const uint64_t b0 = w * 16;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t b = b0 + 4 * k + u;
+            if (b < nbytes) x |= (uint32_t)packed[b] << (8 * u);
+        }
+        lo |= (u64)even_bits(x) << (16 * k);
+        hi |= (u64)even_bits(x >> 1) << (16 * k);
+    }
+}
+
+// One thread per plane word; see launch_planes.
+__global__ void k_planes(const uint8_t* packed, const uint64_t* d_first, uint64_t n_bases, u64* lo,
+                         u64* hi, uint64_t nwords) {
+    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nwords) return;
+    const uint64_t b0 = d_first ? d_first[0] : 0;
+    const uint64_t w0 = b0 >> 6;
+    u64 a, b;
+    plane_word(packed, (b0 + n_bases + 3) / 4, w0 + w, a, b);
+    lo[w] = a;
+    hi[w] = b;
+}
+
+// One block per uploaded range; see launch_scatter_planes.
+__global__ void k_scatter_planes(const uint8_t* src, const uint64_t* src_off, const uint32_t* len,
+                                 u64* lo, u64* hi, const uint64_t* dst_word, uint32_t n) {
+    const uint32_t k = blockIdx.x;
+    if (k >= n) return;
+    const uint64_t nbytes = ((uint64_t)len[k] + 3) / 4;
+    const uint64_t nw = ((uint64_t)len[k] + 63) / 64;
+    for (uint64_t w = threadIdx.x; w < nw; w += blockDim.x) {
+        u64 a, b;
+        plane_word(src + src_off[k], nbytes, w, a, b);
+        lo[dst_word[k] + w] = a;
+        hi[dst_word[k] + w] = b;
+    }
+}
+
 // One block per range; see launch_scatter_bytes.
 __global__ void k_scatter_bytes(const uint8_t* src, const uint64_t* src_off, uint8_t* dst,
                                 const uint64_t* dst_off, const uint32_t* len, uint32_t n) {
@@ -976,6 +1060,23 @@ hipError_t launch_scatter_bytes(const uint8_t* src, const uint64_t* src_off, uin
                                 hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_scatter_bytes, dim3(n), dim3(256), 0, s, src, src_off, dst, dst_off, len, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_planes(const uint8_t* packed, const uint64_t* d_first, uint64_t n_bases,
+                         unsigned long long* lo, unsigned long long* hi, hipStream_t s) {
+    const uint64_t nwords = plane_words(n_bases);
+    hipLaunchKernelGGL(k_planes, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, s, packed,
+                       d_first, n_bases, lo, hi, nwords);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_planes(const uint8_t* src, const uint64_t* src_off, const uint32_t* len,
+                                 unsigned long long* lo, unsigned long long* hi,
+                                 const uint64_t* dst_word, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_planes, dim3(n), dim3(256), 0, s, src, src_off, len, lo, hi,
+                       dst_word, n);
     return hipGetLastError();
 }
 

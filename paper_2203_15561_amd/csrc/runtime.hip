@@ -176,6 +176,7 @@ void genasm_destroy(genasm_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->planes) (void)hipFree(ctx->planes);
     if (ctx->stage) (void)hipFree(ctx->stage);
     if (ctx->stats) (void)hipFree(ctx->stats);
     for (hipEvent_t e : ctx->ev)
@@ -292,6 +293,19 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     p.cigar = d_cigar;
     p.cigar_cap = cigar_cap;
 
+    // bit planes of both streams (window kernels), in the context's plane buffer
+    {
+        const uint64_t rw = plane_words(total_read_bases), fw = plane_words(total_ref_bases);
+        rc = ensure(ctx, &ctx->planes, &ctx->planes_cap, (size_t)(2 * rw + 2 * fw) * 8);
+        if (rc) return rc;
+        unsigned long long* pw = reinterpret_cast<unsigned long long*>(ctx->planes);
+        p.read_lo = pw;
+        p.read_hi = pw + rw;
+        p.ref_lo = pw + 2 * rw;
+        p.ref_hi = pw + 2 * rw + fw;
+        p.planes_from_off0 = 1;
+    }
+
     if (ctx->profiling) {
         const size_t words = (size_t)n_pairs * kStatCount;
         rc = ensure(ctx, &ctx->stats, &ctx->stats_cap, words * 8);
@@ -308,6 +322,12 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     if (L.form == GENASM_FORM_PLAIN) {
         p.lds_rows = 64;
         CHECK_HIP(ctx, mark(0));
+        CHECK_HIP(ctx, launch_planes(d_reads2b, d_read_off, total_read_bases,
+                                     const_cast<unsigned long long*>(p.read_lo),
+                                     const_cast<unsigned long long*>(p.read_hi), s));
+        CHECK_HIP(ctx, launch_planes(d_refs2b, d_ref_off, total_ref_bases,
+                                     const_cast<unsigned long long*>(p.ref_lo),
+                                     const_cast<unsigned long long*>(p.ref_hi), s));
         CHECK_HIP(ctx, mark(1));
         CHECK_HIP(ctx, mark(2));
         CHECK_HIP(ctx, launch_plain(p, s));
@@ -356,6 +376,12 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     auto [lists, keys, vals, keys2, order, tmp] = carve(real);
 
     CHECK_HIP(ctx, mark(0));
+    CHECK_HIP(ctx, launch_planes(d_reads2b, d_read_off, total_read_bases,
+                                 const_cast<unsigned long long*>(p.read_lo),
+                                 const_cast<unsigned long long*>(p.read_hi), s));
+    CHECK_HIP(ctx, launch_planes(d_refs2b, d_ref_off, total_ref_bases,
+                                 const_cast<unsigned long long*>(p.ref_lo),
+                                 const_cast<unsigned long long*>(p.ref_hi), s));
     if (L.lpt_order) {
         CHECK_HIP(ctx, launch_lpt_keys(d_read_off, n_pairs, keys, vals, s));
         size_t t = sort_tmp;

@@ -87,7 +87,7 @@ class RangeAlloc {
     uint64_t used_ = 0;
 };
 
-constexpr uint64_t kBaseUnit = 16;  // pool allocations in bases: byte-aligned, 4-byte multiples
+constexpr uint64_t kBaseUnit = 64;  // pool allocations in bases: whole bit-plane words
 
 uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -133,7 +133,8 @@ struct genasm_server {
     hipGraphExec_t graph_exec = nullptr;
 
     // device
-    uint8_t* d_pool = nullptr;
+    uint8_t* d_pool = nullptr;                 // 2-bit packed bases (start search)
+    unsigned long long *d_plo = nullptr, *d_phi = nullptr;  // the same bases as bit planes (windows)
     uint32_t* d_cigar = nullptr;
     uint64_t *d_read_off = nullptr, *d_ref_off = nullptr, *d_run_base = nullptr;
     uint32_t *d_read_len = nullptr, *d_ref_len = nullptr;
@@ -144,8 +145,8 @@ struct genasm_server {
              *d_params = nullptr;
     unsigned long long* d_spill = nullptr;
     uint8_t* d_upload = nullptr;
-    uint64_t *d_up_src = nullptr, *d_up_dst = nullptr;
-    uint32_t* d_up_len = nullptr;
+    uint64_t *d_up_src = nullptr, *d_up_dst = nullptr, *d_up_word = nullptr;
+    uint32_t *d_up_len = nullptr, *d_up_bases = nullptr;
     uint32_t* d_gather_list = nullptr;
     uint64_t* d_gather_off = nullptr;
     uint32_t* d_gather = nullptr;
@@ -156,8 +157,8 @@ struct genasm_server {
     uint32_t *h_read_len = nullptr, *h_ref_len = nullptr;
     uint32_t *h_new = nullptr, *h_active = nullptr, *h_params = nullptr;
     uint8_t* h_upload = nullptr;
-    uint64_t *h_up_src = nullptr, *h_up_dst = nullptr;
-    uint32_t* h_up_len = nullptr;
+    uint64_t *h_up_src = nullptr, *h_up_dst = nullptr, *h_up_word = nullptr;
+    uint32_t *h_up_len = nullptr, *h_up_bases = nullptr;
     PairState* h_state = nullptr;
     genasm_result* h_out = nullptr;
     SearchOut* h_search = nullptr;
@@ -272,6 +273,8 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     srv->upload_cap = 1ull << 24;
     srv->gather_cap = 1ull << 22;
     D(srv->d_pool, pool_bytes + 16);
+    D(srv->d_plo, plane_words(cfg.pool_bases));
+    D(srv->d_phi, plane_words(cfg.pool_bases));
     D(srv->d_cigar, cfg.pool_bases);  // a pair's CIGAR needs at most m + n elements
     D(srv->d_read_off, NS); D(srv->d_ref_off, NS); D(srv->d_run_base, NS);
     D(srv->d_read_len, NS); D(srv->d_ref_len, NS);
@@ -281,12 +284,14 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     D(srv->d_spill, workers * (64 - lds_rows) * stride);
     D(srv->d_upload, srv->upload_cap);
     D(srv->d_up_src, 2 * (size_t)NS); D(srv->d_up_dst, 2 * (size_t)NS); D(srv->d_up_len, 2 * (size_t)NS);
+    D(srv->d_up_word, 2 * (size_t)NS); D(srv->d_up_bases, 2 * (size_t)NS);
     D(srv->d_gather_list, NS); D(srv->d_gather_off, NS); D(srv->d_gather, srv->gather_cap);
     H(srv->h_read_off, NS); H(srv->h_ref_off, NS); H(srv->h_run_base, NS);
     H(srv->h_read_len, NS); H(srv->h_ref_len, NS);
     H(srv->h_new, NS); H(srv->h_active, NS); H(srv->h_params, 4);
     H(srv->h_upload, srv->upload_cap);
     H(srv->h_up_src, 2 * (size_t)NS); H(srv->h_up_dst, 2 * (size_t)NS); H(srv->h_up_len, 2 * (size_t)NS);
+    H(srv->h_up_word, 2 * (size_t)NS); H(srv->h_up_bases, 2 * (size_t)NS);
     H(srv->h_state, NS); H(srv->h_out, NS); H(srv->h_search, NS);
     H(srv->h_gather_list, NS); H(srv->h_gather_off, NS); H(srv->h_gather, srv->gather_cap);
     ok = ok && hipStreamCreateWithFlags(&srv->s, hipStreamNonBlocking) == hipSuccess;
@@ -310,6 +315,11 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     AlignParams p{};
     p.reads = srv->d_pool;
     p.refs = srv->d_pool;
+    p.read_lo = srv->d_plo;
+    p.read_hi = srv->d_phi;
+    p.ref_lo = srv->d_plo;
+    p.ref_hi = srv->d_phi;
+    p.planes_from_off0 = 0;
     p.read_off = srv->d_read_off;
     p.ref_off = srv->d_ref_off;
     p.read_len = srv->d_read_len;
@@ -441,14 +451,14 @@ void genasm_server_destroy(genasm_server* srv) {
     for (auto& c : srv->done) genasm_completion_release(&c);
     if (srv->graph_exec) (void)hipGraphExecDestroy(srv->graph_exec);
     if (srv->graph) (void)hipGraphDestroy(srv->graph);
-    void* dev[] = {srv->d_pool, srv->d_cigar, srv->d_read_off, srv->d_ref_off, srv->d_run_base,
+    void* dev[] = {srv->d_pool, srv->d_plo, srv->d_phi, srv->d_up_word, srv->d_up_bases, srv->d_cigar, srv->d_read_off, srv->d_ref_off, srv->d_run_base,
                    srv->d_read_len, srv->d_ref_len, srv->d_out, srv->d_state, srv->d_search,
                    srv->d_counters, srv->d_lists, srv->d_new, srv->d_active, srv->d_params,
                    srv->d_spill, srv->d_upload, srv->d_up_src, srv->d_up_dst, srv->d_up_len,
                    srv->d_gather_list, srv->d_gather_off, srv->d_gather};
     for (void* p : dev)
         if (p) (void)hipFree(p);
-    void* host[] = {srv->h_read_off, srv->h_ref_off, srv->h_run_base, srv->h_read_len,
+    void* host[] = {srv->h_up_word, srv->h_up_bases, srv->h_read_off, srv->h_ref_off, srv->h_run_base, srv->h_read_len,
                     srv->h_ref_len, srv->h_new, srv->h_active, srv->h_params, srv->h_upload,
                     srv->h_up_src, srv->h_up_dst, srv->h_up_len, srv->h_state, srv->h_out,
                     srv->h_search, srv->h_gather_list, srv->h_gather_off, srv->h_gather};
@@ -515,13 +525,16 @@ int iterate(genasm_server* srv, std::vector<uint32_t>& fresh) {
         const Slot& sl = srv->slots[fresh[fresh.size() - admitted.size() + a]];
         const Request& r = admitted[a];
         const std::vector<uint8_t>* parts[2] = {&r.read2b, &r.ref2b};
-        const uint64_t dst[2] = {sl.rstart / 4, sl.fstart / 4};
+        const uint64_t dst[2] = {sl.rstart, sl.fstart};
+        const uint32_t nb[2] = {r.m, r.n};
         for (int q = 0; q < 2; ++q) {
             if (parts[q]->empty()) continue;
             std::memcpy(srv->h_upload + up, parts[q]->data(), parts[q]->size());
             srv->h_up_src[nr] = up;
-            srv->h_up_dst[nr] = dst[q];
+            srv->h_up_dst[nr] = dst[q] / 4;
             srv->h_up_len[nr] = (uint32_t)parts[q]->size();
+            srv->h_up_word[nr] = dst[q] / 64;
+            srv->h_up_bases[nr] = nb[q];
             up += parts[q]->size();
             ++nr;
         }
@@ -539,8 +552,12 @@ int iterate(genasm_server* srv, std::vector<uint32_t>& fresh) {
         SRV_HIP(srv, hipMemcpyAsync(srv->d_up_src, srv->h_up_src, nr * 8, hipMemcpyHostToDevice, s));
         SRV_HIP(srv, hipMemcpyAsync(srv->d_up_dst, srv->h_up_dst, nr * 8, hipMemcpyHostToDevice, s));
         SRV_HIP(srv, hipMemcpyAsync(srv->d_up_len, srv->h_up_len, nr * 4, hipMemcpyHostToDevice, s));
+        SRV_HIP(srv, hipMemcpyAsync(srv->d_up_word, srv->h_up_word, nr * 8, hipMemcpyHostToDevice, s));
+        SRV_HIP(srv, hipMemcpyAsync(srv->d_up_bases, srv->h_up_bases, nr * 4, hipMemcpyHostToDevice, s));
         SRV_HIP(srv, launch_scatter_bytes(srv->d_upload, srv->d_up_src, srv->d_pool, srv->d_up_dst,
                                           srv->d_up_len, nr, s));
+        SRV_HIP(srv, launch_scatter_planes(srv->d_upload, srv->d_up_src, srv->d_up_bases,
+                                           srv->d_plo, srv->d_phi, srv->d_up_word, nr, s));
     }
     if (n_new) {
         SRV_HIP(srv, hipMemcpyAsync(srv->d_read_off, srv->h_read_off, NS * 8, hipMemcpyHostToDevice, s));

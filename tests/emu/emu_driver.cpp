@@ -59,6 +59,21 @@ int main(int argc, char** argv) {
     p.out = out.data();
     p.cigar = cigar.data();
     p.cigar_cap = cap;
+    // bit planes of both streams: from base 0 for the serving loop (slot offsets
+    // are absolute), from the first offset otherwise, as the runtime does
+    const bool serve = form == 2;
+    const uint64_t rbases = serve ? roff[n] : roff[n] - roff[0];
+    const uint64_t fbases = serve ? foff[n] : foff[n] - foff[0];
+    std::vector<unsigned long long> rlo(plane_words(rbases)), rhi(plane_words(rbases));
+    std::vector<unsigned long long> flo(plane_words(fbases)), fhi(plane_words(fbases));
+    emu::group_lanes = 64;
+    launch_planes(reads.data(), serve ? nullptr : roff.data(), rbases, rlo.data(), rhi.data(), nullptr);
+    launch_planes(refs.data(), serve ? nullptr : foff.data(), fbases, flo.data(), fhi.data(), nullptr);
+    p.read_lo = rlo.data();
+    p.read_hi = rhi.data();
+    p.ref_lo = flo.data();
+    p.ref_hi = fhi.data();
+    p.planes_from_off0 = serve ? 0 : 1;
     if (form == 2) {
         // Serving loop, device side: slots are reused; each iteration admits
         // up to per_iter pairs into free slots, resets their state, advances the

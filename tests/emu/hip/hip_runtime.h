@@ -161,6 +161,14 @@ void launch(K kernel, dim3 grid, dim3 block, size_t lds_bytes, unsigned long lon
 #define blockDim (emu::block_dim())
 #define gridDim (emu::grid_dim())
 
+namespace emu {
+inline unsigned long long bitreverse64(unsigned long long x) {
+    unsigned long long r = 0;
+    for (int b = 0; b < 64; ++b) r |= ((x >> b) & 1ull) << (63 - b);
+    return r;
+}
+}  // namespace emu
+#define __builtin_bitreverse64 emu::bitreverse64
 #define __builtin_amdgcn_update_dpp emu::update_dpp
 #define __builtin_amdgcn_s_waitcnt(x) emu::group_barrier()
 #define __builtin_amdgcn_wave_barrier() emu::group_barrier()
