@@ -46,9 +46,9 @@ def rle(ops: str) -> str:
 
 def serving_leg(ga, gen, ctx, args):
     """Serving form on the request mix: a saturated run (every request queued
-    at once) gives the sustainable rate; an open-loop run with Poisson arrivals
-    at a fraction of it gives latency percentiles, measured from each request's
-    scheduled arrival to its completion."""
+    at once) gives the sustainable rate; open-loop runs with Poisson arrivals
+    at a sweep of rates below it give latency percentiles, measured from each
+    request's scheduled arrival to its completion."""
     def requests(n, start):
         ps = gen.make("serving", n, start=start)
         asc = [(ga.capi._ascii(ps.read(i)), ga.capi._ascii(ps.ref(i))) for i in range(n)]
@@ -65,6 +65,39 @@ def serving_leg(ga, gen, ctx, args):
             if time.time() > t_log:
                 log(f"serving: {len(got)} of {n} requests completed")
                 t_log = time.time() + 10
+
+    def open_loop(srv, rate, start):
+        n_open = max(200, int(rate * args.serving_seconds))
+        ps2, asc2 = requests(n_open, start)
+        rng = np.random.default_rng(2203 + start)
+        gaps = rng.exponential(1.0 / rate, n_open)
+        got = {}
+        t_start = ga.now_ns() + 1_000_000
+        sched = t_start + np.cumsum(gaps * 1e9).astype(np.int64)
+        i = 0
+        while i < n_open:
+            now = ga.now_ns()
+            while i < n_open and sched[i] <= now:
+                while srv.submit(asc2[i][0], asc2[i][1], i) == ga.capi.E_BUSY:
+                    time.sleep(0.0005)
+                i += 1
+            for c in srv.poll(timeout_ms=0):
+                got[c["tag"]] = c
+            if i < n_open:
+                wait = (sched[i] - ga.now_ns()) / 1e9
+                if wait > 0.0002:
+                    time.sleep(min(wait, 0.002))
+        drain(srv, n_open, got)
+        assert all(c["flags"] == 0 for c in got.values())
+        lat = np.array([(got[t]["done_ns"] - sched[t]) / 1e6 for t in range(n_open)])
+        short = np.array([len(ps2.read(t)) <= 1000 for t in range(n_open)])
+        t_last = max(c["done_ns"] for c in got.values())
+        pct = lambda a, q: float(np.percentile(a, q)) if len(a) else None
+        return {"arrival_rate_per_s": rate, "requests": n_open,
+                "completed_per_s": n_open / ((t_last - t_start) / 1e9),
+                "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": float(lat.mean()),
+                "short_p50_ms": pct(lat[short], 50), "short_p99_ms": pct(lat[short], 99),
+                "long_p50_ms": pct(lat[~short], 50), "long_p99_ms": pct(lat[~short], 99)}
 
     ps, asc = requests(args.serving_requests, 0)
     out = {"mix": gen.DESCRIPTIONS["serving"], "k": ps.k, "W": ps.W, "O": ps.O}
@@ -91,43 +124,15 @@ def serving_leg(ga, gen, ctx, args):
                             "device_ms_per_iteration": (st1["device_ms"] - st0["device_ms"]) / max(iters, 1)}
         log(f"serving saturated: {sat:.0f} req/s over {len(asc)} requests, {iters} iterations")
 
-        rate = args.serving_load * sat
-        n_open = max(100, int(rate * args.serving_seconds))
-        ps2, asc2 = requests(n_open, args.serving_requests)
-        rng = np.random.default_rng(2203)
-        gaps = rng.exponential(1.0 / rate, n_open)
-        got = {}
-        t_start = ga.now_ns() + 1_000_000
-        sched = t_start + np.cumsum(gaps * 1e9).astype(np.int64)
-        i = 0
-        while i < n_open:
-            now = ga.now_ns()
-            while i < n_open and sched[i] <= now:
-                while srv.submit(asc2[i][0], asc2[i][1], i) == ga.capi.E_BUSY:
-                    time.sleep(0.0005)
-                i += 1
-            for c in srv.poll(timeout_ms=0):
-                got[c["tag"]] = c
-            if i < n_open:
-                wait = (sched[i] - ga.now_ns()) / 1e9
-                if wait > 0.0002:
-                    time.sleep(min(wait, 0.002))
-        drain(srv, n_open, got)
-        lat = np.array([(got[t]["done_ns"] - sched[t]) / 1e6 for t in range(n_open)])
-        short = np.array([len(ps2.read(t)) <= 1000 for t in range(n_open)])
-        t_last = max(c["done_ns"] for c in got.values())
-        out["open_loop"] = {
-            "arrival_rate_per_s": rate, "requests": n_open,
-            "completed_per_s": n_open / ((t_last - t_start) / 1e9),
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()),
-            "short_p50_ms": float(np.percentile(lat[short], 50)) if short.any() else None,
-            "short_p99_ms": float(np.percentile(lat[short], 99)) if short.any() else None,
-            "long_p50_ms": float(np.percentile(lat[~short], 50)) if (~short).any() else None,
-            "long_p99_ms": float(np.percentile(lat[~short], 99)) if (~short).any() else None,
-        }
-        log(f"serving open loop at {rate:.0f} req/s: p50 {out['open_loop']['p50_ms']:.2f} ms, "
-            f"p99 {out['open_loop']['p99_ms']:.2f} ms")
+        rates = [float(x) for x in args.serving_rates.split(",") if x.strip()]
+        rates = sorted({r for r in rates if r < sat} | {args.serving_load * sat})
+        out["open_loop"] = []
+        for k_rate, rate in enumerate(rates):
+            out["open_loop"].append(open_loop(srv, rate, args.serving_requests + 100_000 * k_rate))
+            o = out["open_loop"][-1]
+            log(f"serving open loop at {rate:.0f} req/s: p50 {o['p50_ms']:.2f} ms, "
+                f"p99 {o['p99_ms']:.2f} ms (short p50 {o['short_p50_ms']:.2f} / p99 "
+                f"{o['short_p99_ms']:.2f} ms)")
     return out
 
 
@@ -140,13 +145,14 @@ def main():
     ap.add_argument("--pairs", type=int, default=None, help="pairs (default: the full workload)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=4000,
+    ap.add_argument("--cpu-sample", type=int, default=20000,
                     help="pairs of the workload the CPU oracle aligns for the baseline")
     ap.add_argument("--verify", type=int, default=32, help="pairs checked against the oracle")
     ap.add_argument("--group-lanes", type=int, default=0)
     ap.add_argument("--lds-rows", type=int, default=0)
     ap.add_argument("--workers-per-cu", type=int, default=0)
     ap.add_argument("--hard-row", type=int, default=0)
+    ap.add_argument("--hard-lanes", type=int, default=0)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB "
@@ -155,8 +161,12 @@ def main():
                     help="requests of the serving mix for the saturated run")
     ap.add_argument("--serving-load", type=float, default=0.5,
                     help="open-loop arrival rate as a fraction of the saturated rate")
-    ap.add_argument("--serving-seconds", type=float, default=4.0,
-                    help="length of the open-loop arrival schedule")
+    ap.add_argument("--serving-seconds", type=float, default=3.0,
+                    help="length of each open-loop arrival schedule")
+    ap.add_argument("--serving-rates", default="1000,3000,10000",
+                    help="open-loop arrival rates (req/s) below the saturated rate, comma-separated")
+    ap.add_argument("--no-graph", action="store_true", help="skip timing the graph-captured step")
+    ap.add_argument("--no-end-to-end", action="store_true", help="skip the host-memory form timing")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -195,6 +205,8 @@ def main():
         kw["workers_per_cu"] = args.workers_per_cu
     if args.hard_row:
         kw["hard_row"] = args.hard_row
+    if args.hard_lanes:
+        kw["hard_lanes"] = args.hard_lanes
     batched = ga.make_launch(ga.FORM_BATCHED, **kw)
     plain = ga.make_launch(ga.FORM_PLAIN)
 
@@ -281,7 +293,8 @@ def main():
         "config": {"workload": f"{args.workload}: {gen.DESCRIPTIONS[args.workload]}",
                    "pairs": ps.n_pairs, "k": ps.k, "W": ps.W, "O": ps.O, "form": "batched",
                    "group_lanes": batched.group_lanes, "lds_rows": batched.lds_rows,
-                   "workers_per_cu": batched.workers_per_cu, "hard_row": batched.hard_row},
+                   "workers_per_cu": batched.workers_per_cu, "hard_row": batched.hard_row,
+                   "hard_lanes": batched.hard_lanes},
         "gcups": cells / (ms_step / 1e3) / 1e9,
         "window_kernel_ms": float(np.mean(win_ms)),
         "search_ms": float(np.mean(search_ms)),
@@ -307,19 +320,76 @@ def main():
                          "gcups": cells / (pm / 1e3) / 1e9}
         log(f"plain: {pm:.2f} ms/step")
 
+    if not args.no_graph:
+        # the same step captured once in a HIP graph (through torch's stream
+        # capture) and replayed; a context of its own keeps the captured scratch
+        gctx = ga.Context(0)
+        gs = torch.cuda.Stream()
+        gs.wait_stream(torch.cuda.current_stream())
+
+        def gstep():
+            gctx.pack_dev(reads_ascii, reads2b, bad)
+            gctx.pack_dev(refs_ascii, refs2b, bad)
+            gctx.align_dev(reads2b, roff, refs2b, foff, ps.k, ps.W, ps.O, launch=batched, out=out,
+                           cigar=cigar, total_read_bases=nr, total_ref_bases=nf, max_ref_len=max_ref)
+
+        with torch.cuda.stream(gs):
+            gstep()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=gs):
+            gstep()
+        graph.replay()
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record()
+        for _ in range(args.steps):
+            graph.replay()
+        g1.record()
+        torch.cuda.synchronize()
+        gms = g0.elapsed_time(g1) / args.steps
+        res_g = out.cpu().numpy().view(ga.RESULT_DTYPE).reshape(-1)
+        assert (res_g["edit_distance"] == res["edit_distance"]).all()
+        line["graph"] = {"alignments_per_s": ps.n_pairs / (gms / 1e3), "ms_per_step": gms}
+        log(f"graph replay: {gms:.2f} ms/step")
+        del graph
+        gctx.close()
+
+    if not args.no_end_to_end:
+        # host memory in and out: ASCII upload, packing, the whole path, CIGAR text back
+        r_ascii, f_ascii = gen.to_ascii(ps.reads), gen.to_ascii(ps.refs)
+        ctx.align_buffers(r_ascii, ps.read_off, f_ascii, ps.ref_off, ps.k, ps.W, ps.O, batched)
+        t0 = time.perf_counter()
+        res_h, _ = ctx.align_buffers(r_ascii, ps.read_off, f_ascii, ps.ref_off, ps.k, ps.W, ps.O,
+                                     batched)
+        e2e = time.perf_counter() - t0
+        assert (res_h["edit_distance"] == res["edit_distance"]).all()
+        line["end_to_end"] = {"alignments_per_s": ps.n_pairs / e2e, "seconds": e2e,
+                              "what": "host ASCII in, CIGAR text out (PCIe and host gather included)"}
+        log(f"end to end (host form): {e2e * 1e3:.1f} ms")
+
     if not args.no_serving:
         line["serving"] = serving_leg(ga, gen, ctx, args)
 
     if not args.no_cpu_baseline:
         import oracle
         sample = min(args.cpu_sample, ps.n_pairs)
-        sub = ps.subset(np.arange(sample))
+        sub = ps if sample == ps.n_pairs else ps.subset(np.arange(sample))
         _, _, secs, used = oracle.batch(sub)
-        line["cpu_baseline"] = {"value": sample / secs, "unit": "alignments/s", "cores": used,
-                                "kind": "oracle",
-                                "sample": f"first {sample} pairs of {args.workload} (same mix), "
-                                          f"improved form, {used} threads, {secs:.2f} s wall"}
-        log(f"cpu oracle: {sample / secs:.1f} alignments/s on {used} threads")
+        one = ps.subset(np.arange(min(500, ps.n_pairs)))
+        _, _, secs1, _ = oracle.batch(one, nthreads=1)
+        unc = ps.subset(np.arange(min(300, ps.n_pairs)))
+        _, _, secs_u, used_u = oracle.batch(unc, "uncompressed")
+        line["cpu_baseline"] = {
+            "value": sample / secs, "unit": "alignments/s", "cores": used, "kind": "oracle",
+            "sample": f"first {sample} pairs of {args.workload} (same mix), improved form, "
+                      f"{used} threads, {secs:.2f} s wall",
+            "per_core": {"alignments_per_s": one.n_pairs / secs1, "pairs": one.n_pairs},
+            "uncompressed": {"alignments_per_s": unc.n_pairs / secs_u, "pairs": unc.n_pairs,
+                             "cores": used_u}}
+        log(f"cpu oracle: {sample / secs:.1f} alignments/s on {used} threads; "
+            f"{one.n_pairs / secs1:.1f} on 1 thread; uncompressed {unc.n_pairs / secs_u:.1f} "
+            f"on {used_u} threads")
 
     ctx.close()
     print(json.dumps(line), flush=True)

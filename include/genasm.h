@@ -92,9 +92,12 @@ typedef struct {
                                 as LDS allows */
     int32_t lpt_order;       /* batched: 1 = longest reads first, 0 = input order; -1 = default */
     int32_t hard_row;        /* batched: pairs whose start search needs this many edit rows or
-                                more run one pair per wavefront with the whole 64-row table in
-                                LDS; 0 = default (65: never), 16 suits decoy-rich batches */
-    int32_t reserved;
+                                more (decoy-like pairs, whose windows cost several DC passes)
+                                go to a separate queue that the window workers drain first;
+                                0 = default (16); 65 = no separate queue */
+    int32_t hard_lanes;      /* batched: lanes per pair for that queue: 16 (the ordinary
+                                groups, table rows past lds_rows spilled) or 64 (one pair per
+                                wavefront, the whole 64-row table in LDS); 0 = default (16) */
 } genasm_launch;
 
 typedef struct genasm_ctx genasm_ctx;
@@ -221,6 +224,10 @@ typedef struct {
     uint64_t tb_reads;         /* DP words read by tracebacks */
     uint64_t window_lane_steps;/* lane-steps issued by DC passes, speculative rows included */
     uint64_t search_lane_steps;/* lane-cell-steps issued by the start search */
+    uint64_t windows;          /* windows processed */
+    uint64_t dc_cycles;        /* shader-clock cycles in DC passes (window setup included), summed over pairs */
+    uint64_t tb_cycles;        /* shader-clock cycles in tracebacks and CIGAR stores, summed over pairs */
+    uint64_t pair_cycles;      /* shader-clock cycles from a pair's first to last window, summed */
 } genasm_profile;
 
 int genasm_profile_enable(genasm_ctx* ctx, int on);

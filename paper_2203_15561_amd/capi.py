@@ -59,7 +59,7 @@ class Launch(ctypes.Structure):
         ("workers_per_cu", ctypes.c_int32),
         ("lpt_order", ctypes.c_int32),
         ("hard_row", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("hard_lanes", ctypes.c_int32),
     ]
 
 
@@ -78,6 +78,10 @@ class Profile(ctypes.Structure):
         ("tb_reads", ctypes.c_uint64),
         ("window_lane_steps", ctypes.c_uint64),
         ("search_lane_steps", ctypes.c_uint64),
+        ("windows", ctypes.c_uint64),
+        ("dc_cycles", ctypes.c_uint64),
+        ("tb_cycles", ctypes.c_uint64),
+        ("pair_cycles", ctypes.c_uint64),
     ]
 
     def as_dict(self):
@@ -310,25 +314,29 @@ class Context:
         """Host-memory form. Returns (results structured array, list of CIGAR strings)."""
         r, roff = _concat(reads)
         f, foff = _concat(refs)
+        out, raw = self.align_buffers(r, roff, f, foff, k, W, O, launch)
+        cig = [raw[int(o):int(o) + int(L)].decode() for o, L in zip(out["cigar_off"], out["cigar_len"])]
+        return out, cig
+
+    def align_buffers(self, r: bytes, roff, f: bytes, foff, k: int, W: int = 64, O: int = 24,
+                      launch: Launch | None = None):
+        """Host-memory form on concatenated ASCII streams and uint64 offsets.
+        Returns (results structured array, CIGAR text buffer as bytes)."""
+        roff = np.ascontiguousarray(roff, dtype=np.uint64)
+        foff = np.ascontiguousarray(foff, dtype=np.uint64)
         n = len(roff) - 1
         out = np.zeros(n, dtype=RESULT_DTYPE)
         need = ctypes.c_uint64(0)
-        cap = 4 * (len(r) + len(f)) + 16
-        buf = ctypes.create_string_buffer(cap)
+        # a run of length L takes at most L + 1 <= 2L characters, and a pair has
+        # at most m + n ops: 2 (m + n) characters always suffice
+        cap = 2 * (len(r) + len(f)) + 16
+        buf = np.empty(cap, dtype=np.uint8)
         rc = lib().genasm_batch_align(self._ctx, r, roff.ctypes.data_as(_u64p), f,
                                       foff.ctypes.data_as(_u64p), n, k, W, O, out.ctypes.data,
-                                      buf, cap, ctypes.byref(need),
+                                      buf.ctypes.data, cap, ctypes.byref(need),
                                       ctypes.byref(launch) if launch is not None else None)
-        if rc == E_NOSPACE:
-            buf = ctypes.create_string_buffer(int(need.value))
-            rc = lib().genasm_batch_align(self._ctx, r, roff.ctypes.data_as(_u64p), f,
-                                          foff.ctypes.data_as(_u64p), n, k, W, O,
-                                          out.ctypes.data, buf, need.value, ctypes.byref(need),
-                                          ctypes.byref(launch) if launch is not None else None)
         self._check(rc, "genasm_batch_align")
-        raw = buf.raw
-        cig = [raw[int(o):int(o) + int(L)].decode() for o, L in zip(out["cigar_off"], out["cigar_len"])]
-        return out, cig
+        return out, buf[:need.value].tobytes()
 
     def align_dev(self, reads2b, read_off, refs2b, ref_off, k: int, W: int = 64, O: int = 24,
                   launch: Launch | None = None, out=None, cigar=None, stream=None,

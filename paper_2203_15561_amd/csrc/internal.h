@@ -96,6 +96,7 @@ struct AlignParams {
     uint32_t* easy_list;        // pairs for the 16-lane window groups (filled by the search)
     uint32_t* hard_list;        // pairs for whole-wavefront windows (start row >= hard_row)
     int32_t hard_row;
+    int32_t hard_lanes;         // 16: the hard list is drained first by 16-lane groups; 64: by whole wavefronts
     int32_t route;              // search: append finished pairs to the window lists
     // Optional per-pair layout (serving: sequences sit anywhere in a device pool).
     const uint32_t* read_len;   // if set, pair i's read is [read_off[i], read_off[i] + read_len[i])
@@ -114,7 +115,11 @@ constexpr int kStatTableWords = 4;      // sum over windows of (d* + 1) * (min(n
 constexpr int kStatTbReads = 5;         // table words read by traceback
 constexpr int kStatWindowLaneSteps = 6; // lane-steps issued by DC passes (speculative rows included)
 constexpr int kStatSearchLaneSteps = 7; // lane-steps issued by the start search (all stages)
-constexpr int kStatCount = 8;
+constexpr int kStatWindows = 8;         // windows processed
+constexpr int kStatDcCycles = 9;        // shader-clock cycles: window setup and DC passes
+constexpr int kStatTbCycles = 10;       // shader-clock cycles: traceback and run stores
+constexpr int kStatPairCycles = 11;     // shader-clock cycles of the pair's window loop
+constexpr int kStatCount = 12;
 
 // counters[] layout: queue heads and list lengths for the batched pipeline.
 constexpr int kCounterListBase = 2;  // search stage s: counters[2 + 2s] = list length, [3 + 2s] = head
@@ -148,8 +153,11 @@ hipError_t launch_gather_runs(const genasm_result* out, const uint32_t* list, ui
                               const uint64_t* dst_off, const uint32_t* cigar, uint32_t* dst,
                               hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
-hipError_t launch_lpt_keys(const uint64_t* read_off, uint64_t n_pairs, uint32_t* keys,
-                           uint32_t* vals, hipStream_t s);
+// Longest-read-first pair order (approximate: reads are bucketed by length)
+// into order[0..n_pairs); hist is kLptBuckets words of scratch.
+constexpr int kLptBuckets = 336;
+hipError_t launch_lpt_order(const uint64_t* read_off, uint64_t n_pairs, uint32_t* hist,
+                            uint32_t* order, hipStream_t s);
 hipError_t launch_compact_cigar(const genasm_result* d_out, const uint64_t* dst_off,
                                 uint64_t n_pairs, const uint32_t* cigar, uint32_t* dst,
                                 hipStream_t s);

@@ -103,10 +103,11 @@ __device__ __forceinline__ u64 group_ballot(bool pred, int G, int lane) {
     return (b >> shift) & ((1ull << G) - 1);
 }
 
-// Device-memory loads that bypass the per-CU vector cache (the spill area is
-// rewritten every window).
-__device__ __forceinline__ u64 load_coherent(const u64* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Loads of a group's spilled table rows. The rows are written and read back by
+// the same wavefront, so wavefront scope is enough (a device-scope load would
+// skip the XCD's L2 for data that never leaves this CU).
+__device__ __forceinline__ u64 load_spill(const u64* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
 // Per-group LDS layout (64-bit words).
@@ -444,8 +445,8 @@ __device__ TbOut traceback_planes(const u64* lds, const u64* spill, uint32_t* ru
             B = row[i + 1];
         } else {
             const u64* row = spill + (size_t)(r - lds_rows) * stride + 1;
-            C = load_coherent(row + i);
-            B = load_coherent(row + i + 1);
+            C = load_spill(row + i);
+            B = load_spill(row + i + 1);
         }
         const bool intext = i < nw;
         const bool s_ok = intext && !(((B << 1) >> p) & 1ull);
@@ -514,6 +515,10 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
     bool overflow = (st.flags & kStateOverflow) != 0;
     bool failed = false, internal = false;
     u64 st_wops = 0, st_cells = 0, st_table = 0, st_tb = 0, st_steps = 0;
+    // phase clocks, read only when profiling
+    const bool timing = P.stats != nullptr;
+    u64 cyc_dc = 0, cyc_tb = 0;
+    const u64 cyc_start = timing ? clock64() : 0;
     // Every window commits at least one base, so a pair has at most m + n
     // windows; the cap keeps the loop finite even if that ever failed.
     const uint32_t max_windows = (uint32_t)pc.m + (uint32_t)pc.n + 1u;
@@ -533,6 +538,7 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
         const int Lc = min(nw, P.L);
         ++st.nwin;
         ++done_here;
+        const u64 cyc0 = timing ? clock64() : 0;
         u64 pl, ph, tl, th;
         seq_window(rc, P.read_lo, P.read_hi, pc.rb - rorg + st.pj, pl, ph);
         seq_window(fc, P.ref_lo, P.ref_hi, pc.fb - forg + st.ti, tl, th);
@@ -559,7 +565,7 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
                 wave_sync();
             }
             const int d = c * G + gl;
-            const u64 r0 = spill_pass ? load_coherent(spill + (size_t)(d - lds_rows) * P.stride + 1)
+            const u64 r0 = spill_pass ? load_spill(spill + (size_t)(d - lds_rows) * P.stride + 1)
                                       : lds[OFF_TAB + d * P.stride + 1];
             const bool sol = d <= Kr && !((r0 >> (mw - 1)) & 1ull);
             const u64 bits = group_ballot(sol, G, lane);
@@ -569,6 +575,7 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
             if (mw <= P.K) dstar = mw;  // no row below mw solves: d* = mw
             else { failed = true; break; }
         }
+        const u64 cyc1 = timing ? clock64() : 0;
         // traceback, in every lane of the group on the same values
         TbOut t;
         run_window_start(runs, rs, writer);
@@ -594,6 +601,11 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
         wave_sync();  // the next window's traceback rewrites the run slots
         st.ti += t.i_end;
         st.pj += t.j_end;
+        if (timing) {
+            const u64 cyc2 = clock64();
+            cyc_dc += cyc1 - cyc0;
+            cyc_tb += cyc2 - cyc1;
+        }
     }
     st.cur_op = rs.cur_op;
     st.cur_len = rs.cur_len;
@@ -634,6 +646,10 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
         stp[kStatTableWords] += st_table;
         stp[kStatTbReads] += st_tb;
         stp[kStatWindowLaneSteps] += st_steps;
+        stp[kStatWindows] += done_here;
+        stp[kStatDcCycles] += cyc_dc;
+        stp[kStatTbCycles] += cyc_tb;
+        stp[kStatPairCycles] += clock64() - cyc_start;
     }
 }
 
@@ -788,12 +804,15 @@ __global__ __launch_bounds__(64) void k_search(AlignParams P) {
     }
 }
 
-// Window kernel of the batched form. Each workgroup is one wavefront. It first
-// takes pairs from the hard queue (start row >= hard_row: decoy-like pairs whose
-// windows need most of the 64 rows), one pair per wavefront with all 64 lanes
-// as rows and the full table in LDS; when that queue is empty it takes pairs
-// from the easy queue, four at a time in 16-lane groups with `lds_rows` table
-// rows in LDS (rows above spill to device memory).
+// Window kernel of the batched form. Each workgroup is one wavefront. Pairs
+// come from two queues filled by the start search: the hard queue (start row
+// >= hard_row: decoy-like pairs whose windows need several DC passes) and the
+// easy queue, and a worker drains the hard queue first, so that the costliest
+// pairs start first and the queue tail is made of cheap ones. With hard_lanes
+// 64 a hard pair takes a whole wavefront (all 64 rows in one pass, the full
+// table in LDS); otherwise every pair runs in a 16-lane group, four pairs per
+// wavefront, with `lds_rows` table rows in LDS and the rows above spilled to
+// device memory.
 __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
     extern __shared__ u64 smem[];
     const int lane = threadIdx.x & 63;
@@ -801,13 +820,15 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
                                               __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t n_easy = __hip_atomic_load(P.counters + kCounterEasyLen, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
-    for (uint32_t iter = 0; iter <= n_hard; ++iter) {
-        const uint32_t item = group_pop(P.counters + kCounterHardHead, smem, lane);
-        if (item >= n_hard) break;
-        const uint64_t pair = P.hard_list[item];
-        const SearchOut so = P.search[pair];
-        if (so.row < 0) continue;  // ended in the search (result already written)
-        run_pair<64>(P, smem, nullptr, 64, lane, lane, pair, (int)so.col);
+    if (P.hard_lanes == 64) {
+        for (uint32_t iter = 0; iter <= n_hard; ++iter) {
+            const uint32_t item = group_pop(P.counters + kCounterHardHead, smem, lane);
+            if (item >= n_hard) break;
+            const uint64_t pair = P.hard_list[item];
+            const SearchOut so = P.search[pair];
+            if (so.row < 0) continue;  // ended in the search (result already written)
+            run_pair<64>(P, smem, nullptr, 64, lane, lane, pair, (int)so.col);
+        }
     }
     const int gl = lane & 15;
     const int grp = lane >> 4;
@@ -815,13 +836,18 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
     const int spill_rows = 64 - P.lds_rows;
     u64* spill = spill_rows > 0
         ? P.spill + ((uint64_t)blockIdx.x * 4 + grp) * (uint64_t)spill_rows * P.stride : nullptr;
-    for (uint32_t iter = 0; iter <= n_easy; ++iter) {
-        const uint32_t item = group_pop(P.counters + kCounterEasyHead, lds, gl);
-        if (item >= n_easy) break;
-        const uint64_t pair = P.easy_list[item];
-        const SearchOut so = P.search[pair];
-        if (so.row < 0) continue;  // ended in the search (result already written)
-        run_pair<16>(P, lds, spill, P.lds_rows, gl, lane, pair, (int)so.col);
+    for (int q = P.hard_lanes == 64 ? 1 : 0; q < 2; ++q) {
+        const uint32_t* list = q == 0 ? P.hard_list : P.easy_list;
+        const uint32_t n = q == 0 ? n_hard : n_easy;
+        uint32_t* head = P.counters + (q == 0 ? kCounterHardHead : kCounterEasyHead);
+        for (uint32_t iter = 0; iter <= n; ++iter) {
+            const uint32_t item = group_pop(head, lds, gl);
+            if (item >= n) break;
+            const uint64_t pair = list[item];
+            const SearchOut so = P.search[pair];
+            if (so.row < 0) continue;  // ended in the search (result already written)
+            run_pair<16>(P, lds, spill, P.lds_rows, gl, lane, pair, (int)so.col);
+        }
     }
 }
 
@@ -960,14 +986,50 @@ __global__ void k_init_counters_dev(uint32_t* counters, const uint32_t* params) 
         counters[i] = i == kCounterListBase ? params[0] : i == kCounterEasyLen ? params[1] : 0u;
 }
 
-// Sort keys for longest-read-first scheduling: key = ~read length (ascending
-// radix sort then puts long reads first), value = pair index.
-__global__ void k_lpt_keys(const uint64_t* read_off, uint64_t n_pairs, uint32_t* keys,
-                           uint32_t* vals) {
+// Longest-first order by a counting sort over length buckets: bucket 0 holds
+// the longest reads. A bucket is the read length's binary exponent and its
+// next three bits, so reads within about 12% of each other share a bucket
+// (their order inside it is arbitrary; the order only steers scheduling).
+__device__ __forceinline__ uint32_t lpt_bucket(uint64_t len) {
+    if (len == 0) return kLptBuckets - 1;
+    const int e = 63 - __builtin_clzll(len);
+    const uint32_t frac = e >= 3 ? (uint32_t)(len >> (e - 3)) & 7u : (uint32_t)(len << (3 - e)) & 7u;
+    const uint32_t key = (uint32_t)min(e, 40) * 8u + frac;  // grows with len, < 41 * 8
+    return kLptBuckets - 2 - key;
+}
+
+__global__ void k_lpt_count(const uint64_t* read_off, uint64_t n_pairs, uint32_t* hist) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_pairs) return;
-    keys[i] = ~(uint32_t)(read_off[i + 1] - read_off[i]);
-    vals[i] = (uint32_t)i;
+    atomicAdd(&hist[lpt_bucket(read_off[i + 1] - read_off[i])], 1u);
+}
+
+// Exclusive prefix sum of the bucket counts, in place (one block of kLptBuckets threads).
+__global__ void k_lpt_scan(uint32_t* hist) {
+    __shared__ uint32_t v[kLptBuckets];
+    const int t = threadIdx.x;
+    v[t] = hist[t];
+    __syncthreads();
+    for (int off = 1; off < kLptBuckets; off <<= 1) {
+        const uint32_t x = t >= off ? v[t - off] : 0u;
+        __syncthreads();
+        v[t] += x;
+        __syncthreads();
+    }
+    hist[t] = t == 0 ? 0u : v[t - 1];
+}
+
+__global__ void k_lpt_place(const uint64_t* read_off, uint64_t n_pairs, uint32_t* pos,
+                            uint32_t* order) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pairs) return;
+    const uint32_t at = atomicAdd(&pos[lpt_bucket(read_off[i + 1] - read_off[i])], 1u);
+    order[at] = (uint32_t)i;
+}
+
+__global__ void k_zero_u32(uint32_t* p, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
 }
 
 // Copies each pair's CIGAR elements to dst + dst_off[pair] (one block per pair).
@@ -1086,11 +1148,14 @@ hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long
     return hipGetLastError();
 }
 
-hipError_t launch_lpt_keys(const uint64_t* read_off, uint64_t n_pairs, uint32_t* keys,
-                           uint32_t* vals, hipStream_t s) {
+hipError_t launch_lpt_order(const uint64_t* read_off, uint64_t n_pairs, uint32_t* hist,
+                            uint32_t* order, hipStream_t s) {
     if (n_pairs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lpt_keys, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s,
-                       read_off, n_pairs, keys, vals);
+    const unsigned blocks = (unsigned)((n_pairs + 255) / 256);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kLptBuckets), 0, s, hist, (uint32_t)kLptBuckets);
+    hipLaunchKernelGGL(k_lpt_count, dim3(blocks), dim3(256), 0, s, read_off, n_pairs, hist);
+    hipLaunchKernelGGL(k_lpt_scan, dim3(1), dim3(kLptBuckets), 0, s, hist);
+    hipLaunchKernelGGL(k_lpt_place, dim3(blocks), dim3(256), 0, s, read_off, n_pairs, hist, order);
     return hipGetLastError();
 }
 

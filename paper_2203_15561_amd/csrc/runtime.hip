@@ -2,7 +2,6 @@
 // scratch, launch orchestration for the plain and batched forms, and the
 // host-memory convenience call.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <atomic>
@@ -10,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -59,6 +59,26 @@ int ensure(genasm_ctx* ctx, char** buf, size_t* cap, size_t need) {
     return GENASM_OK;
 }
 
+// Characters of one CIGAR run as text ("12=").
+inline uint64_t cigar_run_chars(uint32_t e) {
+    uint32_t len = GENASM_CIGAR_LEN(e);
+    uint64_t digits = 1;
+    while (len >= 10) { len /= 10; ++digits; }
+    return digits + 1;
+}
+
+// Writes one CIGAR run as text at w; returns the position after it.
+inline char* cigar_run_text(uint32_t e, char* w) {
+    static const char kOp[4] = {'=', 'X', 'I', 'D'};
+    char tmp[12];
+    int k = 0;
+    uint32_t len = GENASM_CIGAR_LEN(e);
+    do { tmp[k++] = (char)('0' + len % 10); len /= 10; } while (len);
+    while (k) *w++ = tmp[--k];
+    *w++ = kOp[GENASM_CIGAR_OP(e)];
+    return w;
+}
+
 struct Carver {
     char* base;
     size_t off = 0;
@@ -85,12 +105,18 @@ int resolve_launch(const genasm_launch* in, genasm_launch* out) {
     out->workers_per_cu = in->workers_per_cu;
     if (in->lpt_order >= 0) out->lpt_order = in->lpt_order;
     if (in->hard_row) out->hard_row = in->hard_row;
+    if (in->hard_lanes) out->hard_lanes = in->hard_lanes;
+    if (out->hard_lanes != 16 && out->hard_lanes != 64) return GENASM_E_INVAL;
     if (out->group_lanes != 16 && out->group_lanes != 64) return GENASM_E_INVAL;
     if (out->search_lanes != 16 && out->search_lanes != 64) return GENASM_E_INVAL;
     if (out->lds_rows < 16 || out->lds_rows > 64 || out->lds_rows % 16) return GENASM_E_INVAL;
     if (out->workers_per_cu < 0 || out->workers_per_cu > 32) return GENASM_E_INVAL;
     if (out->hard_row < 0 || out->hard_row > 65) return GENASM_E_INVAL;
-    if (out->group_lanes == 64) out->hard_row = 0;
+    if (out->group_lanes == 64) {
+        // every pair on the whole-wavefront path
+        out->hard_row = 0;
+        out->hard_lanes = 64;
+    }
     return GENASM_OK;
 }
 
@@ -123,7 +149,8 @@ int genasm_default_launch(int32_t form, genasm_launch* out) {
     out->lds_rows = 16;
     out->workers_per_cu = 0;
     out->lpt_order = 1;
-    out->hard_row = 65;
+    out->hard_row = 16;
+    out->hard_lanes = 16;
     return GENASM_OK;
 }
 
@@ -338,6 +365,7 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     // Batched: scratch layout.
     p.lds_rows = L.lds_rows;
     p.hard_row = L.hard_row;
+    p.hard_lanes = L.hard_lanes;
     p.route = 1;
     const int win_lds = window_lds_bytes(p.lds_rows, p.stride);
     int per_cu = L.workers_per_cu;
@@ -348,12 +376,6 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     const int search_blocks = ctx->num_cus * 8;
     const uint64_t workers = (uint64_t)win_blocks * 4;
     const int spill_rows = 64 - L.lds_rows;
-    size_t sort_tmp = 0;
-    if (L.lpt_order) {
-        (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, (uint32_t*)nullptr,
-                                                 (uint32_t*)nullptr, (uint32_t*)nullptr,
-                                                 (uint32_t*)nullptr, (int)n_pairs, 0, 32, s);
-    }
     auto carve = [&](Carver& c) {
         p.search = c.take<SearchOut>(n_pairs);
         p.counters = c.take<uint32_t>(kCounterCount);
@@ -361,19 +383,16 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
         p.easy_list = c.take<uint32_t>(n_pairs);
         p.hard_list = c.take<uint32_t>(n_pairs);
         p.spill = spill_rows > 0 ? c.take<unsigned long long>(workers * spill_rows * p.stride) : nullptr;
-        uint32_t* keys = c.take<uint32_t>(n_pairs);
-        uint32_t* vals = c.take<uint32_t>(n_pairs);
-        uint32_t* keys2 = c.take<uint32_t>(n_pairs);
+        uint32_t* hist = c.take<uint32_t>(kLptBuckets);
         uint32_t* order = c.take<uint32_t>(n_pairs);
-        void* tmp = c.take<char>(sort_tmp);
-        return std::make_tuple(lists, keys, vals, keys2, order, tmp);
+        return std::make_tuple(lists, hist, order);
     };
     Carver dry{nullptr};
     carve(dry);
     rc = ensure(ctx, &ctx->scratch, &ctx->scratch_cap, dry.off + 256);
     if (rc) return rc;
     Carver real{ctx->scratch};
-    auto [lists, keys, vals, keys2, order, tmp] = carve(real);
+    auto [lists, hist, order] = carve(real);
 
     CHECK_HIP(ctx, mark(0));
     CHECK_HIP(ctx, launch_planes(d_reads2b, d_read_off, total_read_bases,
@@ -383,10 +402,7 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
                                  const_cast<unsigned long long*>(p.ref_lo),
                                  const_cast<unsigned long long*>(p.ref_hi), s));
     if (L.lpt_order) {
-        CHECK_HIP(ctx, launch_lpt_keys(d_read_off, n_pairs, keys, vals, s));
-        size_t t = sort_tmp;
-        CHECK_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(tmp, t, keys, keys2, vals, order,
-                                                          (int)n_pairs, 0, 32, s));
+        CHECK_HIP(ctx, launch_lpt_order(d_read_off, n_pairs, hist, order, s));
         p.order = order;
     }
     // Start search: stage 0 over all pairs (longest first when ordered), then
@@ -455,6 +471,10 @@ int genasm_profile_read(genasm_ctx* ctx, genasm_profile* out) {
     out->tb_reads = sum[kStatTbReads];
     out->window_lane_steps = sum[kStatWindowLaneSteps];
     out->search_lane_steps = sum[kStatSearchLaneSteps];
+    out->windows = sum[kStatWindows];
+    out->dc_cycles = sum[kStatDcCycles];
+    out->tb_cycles = sum[kStatTbCycles];
+    out->pair_cycles = sum[kStatPairCycles];
     return GENASM_OK;
 }
 
@@ -546,29 +566,41 @@ int genasm_batch_align(genasm_ctx* ctx, const char* reads, const uint64_t* read_
         CHECK_HIP(ctx, hipMemcpyAsync(elems.data(), b.cig2, n_elems * 4, hipMemcpyDeviceToHost, s));
         CHECK_HIP(ctx, hipStreamSynchronize(s));
     }
-    // Format the text CIGARs.
-    static const char kOp[4] = {'=', 'X', 'I', 'D'};
-    uint64_t need = 0;
-    for (uint64_t e = 0; e < n_elems; ++e) {
-        uint32_t len = GENASM_CIGAR_LEN(elems[e]);
-        int digits = 1;
-        while (len >= 10) { len /= 10; ++digits; }
-        need += digits + 1;
-    }
+    // Format the text CIGARs: per-pair text lengths, their prefix sum, then
+    // the text itself, each pass split over host threads by pair ranges.
+    std::vector<uint64_t> tpos(n_pairs + 1, 0);
+    const unsigned n_thr = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>({(uint64_t)std::max(1u, std::thread::hardware_concurrency()), 16,
+                               n_elems / 65536 + 1}));
+    auto parallel = [&](auto&& body) {
+        std::vector<std::thread> th;
+        for (unsigned t = 1; t < n_thr; ++t)
+            th.emplace_back(body, n_pairs * t / n_thr, n_pairs * (t + 1) / n_thr);
+        body((uint64_t)0, n_pairs / n_thr);
+        for (auto& x : th) x.join();
+    };
+    parallel([&](uint64_t lo, uint64_t hi) {
+        for (uint64_t i = lo; i < hi; ++i) {
+            uint64_t chars = 0;
+            for (uint64_t e = dst[i]; e < dst[i + 1]; ++e) chars += cigar_run_chars(elems[e]);
+            tpos[i + 1] = chars;
+        }
+    });
+    for (uint64_t i = 0; i < n_pairs; ++i) tpos[i + 1] += tpos[i];
+    const uint64_t need = tpos[n_pairs];
     *cigar_needed = need;
     const bool fits = need <= cigar_cap;
-    uint64_t pos = 0;
     for (uint64_t i = 0; i < n_pairs; ++i) {
-        const uint64_t start = pos;
-        for (uint64_t e = dst[i]; e < dst[i + 1]; ++e) {
-            char tmp[16];
-            int len = std::snprintf(tmp, sizeof tmp, "%u%c", GENASM_CIGAR_LEN(elems[e]),
-                                    kOp[GENASM_CIGAR_OP(elems[e])]);
-            if (fits) std::memcpy(cigar_buf + pos, tmp, len);
-            pos += len;
-        }
-        out[i].cigar_off = start;
-        out[i].cigar_len = (uint32_t)(pos - start);
+        out[i].cigar_off = tpos[i];
+        out[i].cigar_len = (uint32_t)(tpos[i + 1] - tpos[i]);
+    }
+    if (fits) {
+        parallel([&](uint64_t lo, uint64_t hi) {
+            for (uint64_t i = lo; i < hi; ++i) {
+                char* w = cigar_buf + tpos[i];
+                for (uint64_t e = dst[i]; e < dst[i + 1]; ++e) w = cigar_run_text(elems[e], w);
+            }
+        });
     }
     if (!fits) return set_err(ctx, GENASM_E_NOSPACE, "cigar_cap below the CIGAR text size");
     return GENASM_OK;

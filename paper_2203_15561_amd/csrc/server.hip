@@ -338,6 +338,7 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     p.spill = srv->d_spill;
     p.lds_rows = lds_rows;
     p.hard_row = 65;
+    p.hard_lanes = 16;
     p.route = 0;
     p.state = srv->d_state;
     p.window_budget = cfg.window_budget;

@@ -5,8 +5,8 @@
 //   emu_driver IN OUT
 // IN : int64 form (0 plain, 1 batched, 2 serving loop), group_lanes, search_lanes,
 //      lds_rows, k, W, O, n_pairs, read_bytes, ref_bytes, hard_row, window_budget,
-//      slots, admit_per_iteration; then the packed read bytes, the packed
-//      reference bytes, read_off[n+1], ref_off[n+1] (uint64).
+//      slots, admit_per_iteration, hard_lanes; then the packed read bytes, the
+//      packed reference bytes, read_off[n+1], ref_off[n+1] (uint64).
 // OUT: n genasm_result records, then (read bases + ref bases) CIGAR elements.
 #include "../../paper_2203_15561_amd/csrc/kernels.hip"
 
@@ -25,13 +25,14 @@ int main(int argc, char** argv) {
     if (argc != 3) { fprintf(stderr, "usage: emu_driver IN OUT\n"); return 2; }
     FILE* f = fopen(argv[1], "rb");
     if (!f) { perror("open IN"); return 2; }
-    int64_t h[14];
+    int64_t h[15];
     if (!read_all(f, h, sizeof h)) return 2;
     const int form = (int)h[0], G = (int)h[1], SG = (int)h[2], lds_rows = (int)h[3];
     const int k = (int)h[4], W = (int)h[5], O = (int)h[6];
     const uint64_t n = (uint64_t)h[7], nrb = (uint64_t)h[8], nfb = (uint64_t)h[9];
     const int hard_row = (int)h[10];
     const uint32_t budget = (uint32_t)h[11], n_slots = (uint32_t)h[12], per_iter = (uint32_t)h[13];
+    const int hard_lanes = (int)h[14];
     std::vector<uint8_t> reads(nrb + 8), refs(nfb + 8);
     std::vector<uint64_t> roff(n + 1), foff(n + 1);
     if (!read_all(f, reads.data(), nrb) || !read_all(f, refs.data(), nfb) ||
@@ -104,6 +105,7 @@ int main(int argc, char** argv) {
         p.spill = spill_rows > 0 ? spill.data() : nullptr;
         p.lds_rows = lds_rows;
         p.hard_row = 65;
+        p.hard_lanes = 16;
         p.route = 0;
         p.state = state.data();
         p.window_budget = budget;
@@ -191,6 +193,7 @@ int main(int argc, char** argv) {
         p.easy_list = easy.data();
         p.hard_list = hard.data();
         p.hard_row = G == 64 ? 0 : hard_row;
+        p.hard_lanes = G == 64 ? 64 : hard_lanes;
         p.route = 1;
         p.lds_rows = lds_rows;
         launch_init_counters(p.counters, (uint32_t)n, nullptr);
@@ -219,17 +222,22 @@ int main(int argc, char** argv) {
         }
         p.list_in = nullptr;
         p.list_out = nullptr;
-        // The window kernel changes lane-group width between its two queues; the
-        // emulation runs it once per queue with the matching group width.
         const uint32_t n_easy = counters[kCounterEasyLen], n_hard = counters[kCounterHardLen];
-        counters[kCounterEasyLen] = 0;
-        emu::group_lanes = 64;
-        launch_windows(p, blocks, nullptr);
-        counters[kCounterEasyLen] = n_easy;
-        counters[kCounterEasyHead] = 0;  // the first launch's easy loop popped past the end
-        counters[kCounterHardLen] = 0;
-        emu::group_lanes = 16;
-        launch_windows(p, blocks, nullptr);
+        if (p.hard_lanes == 64) {
+            // The window kernel changes lane-group width between its two queues;
+            // the emulation runs it once per queue with the matching group width.
+            counters[kCounterEasyLen] = 0;
+            emu::group_lanes = 64;
+            launch_windows(p, blocks, nullptr);
+            counters[kCounterEasyLen] = n_easy;
+            counters[kCounterEasyHead] = 0;  // the first launch's easy loop popped past the end
+            counters[kCounterHardLen] = 0;
+            emu::group_lanes = 16;
+            launch_windows(p, blocks, nullptr);
+        } else {
+            emu::group_lanes = 16;
+            launch_windows(p, blocks, nullptr);
+        }
         fprintf(stderr, "emu: %u easy pairs, %u hard pairs\n", n_easy, n_hard);
     }
     FILE* g = fopen(argv[2], "wb");

@@ -169,12 +169,14 @@ inline unsigned long long bitreverse64(unsigned long long x) {
 }
 }  // namespace emu
 #define __builtin_bitreverse64 emu::bitreverse64
+inline unsigned long long clock64() { return 0ull; }
 #define __builtin_amdgcn_update_dpp emu::update_dpp
 #define __builtin_amdgcn_s_waitcnt(x) emu::group_barrier()
 #define __builtin_amdgcn_wave_barrier() emu::group_barrier()
 #define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __ballot(p) emu::ballot(p)
 #define __HIP_MEMORY_SCOPE_AGENT 0
+#define __HIP_MEMORY_SCOPE_WAVEFRONT 0
 #define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_SEQ_CST)
 
 template <class T>

@@ -36,12 +36,12 @@ SERVE = 2  # the device side of the serving loop (slot reuse, window budget)
 
 
 def run(driver: str, ps, form: int, group_lanes=16, search_lanes=16, lds_rows=16, hard_row=16,
-        timeout=600, window_budget=0, slots=0, admit_per_iteration=0):
+        timeout=600, window_budget=0, slots=0, admit_per_iteration=0, hard_lanes=16):
     """Returns (results, list of (op char, length) runs per pair)."""
     reads2b, refs2b = pack2b(ps.reads), pack2b(ps.refs)
     hdr = np.array([form, group_lanes, search_lanes, lds_rows, ps.k, ps.W, ps.O, ps.n_pairs,
                     len(reads2b), len(refs2b), hard_row, window_budget, slots,
-                    admit_per_iteration], dtype=np.int64)
+                    admit_per_iteration, hard_lanes], dtype=np.int64)
     with tempfile.TemporaryDirectory() as tmp:
         fin, fout = os.path.join(tmp, "in.bin"), os.path.join(tmp, "out.bin")
         with open(fin, "wb") as f:

@@ -32,15 +32,15 @@ def expected(ps):
             for i in range(ps.n_pairs)]
 
 
-def emulated(driver, ps, form, hard_row=16):
-    res, cig = emu.run(driver, ps, form, 16, 16, 16, hard_row=hard_row)
+def emulated(driver, ps, form, hard_row=16, hard_lanes=16):
+    res, cig = emu.run(driver, ps, form, 16, 16, 16, hard_row=hard_row, hard_lanes=hard_lanes)
     assert (res["flags"] == 0).all()
     return [(int(r["edit_distance"]), c, int(r["ref_begin"]), int(r["ref_end"]), int(r["n_windows"]))
             for r, c in zip(res, cig)]
 
 
-def check(driver, ps, form, hard_row=16):
-    want, got = expected(ps), emulated(driver, ps, form, hard_row)
+def check(driver, ps, form, hard_row=16, hard_lanes=16):
+    want, got = expected(ps), emulated(driver, ps, form, hard_row, hard_lanes)
     bad = [i for i in range(ps.n_pairs) if want[i] != got[i]]
     assert not bad, (bad[:5], want[bad[0]], got[bad[0]])
 
@@ -52,12 +52,12 @@ def test_hand_examples(driver, form):
         check(driver, ps, form)
 
 
-@pytest.mark.parametrize("hard_row", [16, 0, 65])
-def test_fuzz_batched(driver, hard_row):
-    # hard_row 0 sends every pair through the whole-wavefront path, whose
-    # 64-lane emulation is slow: fewer and shorter pairs there
+@pytest.mark.parametrize("hard_row,hard_lanes", [(16, 16), (0, 64), (65, 16), (4, 64)])
+def test_fuzz_batched(driver, hard_row, hard_lanes):
+    # hard_row 0 with 64 hard lanes sends every pair through the whole-wavefront
+    # path, whose 64-lane emulation is slow: fewer and shorter pairs there
     rng = np.random.default_rng(31 + hard_row)
-    n, max_len = (8, 120) if hard_row == 0 else (40, 250)
+    n, max_len = (8, 120) if hard_lanes == 64 else (40, 250)
     pairs = gen.fuzz(4242 + hard_row, 2 * n, max_len=max_len)
     for chunk in range(2):
         W = int(rng.choice([4, 8, 33, 64]))
@@ -65,7 +65,7 @@ def test_fuzz_batched(driver, hard_row):
         k = int(rng.choice([1, 5, 64]))
         sub = pairs[chunk * n:(chunk + 1) * n]
         ps = gen.from_lists("fuzz", [p[0] for p in sub], [p[1] for p in sub], k, W, O)
-        check(driver, ps, 1, hard_row)
+        check(driver, ps, 1, hard_row, hard_lanes)
 
 
 def test_edge_cases_batched(driver):
@@ -76,15 +76,16 @@ def test_edge_cases_batched(driver):
         check(driver, ps, 1)
 
 
-@pytest.mark.parametrize("hard_row", [16, 65])
-def test_long_read_prefixes_with_decoy(driver, hard_row):
+@pytest.mark.parametrize("hard_row,hard_lanes", [(16, 16), (16, 64)])
+def test_long_read_prefixes_with_decoy(driver, hard_row, hard_lanes):
     # 1,200-base prefixes of a true pair and a decoy pair: the decoy's windows
-    # need most of the 64 rows (hard path, or spilled rows when hard_row=65)
+    # need most of the 64 rows (spilled rows with 16 lanes, the whole-wavefront
+    # path with 64)
     ps = gen.make("long10k", 2, start=4)  # pair 4 is a decoy, pair 5 is not
     assert ps.decoy.tolist() == [True, False]
     cut = gen.from_lists("long-prefix", [ps.read(i)[:1200] for i in range(2)],
                          [ps.ref(i)[:1300] for i in range(2)], 64)
-    check(driver, cut, 1, hard_row)
+    check(driver, cut, 1, hard_row, hard_lanes)
 
 
 @pytest.mark.parametrize("budget", [1, 3])

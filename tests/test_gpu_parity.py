@@ -102,8 +102,10 @@ LAUNCH_VARIANTS = {
     "input_order": dict(lpt_order=0),
     "one_worker": dict(workers_per_cu=1),
     "all_hard": dict(hard_row=0),
+    "all_hard_g64": dict(hard_row=0, hard_lanes=64),
     "no_hard": dict(hard_row=65),
     "hard_from_8": dict(hard_row=8),
+    "hard_g64": dict(hard_row=16, hard_lanes=64),
 }
 
 
@@ -186,3 +188,58 @@ def test_alphabet_error_is_reported(ctx):
     with pytest.raises(ga.GenasmError) as e:
         ctx.align(["ACGT"], ["ACNT"], 5)
     assert e.value.code == ga.capi.E_ALPHABET
+
+
+def _decode_dev(out, cigar, n):
+    res = out.cpu().numpy().view(ga.RESULT_DTYPE).reshape(-1)[:n]
+    elems = cigar.cpu().numpy().view(np.uint32)
+    got = []
+    for r in res:
+        assert r["flags"] == 0
+        o, k = int(r["cigar_off"]), int(r["cigar_len"])
+        got.append((int(r["edit_distance"]), int(r["ref_begin"]), int(r["ref_end"]),
+                    int(r["n_windows"]), ga.decode_cigar(elems[o:o + k])))
+    return got
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_graph_capture_replays(ctx, form):
+    # The device form captured in a HIP graph (through torch's capture of the
+    # current stream): every replay, with eager work and synchronizations
+    # between replays, rewrites the same results. The graph keeps using its
+    # context's scratch, so it gets a context of its own.
+    import torch
+    ps = gen.make("uneven", 300, start=900)
+    want = expected(ps)
+    dev = torch.device("cuda:0")
+    reads2b = torch.from_numpy(ga.pack(ps.reads)).to(dev)
+    refs2b = torch.from_numpy(ga.pack(ps.refs)).to(dev)
+    roff = torch.from_numpy(ps.read_off.astype(np.int64)).to(dev)
+    foff = torch.from_numpy(ps.ref_off.astype(np.int64)).to(dev)
+    nr, nf = int(ps.read_off[-1]), int(ps.ref_off[-1])
+    out = torch.empty((ps.n_pairs, 32), dtype=torch.uint8, device=dev)
+    cigar = torch.empty(nr + nf, dtype=torch.int32, device=dev)
+    gctx = ga.Context(0)
+    try:
+        kw = dict(launch=FORMS[form], out=out, cigar=cigar, total_read_bases=nr,
+                  total_ref_bases=nf, max_ref_len=int(np.diff(ps.ref_off).max()))
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            gctx.align_dev(reads2b, roff, refs2b, foff, ps.k, **kw)  # sizes the scratch
+        torch.cuda.synchronize()
+        assert_same(ps, want, _decode_dev(out, cigar, ps.n_pairs), f"{form} eager")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            gctx.align_dev(reads2b, roff, refs2b, foff, ps.k, **kw)
+        small = gen.make("short100", 50)
+        for rep in range(3):
+            out.zero_()
+            cigar.fill_(-1)
+            torch.cuda.synchronize()
+            on_gpu(ctx, small)  # eager work on another context between replays
+            g.replay()
+            torch.cuda.synchronize()
+            assert_same(ps, want, _decode_dev(out, cigar, ps.n_pairs), f"{form} replay {rep}")
+    finally:
+        gctx.close()
