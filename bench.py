@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--serving-rates", default="1000,3000,10000",
                     help="open-loop arrival rates (req/s) below the saturated rate, comma-separated")
     ap.add_argument("--no-graph", action="store_true", help="skip timing the graph-captured step")
+    ap.add_argument("--no-unimproved", action="store_true",
+                    help="skip the ablation run without the three improvements")
     ap.add_argument("--no-end-to-end", action="store_true", help="skip the host-memory form timing")
     args = ap.parse_args()
 
@@ -319,6 +321,43 @@ def main():
         line["plain"] = {"alignments_per_s": ps.n_pairs / (pm / 1e3), "ms": pm,
                          "gcups": cells / (pm / 1e3) / 1e9}
         log(f"plain: {pm:.2f} ms/step")
+
+    if not args.no_unimproved:
+        # ablation: the same step with the unimproved window (every row, four
+        # edge words per entry in device memory); a profiled run gives its work
+        # counters, an unprofiled one its time
+        unimp = ga.make_launch(ga.FORM_UNIMPROVED)
+        ctx.profile(True)
+        step(unimp)
+        pu = ctx.profile_read()
+        ctx.profile(False)
+        torch.cuda.synchronize()
+        u0, u1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        u0.record()
+        step(unimp)
+        u1.record()
+        torch.cuda.synchronize()
+        um = u0.elapsed_time(u1)
+        res_u = out.cpu().numpy().view(ga.RESULT_DTYPE).reshape(-1)
+        assert (res_u["edit_distance"] == res["edit_distance"]).all()
+        win = max(pr["windows"], 1)
+        line["unimproved"] = {
+            "alignments_per_s": ps.n_pairs / (um / 1e3), "ms": um,
+            "table_words": int(pu["table_words"]), "tb_reads": int(pu["tb_reads"]),
+            "window_word_ops": int(pu["window_word_ops"])}
+        line["improvements"] = {
+            "speedup_batched_over_unimproved": um / ms_step,
+            "speedup_plain_over_unimproved": um / line["plain"]["ms"] if "plain" in line else None,
+            "table_words_per_window": {"improved": pr["table_words"] / win,
+                                       "unimproved": pu["table_words"] / max(pu["windows"], 1)},
+            "footprint_reduction": (pu["table_words"] / max(pu["windows"], 1)) / (pr["table_words"] / win),
+            "access_reduction": (pu["table_words"] + pu["tb_reads"]) / (pr["table_words"] + pr["tb_reads"]),
+            "dc_work_reduction": pu["window_word_ops"] / max(pr["window_word_ops"], 1),
+            "paper": {"footprint_reduction": 24, "access_reduction": 12, "gpu_speedup": 5.9},
+        }
+        log(f"unimproved: {um:.1f} ms/step ({um / ms_step:.1f}x the batched step); footprint "
+            f"{line['improvements']['footprint_reduction']:.1f}x, accesses "
+            f"{line['improvements']['access_reduction']:.1f}x smaller with the improvements")
 
     if not args.no_graph:
         # the same step captured once in a HIP graph (through torch's stream

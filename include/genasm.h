@@ -79,6 +79,10 @@ typedef struct {
 #define GENASM_FORM_PLAIN 0    /* one pair per workgroup: 64 lanes = 64 DP rows of one pair */
 #define GENASM_FORM_BATCHED 1  /* search kernels, then one persistent window kernel with a
                                   device work queue; several pairs per wavefront */
+#define GENASM_FORM_UNIMPROVED 2 /* ablation: one pair per workgroup, each window computing
+                                  every row 0..K and keeping the four edge words of every
+                                  entry in device memory (no early exit, no AND, no pruning);
+                                  same results, for measuring what the improvements save */
 
 typedef struct {
     int32_t form;            /* GENASM_FORM_* */

@@ -25,6 +25,7 @@ E_TOOLONG = -7
 
 FORM_PLAIN = 0
 FORM_BATCHED = 1
+FORM_UNIMPROVED = 2
 
 FLAG_CIGAR_OVERFLOW = 1
 FLAG_INTERNAL = 2

@@ -20,6 +20,9 @@ struct genasm_ctx {
     // bit planes of the current call's streams (device)
     char* planes = nullptr;
     size_t planes_cap = 0;
+    // unimproved-form window tables (device)
+    char* unimp = nullptr;
+    size_t unimp_cap = 0;
     // host-form staging (device)
     char* stage = nullptr;
     size_t stage_cap = 0;
@@ -138,6 +141,11 @@ constexpr int kSearchGroupWords = kGroupHeaderWords;  // PM, ring, broadcast slo
 
 // Kernel launchers (kernels.hip). All return hipError_t of the launch.
 hipError_t launch_plain(const AlignParams& p, hipStream_t s);
+// Unimproved form (ablation): one pair per workgroup, its window table (all
+// rows, four edge words per entry) in `table`, unimproved_table_words(n_pairs)
+// words of device memory.
+uint64_t unimproved_table_words(uint64_t n_pairs);
+hipError_t launch_unimproved(const AlignParams& p, unsigned long long* table, hipStream_t s);
 hipError_t launch_search(const AlignParams& p, int group_lanes, int rows_per_lane, int blocks,
                          hipStream_t s);
 hipError_t launch_windows(const AlignParams& p, int blocks, hipStream_t s);

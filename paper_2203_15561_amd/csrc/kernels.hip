@@ -733,6 +733,222 @@ __global__ __launch_bounds__(64) void k_plain(AlignParams P) {
 }
 
 // ---------------------------------------------------------------------------
+// Unimproved form (ablation): the GenASM window without the three improvements
+// ---------------------------------------------------------------------------
+//
+// One pair per 64-lane workgroup, as the plain form, but each window computes
+// every row 0..K (no early exit), keeps all four edge words (match,
+// substitution, insertion, deletion) of every entry (d, i), i < nw (no AND,
+// no pruning of unreachable entries) in device memory, reads d* off column 0
+// afterwards, and traces back by testing bit p of the stored edge words. Lane
+// d computes row d; when K = 64, lane 63 also computes row 64 from its own
+// row. Results equal the improved forms (the edges are pure functions of R).
+
+// Edge words of entry (d, i): table + ((d * 64) + i) * 4 + {0 M, 1 S, 2 I, 3 D}.
+constexpr int kUnimpRows = 65;
+constexpr uint64_t kUnimpWords = (uint64_t)kUnimpRows * 64 * 4;  // per workgroup
+
+__device__ __forceinline__ void store_edges(u64* e, u64 m, u64 s, u64 in, u64 d) {
+    e[0] = m;
+    e[1] = s;
+    e[2] = in;
+    e[3] = d;
+}
+
+__device__ TbOut traceback_unimproved(const u64* tab, uint32_t* runs, RunState& rs, bool writer,
+                                      u64 pl, u64 ph, u64 tl, u64 th, int mw, int nw, int dstar,
+                                      int L, bool& internal) {
+    int i = 0, p = mw - 1, d = dstar;
+    TbOut o{0, 0, 0, 0u, false};
+    while (p >= 0 && i < L && mw - 1 - p < L) {
+        const int j = mw - 1 - p;
+        const bool intext = i < nw;
+        u64 m = ~0ull, sw = ~0ull, iw = ~0ull, dw = ~0ull;
+        if (intext) {
+            const u64* e = tab + ((size_t)d * 64 + i) * 4;
+            m = load_spill(e + 0);
+            if (d >= 1) {
+                sw = load_spill(e + 1);
+                iw = load_spill(e + 2);
+                dw = load_spill(e + 3);
+            }
+        } else if (d >= 1) {
+            iw = init_word(d - 1) << 1;  // past the text end only the insertion edge exists
+        }
+        const bool m_ok = !((m >> p) & 1ull);
+        const bool s_ok = d >= 1 && !((sw >> p) & 1ull);
+        const bool i_ok = d >= 1 && !((iw >> p) & 1ull);
+        const bool d_ok = d >= 1 && !((dw >> p) & 1ull);
+        // words an edge-by-edge traceback reads: the match word when the bases
+        // agree, then each further edge word tested, in priority order
+        const bool eq = intext && !((((pl >> j) ^ (tl >> i)) | ((ph >> j) ^ (th >> i))) & 1ull);
+        const uint32_t more = (d >= 1 && intext) ? 1u : 0u;
+        o.reads += (eq ? 1u : 0u) +
+                   (m_ok ? 0u : more * (s_ok ? 1u : i_ok ? 2u : 3u));
+        if (!(m_ok || s_ok || i_ok || d_ok)) { internal = true; break; }
+        const int op = m_ok ? GENASM_OP_MATCH : s_ok ? GENASM_OP_MISMATCH
+                     : i_ok ? GENASM_OP_INS : GENASM_OP_DEL;
+        run_push(runs, rs, op, 1u, writer);
+        i += op != GENASM_OP_INS;
+        p -= op != GENASM_OP_DEL;
+        d -= op != GENASM_OP_MATCH;
+    }
+    o.i_end = i;
+    o.j_end = mw - 1 - p;
+    o.edits = dstar - d;
+    return o;
+}
+
+__global__ __launch_bounds__(64) void k_unimproved(AlignParams P, u64* table) {
+    extern __shared__ u64 smem[];
+    const int lane = threadIdx.x;
+    const uint64_t pair = blockIdx.x;
+    if (pair >= P.n_pairs) return;
+    const PairCursor pc = pair_cursor(P, pair);
+    if (pc.m == 0) {
+        if (lane == 0) finish_without_windows(P, pair, 0);
+        return;
+    }
+    const int m1 = min(P.W, pc.m);
+    const int Kr = min(P.K, m1 - 1);
+    build_pm<64>(smem, lane, P.reads, pc.rb, m1, false);
+    int row, col;
+    search_rows<64, 1>(smem, lane, lane, P.refs, pc.fb, pc.n, m1, Kr, &row, &col);
+    if (lane == 0)
+        search_stats(P, pair, pc.n, m1, row >= 0 ? row : (m1 <= P.K ? m1 : Kr), 64ull * (pc.n + 63), true);
+    if (row < 0) {
+        if (m1 <= P.K) { row = m1; col = 0; }
+        else {
+            if (lane == 0) finish_without_windows(P, pair, -1);
+            return;
+        }
+    }
+    u64* tab = table + pair * kUnimpWords;
+    const uint64_t run_base = pair_run_base(P, pair);
+    const uint64_t run_limit = min(P.cigar_cap, run_base + (uint64_t)pc.m + (uint64_t)pc.n);
+    uint32_t* runs = reinterpret_cast<uint32_t*>(smem + OFF_BROW);
+    const bool writer = lane == 0;
+    RunState rs{-1, 0u, -1};
+    int ti = col, pj = 0, score = 0;
+    uint32_t nwin = 0, written = 0;
+    bool overflow = false, failed = false, internal = false;
+    u64 st_wops = 0, st_cells = 0, st_table = 0, st_tb = 0, st_steps = 0;
+    const uint64_t rorg = P.planes_from_off0 ? (P.read_off[0] & ~63ull) : 0;
+    const uint64_t forg = P.planes_from_off0 ? (P.ref_off[0] & ~63ull) : 0;
+    SeqCursor rc, fc;
+    seq_open(rc, P.read_lo, P.read_hi, pc.rb - rorg);
+    seq_open(fc, P.ref_lo, P.ref_hi, pc.fb - forg + ti);
+    const uint32_t max_windows = (uint32_t)pc.m + (uint32_t)pc.n + 1u;
+    const int K = P.K;  // rows 0..K, K <= 64
+    const int d = lane;
+    while (pj < pc.m) {
+        if (nwin >= max_windows) { failed = internal = true; break; }
+        const int mw = min(P.W, pc.m - pj);
+        const int nw = min(P.W, pc.n - ti);
+        ++nwin;
+        u64 pl, ph, tl, th;
+        seq_window(rc, P.read_lo, P.read_hi, pc.rb - rorg + pj, pl, ph);
+        seq_window(fc, P.ref_lo, P.ref_hi, pc.fb - forg + ti, tl, th);
+        u64 pm[4];
+        pm_from_planes(pl, ph, mw, pm);
+        store_pmt<64>(smem, lane, pm, tl, th, nw);
+        wave_sync();
+        // DC over all rows and columns
+        const u64* pmt = smem + OFF_PMT;
+        u64 R = init_word(d);
+        u64 Dp = d == 0 ? ~0ull : init_word(d - 1);
+        u64 R64 = 0ull;  // row 64 (lane 63, K = 64): init word 0
+        u64 col0 = R, col0_64 = R64;
+        for (int t = 0; t < nw + 63; ++t) {
+            const int i = nw - 1 - t + d;
+            const u64 pm_t = pmt[clampi(i, 0, nw)];
+            const u64 up = LaneShift<64>::up(~0ull, R);
+            const u64 m = (R << 1) | pm_t;
+            const u64 sw = Dp << 1, iw = up << 1, dw = Dp;
+            const u64 Rn = d == 0 ? m : (m & sw & iw & dw);
+            const bool live = i >= 0 && i < nw && d <= K;
+            if (live) store_edges(tab + ((size_t)d * 64 + i) * 4, m, sw, iw, dw);
+            if (d == 63 && K == 64 && i >= 0 && i < nw) {
+                // row 64 from row 63: D = R63[i+1] (R), U = R63[i] (Rn)
+                const u64 m64 = (R64 << 1) | pm_t;
+                const u64 s64 = R << 1, i64 = Rn << 1, d64 = R;
+                store_edges(tab + ((size_t)64 * 64 + i) * 4, m64, s64, i64, d64);
+                R64 = m64 & s64 & i64 & d64;
+                if (i == 0) col0_64 = R64;
+            }
+            if (i == 0) col0 = Rn;
+            Dp = up;
+            R = Rn;
+        }
+        mem_sync();
+        st_cells += (u64)mw * nw;
+        st_steps += 64ull * (nw + 63);
+        int dstar = -1;
+        if (nw == 0) {
+            // no columns: every row holds its initial word
+            col0 = init_word(d);
+            col0_64 = 0ull;
+        }
+        const bool sol = d <= K && !((col0 >> (mw - 1)) & 1ull);
+        const u64 bits = __ballot(sol);
+        if (bits) dstar = __builtin_ctzll(bits);
+        else if (K == 64) {
+            const u64 b64 = __ballot(lane == 63 && !((col0_64 >> (mw - 1)) & 1ull));
+            if (b64) dstar = 64;
+        }
+        if (dstar < 0) { failed = true; break; }
+        TbOut t;
+        run_window_start(runs, rs, writer);
+        t = traceback_unimproved(tab, runs, rs, writer, pl, ph, tl, th, mw, nw, dstar, P.L, internal);
+        if (internal) { failed = true; break; }
+        score += t.edits;
+        st_tb += t.reads;
+        st_wops += (u64)nw * (2 + 6 * (u64)K);
+        st_table += (u64)nw * (4ull * (K + 1) - 3);
+        wave_sync();
+        const int closed = max(rs.nr, 0);
+        overflow |= copy_runs<64>(runs, closed, P.cigar, run_base, run_limit, written, lane);
+        written += (uint32_t)closed;
+        wave_sync();
+        ti += t.i_end;
+        pj += t.j_end;
+    }
+    if (!failed && writer && rs.cur_op >= 0) {
+        const uint64_t idx = run_base + written;
+        if (idx < run_limit) P.cigar[idx] = (rs.cur_len << 2) | (uint32_t)rs.cur_op;
+        else overflow = true;
+    }
+    const bool ovf = __ballot(overflow) != 0;
+    if (lane == 0) {
+        genasm_result r;
+        if (failed) {
+            r.edit_distance = -1;
+            r.ref_begin = r.ref_end = 0;
+            r.cigar_len = 0;
+        } else {
+            r.edit_distance = score;
+            r.ref_begin = (uint32_t)col;
+            r.ref_end = (uint32_t)ti;
+            r.cigar_len = ovf ? 0u : written + (rs.cur_op >= 0 ? 1u : 0u);
+        }
+        r.n_windows = nwin;
+        r.cigar_off = run_base;
+        r.flags = (ovf && !failed ? GENASM_FLAG_CIGAR_OVERFLOW : 0u) |
+                  (internal ? GENASM_FLAG_INTERNAL : 0u);
+        P.out[pair] = r;
+        if (P.stats) {
+            u64* stp = P.stats + pair * kStatCount;
+            stp[kStatWindowWordOps] += st_wops;
+            stp[kStatWindowCells] += st_cells;
+            stp[kStatTableWords] += st_table;
+            stp[kStatTbReads] += st_tb;
+            stp[kStatWindowLaneSteps] += st_steps;
+            stp[kStatWindows] += nwin;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Batched form: start search with a retry list, then a persistent window kernel
 // ---------------------------------------------------------------------------
 
@@ -1058,6 +1274,15 @@ hipError_t launch_plain(const AlignParams& p, hipStream_t s) {
     if (p.n_pairs == 0) return hipSuccess;
     const int lds = plain_lds_bytes(p.stride);
     hipLaunchKernelGGL(k_plain, dim3((unsigned)p.n_pairs), dim3(64), lds, s, p);
+    return hipGetLastError();
+}
+
+uint64_t unimproved_table_words(uint64_t n_pairs) { return n_pairs * kUnimpWords; }
+
+hipError_t launch_unimproved(const AlignParams& p, unsigned long long* table, hipStream_t s) {
+    if (p.n_pairs == 0) return hipSuccess;
+    const int lds = plain_lds_bytes(p.stride);
+    hipLaunchKernelGGL(k_unimproved, dim3((unsigned)p.n_pairs), dim3(64), lds, s, p, table);
     return hipGetLastError();
 }
 

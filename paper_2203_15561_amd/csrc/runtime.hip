@@ -98,7 +98,9 @@ bool valid_wko(int32_t k, int32_t W, int32_t O) {
 int resolve_launch(const genasm_launch* in, genasm_launch* out) {
     genasm_default_launch(in ? in->form : GENASM_FORM_BATCHED, out);
     if (!in) return GENASM_OK;
-    if (in->form != GENASM_FORM_PLAIN && in->form != GENASM_FORM_BATCHED) return GENASM_E_INVAL;
+    if (in->form != GENASM_FORM_PLAIN && in->form != GENASM_FORM_BATCHED &&
+        in->form != GENASM_FORM_UNIMPROVED)
+        return GENASM_E_INVAL;
     if (in->group_lanes) out->group_lanes = in->group_lanes;
     if (in->search_lanes) out->search_lanes = in->search_lanes;
     if (in->lds_rows) out->lds_rows = in->lds_rows;
@@ -204,6 +206,7 @@ void genasm_destroy(genasm_ctx* ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->planes) (void)hipFree(ctx->planes);
+    if (ctx->unimp) (void)hipFree(ctx->unimp);
     if (ctx->stage) (void)hipFree(ctx->stage);
     if (ctx->stats) (void)hipFree(ctx->stats);
     for (hipEvent_t e : ctx->ev)
@@ -346,6 +349,23 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     auto mark = [&](int i) -> hipError_t {
         return ctx->profiling ? hipEventRecord(ctx->ev[i], s) : hipSuccess;
     };
+    if (L.form == GENASM_FORM_UNIMPROVED) {
+        p.lds_rows = 64;
+        rc = ensure(ctx, &ctx->unimp, &ctx->unimp_cap, unimproved_table_words(n_pairs) * 8);
+        if (rc) return rc;
+        CHECK_HIP(ctx, mark(0));
+        CHECK_HIP(ctx, launch_planes(d_reads2b, d_read_off, total_read_bases,
+                                     const_cast<unsigned long long*>(p.read_lo),
+                                     const_cast<unsigned long long*>(p.read_hi), s));
+        CHECK_HIP(ctx, launch_planes(d_refs2b, d_ref_off, total_ref_bases,
+                                     const_cast<unsigned long long*>(p.ref_lo),
+                                     const_cast<unsigned long long*>(p.ref_hi), s));
+        CHECK_HIP(ctx, mark(1));
+        CHECK_HIP(ctx, mark(2));
+        CHECK_HIP(ctx, launch_unimproved(p, reinterpret_cast<unsigned long long*>(ctx->unimp), s));
+        CHECK_HIP(ctx, mark(3));
+        return GENASM_OK;
+    }
     if (L.form == GENASM_FORM_PLAIN) {
         p.lds_rows = 64;
         CHECK_HIP(ctx, mark(0));

@@ -3,7 +3,7 @@
 // the device side of the serving loop).
 //
 //   emu_driver IN OUT
-// IN : int64 form (0 plain, 1 batched, 2 serving loop), group_lanes, search_lanes,
+// IN : int64 form (0 plain, 1 batched, 2 serving loop, 3 unimproved), group_lanes, search_lanes,
 //      lds_rows, k, W, O, n_pairs, read_bytes, ref_bytes, hard_row, window_budget,
 //      slots, admit_per_iteration, hard_lanes; then the packed read bytes, the
 //      packed reference bytes, read_off[n+1], ref_off[n+1] (uint64).
@@ -174,6 +174,11 @@ int main(int argc, char** argv) {
         emu::group_lanes = 64;
         p.lds_rows = 64;
         launch_plain(p, nullptr);
+    } else if (form == GENASM_FORM_UNIMPROVED) {
+        emu::group_lanes = 64;
+        p.lds_rows = 64;
+        std::vector<unsigned long long> table(unimproved_table_words(n));
+        launch_unimproved(p, table.data(), nullptr);
     } else {
         const int blocks = 2;
         const uint64_t workers = (uint64_t)blocks * 4;

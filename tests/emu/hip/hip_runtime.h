@@ -171,6 +171,12 @@ inline unsigned long long bitreverse64(unsigned long long x) {
 #define __builtin_bitreverse64 emu::bitreverse64
 inline unsigned long long clock64() { return 0ull; }
 #define __builtin_amdgcn_update_dpp emu::update_dpp
+// Block-wide barriers and static shared arrays are not emulated (kernels that
+// use them, such as the ordering scan, do not run under the emulation).
+inline void __syncthreads() {
+    std::fprintf(stderr, "emu: __syncthreads is not emulated\n");
+    std::abort();
+}
 #define __builtin_amdgcn_s_waitcnt(x) emu::group_barrier()
 #define __builtin_amdgcn_wave_barrier() emu::group_barrier()
 #define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)

@@ -33,6 +33,7 @@ def pack2b(codes: np.ndarray) -> np.ndarray:
 
 
 SERVE = 2  # the device side of the serving loop (slot reuse, window budget)
+UNIMPROVED = 3  # the unimproved (ablation) form
 
 
 def run(driver: str, ps, form: int, group_lanes=16, search_lanes=16, lds_rows=16, hard_row=16,

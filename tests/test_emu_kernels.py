@@ -45,11 +45,28 @@ def check(driver, ps, form, hard_row=16, hard_lanes=16):
     assert not bad, (bad[:5], want[bad[0]], got[bad[0]])
 
 
-@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("form", [0, 1, emu.UNIMPROVED])
 def test_hand_examples(driver, form):
     for ex in load_hand_examples():
         ps = gen.from_lists("hand", [ex["P"]], [ex["T"]], ex["k"], ex["W"], ex["O"])
         check(driver, ps, form)
+
+
+def test_unimproved_fuzz_and_edges(driver):
+    # the ablation form: every row, four edge words per entry, traceback on edges
+    rng = np.random.default_rng(77)
+    pairs = gen.fuzz(9090, 12, max_len=110)
+    for chunk in range(2):
+        W = int(rng.choice([8, 33, 64]))
+        O = int(rng.choice(sorted({0, W // 2, W - 1})))
+        k = int(rng.choice([3, 64]))
+        sub = pairs[chunk * 6:(chunk + 1) * 6]
+        ps = gen.from_lists("fuzz", [p[0] for p in sub], [p[1] for p in sub], k, W, O)
+        check(driver, ps, emu.UNIMPROVED)
+    cases = [("", ""), ("", "ACGT"), ("ACGT", ""), ("A" * 64, "C" * 64), ("T" * 65, "")]
+    for k in (0, 64):
+        ps = gen.from_lists("edge", [c[0] for c in cases], [c[1] for c in cases], k)
+        check(driver, ps, emu.UNIMPROVED)
 
 
 @pytest.mark.parametrize("hard_row,hard_lanes", [(16, 16), (0, 64), (65, 16), (4, 64)])

@@ -57,6 +57,7 @@ def assert_same(ps, want, got, label=""):
 FORMS = {
     "plain": ga.make_launch(ga.FORM_PLAIN),
     "batched": None,
+    "unimproved": ga.make_launch(ga.FORM_UNIMPROVED),
 }
 
 
@@ -243,3 +244,29 @@ def test_graph_capture_replays(ctx, form):
             assert_same(ps, want, _decode_dev(out, cigar, ps.n_pairs), f"{form} replay {rep}")
     finally:
         gctx.close()
+
+
+@pytest.mark.parametrize("form,variant", [("batched", "improved"), ("plain", "improved"),
+                                          ("unimproved", "uncompressed")])
+def test_work_counters_match_oracle(ctx, form, variant):
+    # The device work counters (profiling) against the oracle variant with the
+    # same storage scheme: DC word operations, DP cells, stored table words and,
+    # for the edge-word form, the words its traceback reads.
+    ps = gen.make("uneven", 60, start=3000)
+    res, _, _, _ = oracle.batch(ps, variant)
+    assert (res["status"] == 0).all() and (res["score"] >= 0).all()
+    ctx.profile(True)
+    try:
+        ctx.align([ps.read(i) for i in range(ps.n_pairs)], [ps.ref(i) for i in range(ps.n_pairs)],
+                  ps.k, ps.W, ps.O, FORMS[form])
+        pr = ctx.profile_read()
+    finally:
+        ctx.profile(False)
+    assert pr["n_pairs"] == ps.n_pairs
+    assert pr["window_cells"] == int(res["cells_window"].sum())
+    assert pr["search_cells"] == int(res["cells_search"].sum())
+    assert pr["window_word_ops"] == int(res["word_ops"].sum())
+    assert pr["table_words"] == int(res["words_stored"].sum())
+    assert pr["windows"] == int(res["n_windows"].sum())
+    if variant == "uncompressed":
+        assert pr["tb_reads"] == int(res["words_read"].sum())
