@@ -166,6 +166,9 @@ def main():
     ap.add_argument("--serving-rates", default="1000,3000,10000",
                     help="open-loop arrival rates (req/s) below the saturated rate, comma-separated")
     ap.add_argument("--no-graph", action="store_true", help="skip timing the graph-captured step")
+    ap.add_argument("--no-filter", action="store_true", help="skip the pre-alignment filter leg")
+    ap.add_argument("--filter-pairs", type=int, default=20000,
+                    help="pairs of the 250 bp workload for the filter leg")
     ap.add_argument("--no-unimproved", action="store_true",
                     help="skip the ablation run without the three improvements")
     ap.add_argument("--no-end-to-end", action="store_true", help="skip the host-memory form timing")
@@ -406,6 +409,30 @@ def main():
         line["end_to_end"] = {"alignments_per_s": ps.n_pairs / e2e, "seconds": e2e,
                               "what": "host ASCII in, CIGAR text out (PCIe and host gather included)"}
         log(f"end to end (host form): {e2e * 1e3:.1f} ms")
+
+    if not args.no_filter:
+        # score-only mode on 250 bp reads (2% edits, 20 bp flanks), k = 15
+        fps = gen.make("short250", args.filter_pairs)
+        fr2 = torch.from_numpy(ga.pack(fps.reads)).to(dev)
+        ff2 = torch.from_numpy(ga.pack(fps.refs)).to(dev)
+        fro = torch.from_numpy(fps.read_off.astype(np.int64)).to(dev)
+        ffo = torch.from_numpy(fps.ref_off.astype(np.int64)).to(dev)
+        fmax = int(np.diff(fps.read_off).max())
+        dist, start = ctx.filter_dev(fr2, fro, ff2, ffo, fps.k, fmax)
+        torch.cuda.synchronize()
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record()
+        for _ in range(args.steps):
+            ctx.filter_dev(fr2, fro, ff2, ffo, fps.k, fmax, dist=dist, start=start)
+        f1.record()
+        torch.cuda.synchronize()
+        fms = f0.elapsed_time(f1) / args.steps
+        cells = float((np.diff(fps.read_off) * np.diff(fps.ref_off)).sum())
+        line["filter"] = {"workload": f"short250: {fps.n_pairs} pairs, k={fps.k}",
+                          "pairs_per_s": fps.n_pairs / (fms / 1e3), "ms": fms,
+                          "gcups": cells / (fms / 1e3) / 1e9,
+                          "accepted": float((dist.cpu().numpy() >= 0).mean())}
+        log(f"filter: {fms:.3f} ms for {fps.n_pairs} pairs ({line['filter']['gcups']:.0f} GCUPS)")
 
     if not args.no_serving:
         line["serving"] = serving_leg(ga, gen, ctx, args)

@@ -180,6 +180,27 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
                            const genasm_launch* launch, void* stream);
 
 /*
+ * Pre-alignment filter (score-only mode): the DC recurrence over the whole
+ * read, with no table and no traceback (GenASM-DC used as a filter ahead of
+ * alignment, the use the paper's introduction gives for edit-distance
+ * calculation). For pair i, dist[i] = the least edit distance between read i
+ * and any substring of reference i when that is at most k, else -1; start[i]
+ * = the least start of a reference substring at that distance (0 when
+ * rejected). k is in [0, 63]; reads are at most 1024 bases (GENASM_E_TOOLONG
+ * otherwise). Host form: ASCII streams and offsets as for genasm_batch_align,
+ * synchronous. Device form: 2-bit packed streams and offsets in device memory
+ * as for genasm_batch_align_dev, max_read_len an upper bound on the read
+ * lengths, dist/start in device memory, asynchronous on `stream`.
+ */
+int genasm_filter(genasm_ctx* ctx, const char* reads, const uint64_t* read_off, const char* refs,
+                  const uint64_t* ref_off, uint64_t n_pairs, int32_t k, int32_t* dist,
+                  uint32_t* start);
+int genasm_filter_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
+                      const uint8_t* d_refs2b, const uint64_t* d_ref_off, uint64_t n_pairs,
+                      uint32_t max_read_len, int32_t k, int32_t* d_dist, uint32_t* d_start,
+                      void* stream);
+
+/*
  * Packs n ASCII bases (host memory) into 2-bit codes (host memory, (n+3)/4
  * bytes, layout as for genasm_batch_align_dev). Returns GENASM_E_ALPHABET and
  * sets *bad_index (if not NULL) to the first offending byte.

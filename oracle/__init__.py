@@ -78,6 +78,9 @@ def load(path: str):
     L.oracle_align.restype = ctypes.c_int
     L.oracle_sellers.argtypes = [u8p, ctypes.c_uint32, u8p, ctypes.c_uint32]
     L.oracle_sellers.restype = ctypes.c_int64
+    L.oracle_filter.argtypes = [u8p, ctypes.c_uint32, u8p, ctypes.c_uint32, ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_uint32)]
+    L.oracle_filter.restype = ctypes.c_int32
     L.oracle_check_cigar.argtypes = [u8p, ctypes.c_uint32, u8p, ctypes.c_uint32,
                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_char_p,
                                      ctypes.c_uint32, ctypes.c_int32]
@@ -130,6 +133,16 @@ def sellers(P, T) -> int:
     P = _codes(P)
     T = _codes(T)
     return int(lib().oracle_sellers(_ptr(P), len(P), _ptr(T), len(T)))
+
+
+def filter_pair(P, T, k: int):
+    """Pre-alignment filter: (distance, leftmost start) of the best substring
+    of T for the whole read P, or (-1, 0) when the distance exceeds k."""
+    P, T = _codes(P), _codes(T)
+    st = ctypes.c_uint32(0)
+    d = int(lib().oracle_filter(_ptr(P), len(P), _ptr(T), len(T), int(k), ctypes.byref(st)))
+    assert d >= -1, "oracle_filter: out of memory"
+    return (d, int(st.value) if d >= 0 else 0)
 
 
 def check_cigar(P, T, begin: int, end: int, ops: str, score: int) -> int:

@@ -94,6 +94,39 @@ int64_t oracle_sellers(const uint8_t* P, uint32_t m, const uint8_t* T, uint32_t 
     return best;
 }
 
+int32_t oracle_filter(const uint8_t* P, uint32_t m, const uint8_t* T, uint32_t n, int32_t k,
+                      uint32_t* start) {
+    /* Reversed read P' and reference T': Lev(P, T[a..b)) = Lev(P', T'[n-b..n-a)).
+     * C[r][e] = min over s of Lev(P'[0..r), T'[s..e)), free start C[0][e] = 0;
+     * then the best substring starting at a costs C[m][n-a]. */
+    int64_t* prev = malloc(sizeof(int64_t) * ((size_t)n + 1));
+    int64_t* cur = malloc(sizeof(int64_t) * ((size_t)n + 1));
+    if (!prev || !cur) { free(prev); free(cur); return -2; }
+    for (uint32_t e = 0; e <= n; ++e) prev[e] = 0;
+    for (uint32_t r = 1; r <= m; ++r) {
+        const uint8_t pc = P[m - r];  /* P'[r-1] */
+        cur[0] = (int64_t)r;          /* r read bases against an empty substring */
+        for (uint32_t e = 1; e <= n; ++e) {
+            const uint8_t tc = T[n - e];  /* T'[e-1] */
+            int64_t diag = prev[e - 1] + (pc != tc);
+            int64_t up = prev[e] + 1;
+            int64_t left = cur[e - 1] + 1;
+            int64_t best = diag < up ? diag : up;
+            cur[e] = best < left ? best : left;
+        }
+        int64_t* t = prev; prev = cur; cur = t;
+    }
+    int64_t best = prev[0];
+    uint32_t best_e = 0;
+    for (uint32_t e = 1; e <= n; ++e) {
+        if (prev[e] <= best) { best = prev[e]; best_e = e; }  /* largest e: least a */
+    }
+    free(prev); free(cur);
+    if (best > k) return -1;
+    if (start) *start = n - best_e;
+    return (int32_t)best;
+}
+
 /* ------------------------------------------------------------------------ */
 /* CIGAR replay.                                                             */
 /* ------------------------------------------------------------------------ */

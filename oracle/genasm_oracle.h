@@ -19,6 +19,10 @@
  *                         "parity unpinned": no external source fixes it
  *                         beyond those properties.
  *   oracle_check_cigar    pinned by planted mistakes in tests.
+ *   oracle_filter         pinned: brute-force minimum over all substrings
+ *                         (distance and leftmost start) on tiny inputs,
+ *                         exact-occurrence and empty-read closed forms, and
+ *                         equality with oracle_sellers.
  */
 #ifndef GENASM_ORACLE_H
 #define GENASM_ORACLE_H
@@ -61,6 +65,14 @@ int oracle_align(int variant, const uint8_t* P, uint32_t m, const uint8_t* T, ui
                  oracle_result* res);
 
 /* Infix (Sellers) edit distance: min over a <= b of Levenshtein(P, T[a..b)). */
+/* Pre-alignment filter (score-only mode): d = the least edit distance between
+ * the whole read P and any substring T[a..b) of the reference. Returns d when
+ * d <= k, else -1; *start receives the least a with min_b Lev(P, T[a..b)) = d
+ * (when d <= k). Definition written out: a Sellers DP over the reversed
+ * strings, whose free start becomes the free end of the substring. */
+int32_t oracle_filter(const uint8_t* P, uint32_t m, const uint8_t* T, uint32_t n, int32_t k,
+                      uint32_t* start);
+
 int64_t oracle_sellers(const uint8_t* P, uint32_t m, const uint8_t* T, uint32_t n);
 
 /* Replays ops against P and T[begin..end). Returns 0 when the ops turn P into

@@ -139,7 +139,7 @@ EXPORTS = [
     "genasm_pack_dev", "genasm_validate", "genasm_version", "genasm_profile_enable",
     "genasm_profile_read", "genasm_server_create", "genasm_submit", "genasm_poll",
     "genasm_completion_release", "genasm_server_stats_read", "genasm_server_destroy",
-    "genasm_now_ns",
+    "genasm_now_ns", "genasm_filter", "genasm_filter_dev",
 ]
 
 _c = ctypes
@@ -176,6 +176,11 @@ _SIGS = {
     "genasm_server_stats_read": (_c.c_int, [_c.c_void_p, _c.POINTER(ServerStats)]),
     "genasm_server_destroy": (None, [_c.c_void_p]),
     "genasm_now_ns": (_c.c_uint64, []),
+    "genasm_filter": (_c.c_int, [_c.c_void_p, _c.c_char_p, _u64p, _c.c_char_p, _u64p, _c.c_uint64,
+                                 _c.c_int32, _c.c_void_p, _c.c_void_p]),
+    "genasm_filter_dev": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                     _c.c_void_p, _c.c_uint64, _c.c_uint32, _c.c_int32, _c.c_void_p,
+                                     _c.c_void_p, _c.c_void_p]),
 }
 
 _lib = None
@@ -364,6 +369,36 @@ class Context:
             ctypes.byref(launch) if launch is not None else None, stream)
         self._check(rc, "genasm_batch_align_dev")
         return out, cigar
+
+    def filter(self, reads, refs, k: int):
+        """Pre-alignment filter, host form. Returns (dist int32 array, start uint32 array)."""
+        r, roff = _concat(reads)
+        f, foff = _concat(refs)
+        n = len(roff) - 1
+        dist = np.zeros(n, dtype=np.int32)
+        start = np.zeros(n, dtype=np.uint32)
+        rc = lib().genasm_filter(self._ctx, r, roff.ctypes.data_as(_u64p), f,
+                                 foff.ctypes.data_as(_u64p), n, k, dist.ctypes.data,
+                                 start.ctypes.data)
+        self._check(rc, "genasm_filter")
+        return dist, start
+
+    def filter_dev(self, reads2b, read_off, refs2b, ref_off, k: int, max_read_len: int,
+                   dist=None, start=None, stream=None):
+        """Pre-alignment filter, device form on torch tensors."""
+        import torch
+        n = read_off.numel() - 1
+        if dist is None:
+            dist = torch.empty(max(n, 1), dtype=torch.int32, device=read_off.device)
+        if start is None:
+            start = torch.empty(max(n, 1), dtype=torch.int32, device=read_off.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(read_off.device).cuda_stream
+        rc = lib().genasm_filter_dev(self._ctx, reads2b.data_ptr(), read_off.data_ptr(),
+                                     refs2b.data_ptr(), ref_off.data_ptr(), n, max_read_len, k,
+                                     dist.data_ptr(), start.data_ptr(), stream)
+        self._check(rc, "genasm_filter_dev")
+        return dist, start
 
     def profile(self, on: bool = True):
         self._check(lib().genasm_profile_enable(self._ctx, int(on)), "genasm_profile_enable")

@@ -141,6 +141,14 @@ constexpr int kSearchGroupWords = kGroupHeaderWords;  // PM, ring, broadcast slo
 
 // Kernel launchers (kernels.hip). All return hipError_t of the launch.
 hipError_t launch_plain(const AlignParams& p, hipStream_t s);
+// Pre-alignment filter: dist[i] = least edit distance of read i against any
+// substring of reference i when <= k (k <= 63), else -1; start[i] = leftmost
+// start of such a substring. Reads up to 1024 bases (filter_words gives the
+// 64-bit words per row; 0 = too long).
+int filter_words(uint32_t max_read_len);
+hipError_t launch_filter(const uint8_t* reads, const uint64_t* read_off, const uint8_t* refs,
+                         const uint64_t* ref_off, uint64_t n_pairs, uint32_t max_read_len,
+                         int32_t k, int32_t* dist, uint32_t* start, hipStream_t s);
 // Unimproved form (ablation): one pair per workgroup, its window table (all
 // rows, four edge words per entry) in `table`, unimproved_table_words(n_pairs)
 // words of device memory.

@@ -733,6 +733,140 @@ __global__ __launch_bounds__(64) void k_plain(AlignParams P) {
 }
 
 // ---------------------------------------------------------------------------
+// Pre-alignment filter (score-only mode)
+// ---------------------------------------------------------------------------
+//
+// The DC recurrence over the whole read (an NW-word bit vector per row, bit p
+// = read base m-1-p) against the whole reference, with no table and no
+// traceback: the least row d <= k with a column whose top bit is clear is the
+// least edit distance between the read and any substring of the reference,
+// and the leftmost such column is where that substring starts. One pair per
+// 64-lane workgroup; lane d computes row d over an anti-diagonal wavefront of
+// the reference columns, as the start search does for one read window.
+
+__device__ __forceinline__ u64 init_word_at(int d, int w) {
+    // word w of the initial column of row d: bits below d are 0
+    const int lo = 64 * w;
+    return d >= lo + 64 ? 0ull : d <= lo ? ~0ull : (~0ull << (d - lo));
+}
+
+template <int NW>
+__global__ __launch_bounds__(64) void k_filter(const uint8_t* reads, const uint64_t* read_off,
+                                               const uint8_t* refs, const uint64_t* ref_off,
+                                               uint64_t n_pairs, int32_t K, int32_t* dist,
+                                               uint32_t* start) {
+    extern __shared__ u64 smem[];
+    u64* pm = smem;                                           // 4 x NW words (match masks first)
+    uint8_t* ring = reinterpret_cast<uint8_t*>(smem + 4 * NW);  // 128 text codes
+    u64* bc = smem + 4 * NW + 16;                             // broadcast slot
+    const int lane = threadIdx.x;
+    const uint64_t pair = blockIdx.x;
+    if (pair >= n_pairs) return;
+    const uint64_t rb = read_off[pair], fb = ref_off[pair];
+    const int m = (int)(read_off[pair + 1] - rb);
+    const int n = (int)(ref_off[pair + 1] - fb);
+    if (m == 0) {
+        if (lane == 0) { dist[pair] = 0; start[pair] = 0u; }
+        return;
+    }
+    // match masks: bit q of eq[c] is 1 iff read base m-1-q is c; PM[c] = ~eq[c]
+    for (int w = lane; w < 4 * NW; w += 64) pm[w] = 0ull;
+    wave_sync();
+    for (int b = lane; b < m; b += 64) {
+        const int q = m - 1 - b;
+        atomicOr(&pm[base_at(reads, rb + b) * NW + q / 64], 1ull << (q % 64));
+    }
+    wave_sync();
+    for (int w = lane; w < 4 * NW; w += 64) pm[w] = ~pm[w];
+    wave_sync();
+
+    const int d = lane;
+    u64 R[NW], Dp[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        R[w] = init_word_at(d, w);
+        Dp[w] = d == 0 ? ~0ull : init_word_at(d - 1, w);
+    }
+    const u64 lowin = d == 0 ? 1ull : 0ull;
+    const int top_w = (m - 1) / 64, top_b = (m - 1) % 64;
+    int hit = -1;
+    const int steps = n + 63;
+    const int nblk = (steps + 63) / 64;
+    for (int blk = 0; blk < nblk; ++blk) {
+        // codes of this block's 64 columns into the ring (the previous block's stay)
+        const int c = n - 64 * (blk + 1) + lane;
+        if (c >= 0 && c < n) ring[c & 127] = (uint8_t)base_at(refs, fb + c);
+        wave_sync();
+        for (int tt = 0; tt < 64; ++tt) {
+            const int t = blk * 64 + tt;
+            const int i = n - 1 - t + d;
+            const bool in = i >= 0 && i < n;
+            const int code = in ? ring[i & 127] : 0;
+            u64 up[NW], a[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                up[w] = LaneShift<64>::up(~0ull, R[w]);
+                a[w] = Dp[w] & up[w];
+            }
+            u64 Rn[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const u64 ash = (a[w] << 1) | (w ? (a[w - 1] >> 63) : lowin);
+                const u64 rsh = (R[w] << 1) | (w ? (R[w - 1] >> 63) : 0ull);
+                const u64 pmw = in ? pm[code * NW + w] : ~0ull;
+                Rn[w] = (Dp[w] & ash) & (rsh | pmw);
+            }
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                R[w] = Rn[w];
+                Dp[w] = up[w];
+            }
+            if (in && d <= K && !((R[top_w] >> top_b) & 1ull)) hit = i;  // columns fall: leftmost last
+        }
+        wave_sync();  // the next block overwrites ring entries of the block before last
+    }
+    // rows at or above m also match the empty substring at column n
+    if (hit < 0 && d >= m && d <= K) hit = n;
+    const u64 bits = __ballot(hit >= 0 && d <= K);
+    if (bits) {
+        const int row = __builtin_ctzll(bits);
+        if (lane == row) bc[0] = (u64)(unsigned)hit;
+        wave_sync();
+        if (lane == 0) {
+            dist[pair] = row;
+            start[pair] = (uint32_t)bc[0];
+        }
+    } else if (lane == 0) {
+        dist[pair] = -1;
+        start[pair] = 0u;
+    }
+}
+
+int filter_words(uint32_t max_read_len) {
+    return max_read_len <= 64 ? 1 : max_read_len <= 128 ? 2 : max_read_len <= 256 ? 4
+         : max_read_len <= 512 ? 8 : max_read_len <= 1024 ? 16 : 0;
+}
+
+hipError_t launch_filter(const uint8_t* reads, const uint64_t* read_off, const uint8_t* refs,
+                         const uint64_t* ref_off, uint64_t n_pairs, uint32_t max_read_len,
+                         int32_t k, int32_t* dist, uint32_t* start, hipStream_t s) {
+    if (n_pairs == 0) return hipSuccess;
+    const int NW = filter_words(max_read_len);
+    const int K = k < 63 ? k : 63;
+    const size_t lds = (4 * (size_t)NW + 16 + 1) * 8;
+    const dim3 grid((unsigned)n_pairs), block(64);
+    switch (NW) {
+        case 1: hipLaunchKernelGGL(k_filter<1>, grid, block, lds, s, reads, read_off, refs, ref_off, n_pairs, K, dist, start); break;
+        case 2: hipLaunchKernelGGL(k_filter<2>, grid, block, lds, s, reads, read_off, refs, ref_off, n_pairs, K, dist, start); break;
+        case 4: hipLaunchKernelGGL(k_filter<4>, grid, block, lds, s, reads, read_off, refs, ref_off, n_pairs, K, dist, start); break;
+        case 8: hipLaunchKernelGGL(k_filter<8>, grid, block, lds, s, reads, read_off, refs, ref_off, n_pairs, K, dist, start); break;
+        case 16: hipLaunchKernelGGL(k_filter<16>, grid, block, lds, s, reads, read_off, refs, ref_off, n_pairs, K, dist, start); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Unimproved form (ablation): the GenASM window without the three improvements
 // ---------------------------------------------------------------------------
 //

@@ -498,6 +498,93 @@ int genasm_profile_read(genasm_ctx* ctx, genasm_profile* out) {
     return GENASM_OK;
 }
 
+int genasm_filter_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
+                      const uint8_t* d_refs2b, const uint64_t* d_ref_off, uint64_t n_pairs,
+                      uint32_t max_read_len, int32_t k, int32_t* d_dist, uint32_t* d_start,
+                      void* stream) {
+    if (!ctx) return GENASM_E_INVAL;
+    if (k < 0 || k > 63) return set_err(ctx, GENASM_E_INVAL, "filter k must be in [0, 63]");
+    if (n_pairs == 0) return GENASM_OK;
+    if (n_pairs > 0xffffffffull) return set_err(ctx, GENASM_E_INVAL, "too many pairs");
+    if (!d_read_off || !d_ref_off || !d_dist || !d_start)
+        return set_err(ctx, GENASM_E_INVAL, "null pointer");
+    if (filter_words(max_read_len) == 0)
+        return set_err(ctx, GENASM_E_TOOLONG, "filter reads are limited to 1024 bases");
+    CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    CHECK_HIP(ctx, launch_filter(d_reads2b, d_read_off, d_refs2b, d_ref_off, n_pairs, max_read_len,
+                                 k, d_dist, d_start, (hipStream_t)stream));
+    return GENASM_OK;
+}
+
+int genasm_filter(genasm_ctx* ctx, const char* reads, const uint64_t* read_off, const char* refs,
+                  const uint64_t* ref_off, uint64_t n_pairs, int32_t k, int32_t* dist,
+                  uint32_t* start) {
+    if (!ctx) return GENASM_E_INVAL;
+    if (k < 0 || k > 63) return set_err(ctx, GENASM_E_INVAL, "filter k must be in [0, 63]");
+    if (!read_off || !ref_off || ((!dist || !start) && n_pairs))
+        return set_err(ctx, GENASM_E_INVAL, "null pointer");
+    int rc = check_offsets(read_off, n_pairs, UINT64_MAX);
+    if (!rc) rc = check_offsets(ref_off, n_pairs, UINT64_MAX);
+    if (rc) return set_err(ctx, rc, "bad offsets");
+    if (n_pairs == 0) return GENASM_OK;
+    if ((!reads && read_off[n_pairs] > read_off[0]) || (!refs && ref_off[n_pairs] > ref_off[0]))
+        return set_err(ctx, GENASM_E_INVAL, "null sequence pointer");
+    const uint64_t nr = read_off[n_pairs] - read_off[0];
+    const uint64_t nf = ref_off[n_pairs] - ref_off[0];
+    std::vector<uint64_t> roff(n_pairs + 1), foff(n_pairs + 1);
+    uint32_t max_read = 0;
+    for (uint64_t i = 0; i <= n_pairs; ++i) {
+        roff[i] = read_off[i] - read_off[0];
+        foff[i] = ref_off[i] - ref_off[0];
+        if (i) max_read = std::max<uint32_t>(max_read, (uint32_t)std::min<uint64_t>(roff[i] - roff[i - 1], 0xffffffffull));
+    }
+    if (filter_words(max_read) == 0)
+        return set_err(ctx, GENASM_E_TOOLONG, "filter reads are limited to 1024 bases");
+    CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    auto carve = [&](Carver& c) {
+        struct B {
+            char *ar, *af;
+            uint8_t *pr, *pf;
+            uint64_t *or_, *of;
+            int32_t* dist;
+            uint32_t *start, *bad;
+        } b;
+        b.ar = c.take<char>(nr + 1);
+        b.af = c.take<char>(nf + 1);
+        b.pr = c.take<uint8_t>(nr / 4 + 2);
+        b.pf = c.take<uint8_t>(nf / 4 + 2);
+        b.or_ = c.take<uint64_t>(n_pairs + 1);
+        b.of = c.take<uint64_t>(n_pairs + 1);
+        b.dist = c.take<int32_t>(n_pairs);
+        b.start = c.take<uint32_t>(n_pairs);
+        b.bad = c.take<uint32_t>(2);
+        return b;
+    };
+    Carver dry{nullptr};
+    carve(dry);
+    rc = ensure(ctx, &ctx->stage, &ctx->stage_cap, dry.off + 256);
+    if (rc) return rc;
+    Carver real{ctx->stage};
+    auto b = carve(real);
+    CHECK_HIP(ctx, hipMemsetAsync(b.bad, 0, 2 * sizeof(uint32_t), s));
+    if (nr) CHECK_HIP(ctx, hipMemcpyAsync(b.ar, reads + read_off[0], nr, hipMemcpyHostToDevice, s));
+    if (nf) CHECK_HIP(ctx, hipMemcpyAsync(b.af, refs + ref_off[0], nf, hipMemcpyHostToDevice, s));
+    CHECK_HIP(ctx, hipMemcpyAsync(b.or_, roff.data(), (n_pairs + 1) * 8, hipMemcpyHostToDevice, s));
+    CHECK_HIP(ctx, hipMemcpyAsync(b.of, foff.data(), (n_pairs + 1) * 8, hipMemcpyHostToDevice, s));
+    CHECK_HIP(ctx, launch_pack(b.ar, nr, b.pr, b.bad, s));
+    CHECK_HIP(ctx, launch_pack(b.af, nf, b.pf, b.bad, s));
+    uint32_t bad = 0;
+    CHECK_HIP(ctx, hipMemcpyAsync(&bad, b.bad, sizeof(bad), hipMemcpyDeviceToHost, s));
+    CHECK_HIP(ctx, hipStreamSynchronize(s));
+    if (bad) return set_err(ctx, GENASM_E_ALPHABET, "sequence byte outside ACGTacgt");
+    CHECK_HIP(ctx, launch_filter(b.pr, b.or_, b.pf, b.of, n_pairs, max_read, k, b.dist, b.start, s));
+    CHECK_HIP(ctx, hipMemcpyAsync(dist, b.dist, n_pairs * 4, hipMemcpyDeviceToHost, s));
+    CHECK_HIP(ctx, hipMemcpyAsync(start, b.start, n_pairs * 4, hipMemcpyDeviceToHost, s));
+    CHECK_HIP(ctx, hipStreamSynchronize(s));
+    return GENASM_OK;
+}
+
 int genasm_batch_align(genasm_ctx* ctx, const char* reads, const uint64_t* read_off,
                        const char* refs, const uint64_t* ref_off, uint64_t n_pairs,
                        int32_t k, int32_t W, int32_t O, genasm_result* out, char* cigar_buf,

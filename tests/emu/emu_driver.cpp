@@ -3,11 +3,12 @@
 // the device side of the serving loop).
 //
 //   emu_driver IN OUT
-// IN : int64 form (0 plain, 1 batched, 2 serving loop, 3 unimproved), group_lanes, search_lanes,
+// IN : int64 form (0 plain, 1 batched, 2 serving loop, 3 unimproved, 4 filter), group_lanes, search_lanes,
 //      lds_rows, k, W, O, n_pairs, read_bytes, ref_bytes, hard_row, window_budget,
 //      slots, admit_per_iteration, hard_lanes; then the packed read bytes, the
 //      packed reference bytes, read_off[n+1], ref_off[n+1] (uint64).
-// OUT: n genasm_result records, then (read bases + ref bases) CIGAR elements.
+// OUT: n genasm_result records, then (read bases + ref bases) CIGAR elements;
+//      for the filter, n int32 distances then n uint32 starts.
 #include "../../paper_2203_15561_amd/csrc/kernels.hip"
 
 #include <algorithm>
@@ -75,6 +76,24 @@ int main(int argc, char** argv) {
     p.ref_lo = flo.data();
     p.ref_hi = fhi.data();
     p.planes_from_off0 = serve ? 0 : 1;
+    if (form == 4) {
+        uint32_t max_m = 0;
+        for (uint64_t i = 0; i < n; ++i) max_m = std::max<uint32_t>(max_m, (uint32_t)(roff[i + 1] - roff[i]));
+        std::vector<int32_t> dist(n, -7);
+        std::vector<uint32_t> start(n, 7u);
+        emu::group_lanes = 64;
+        if (launch_filter(reads.data(), roff.data(), refs.data(), foff.data(), n, max_m, k,
+                          dist.data(), start.data(), nullptr) != hipSuccess) {
+            fprintf(stderr, "filter launch rejected\n");
+            return 3;
+        }
+        FILE* g = fopen(argv[2], "wb");
+        if (!g) { perror("open OUT"); return 2; }
+        fwrite(dist.data(), 4, n, g);
+        fwrite(start.data(), 4, n, g);
+        fclose(g);
+        return 0;
+    }
     if (form == 2) {
         // Serving loop, device side: slots are reused; each iteration admits
         // up to per_iter pairs into free slots, resets their state, advances the

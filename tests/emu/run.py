@@ -34,6 +34,7 @@ def pack2b(codes: np.ndarray) -> np.ndarray:
 
 SERVE = 2  # the device side of the serving loop (slot reuse, window budget)
 UNIMPROVED = 3  # the unimproved (ablation) form
+FILTER = 4      # the pre-alignment filter
 
 
 def run(driver: str, ps, form: int, group_lanes=16, search_lanes=16, lds_rows=16, hard_row=16,
@@ -58,3 +59,19 @@ def run(driver: str, ps, form: int, group_lanes=16, search_lanes=16, lds_rows=16
         e = cig[int(r["cigar_off"]):int(r["cigar_off"]) + int(r["cigar_len"])]
         out.append("".join(f"{int(x) >> 2}{'=XID'[int(x) & 3]}" for x in e))
     return res, out
+
+
+def run_filter(driver: str, ps, k: int, timeout=600):
+    """Returns (distances, starts) of the filter kernel under emulation."""
+    reads2b, refs2b = pack2b(ps.reads), pack2b(ps.refs)
+    hdr = np.array([FILTER, 64, 64, 64, k, ps.W, ps.O, ps.n_pairs, len(reads2b), len(refs2b),
+                    65, 0, 0, 0, 16], dtype=np.int64)
+    with tempfile.TemporaryDirectory() as tmp:
+        fin, fout = os.path.join(tmp, "in.bin"), os.path.join(tmp, "out.bin")
+        with open(fin, "wb") as f:
+            for a in (hdr, reads2b, refs2b, ps.read_off.astype(np.uint64), ps.ref_off.astype(np.uint64)):
+                f.write(np.ascontiguousarray(a).tobytes())
+        subprocess.run([driver, fin, fout], check=True, timeout=timeout)
+        raw = open(fout, "rb").read()
+    n = ps.n_pairs
+    return np.frombuffer(raw[:4 * n], dtype=np.int32), np.frombuffer(raw[4 * n:8 * n], dtype=np.uint32)

@@ -125,3 +125,27 @@ def test_serving_loop(driver, budget):
                 int(r["n_windows"])) for r, c in zip(res, cig)]
         bad = [i for i in range(ps.n_pairs) if want[i] != got[i]]
         assert not bad, (k, W, O, bad[:5], want[bad[0]], got[bad[0]])
+
+
+def test_filter_kernel(driver):
+    # multi-word rows (reads over 64 bases), empty reads and references, k caps
+    rng = np.random.default_rng(404)
+    reads, refs = [], []
+    for m, n in [(0, 5), (3, 0), (1, 1), (64, 70), (65, 90), (130, 150), (200, 180), (40, 300)]:
+        r = rng.integers(0, 4, m).astype(np.uint8)
+        if n >= m and m and rng.random() < 0.7:
+            a = int(rng.integers(0, n - m + 1))
+            t = rng.integers(0, 4, n).astype(np.uint8)
+            t[a:a + m] = r
+            for _ in range(int(rng.integers(0, 6))):
+                t[int(rng.integers(0, n))] = int(rng.integers(0, 4))
+        else:
+            t = rng.integers(0, 4, n).astype(np.uint8)
+        reads.append(r)
+        refs.append(t)
+    ps = gen.from_lists("filter", reads, refs, 10)
+    for k in (0, 5, 40):
+        dist, start = emu.run_filter(driver, ps, k)
+        for i in range(ps.n_pairs):
+            want = oracle.filter_pair(ps.read(i), ps.ref(i), k)
+            assert (int(dist[i]), int(start[i]) if dist[i] >= 0 else 0) == want, (i, k)

@@ -33,6 +33,10 @@ MUTANTS = {
     "sellers_mismatch_free": ("int64_t diag = prev[j - 1] + (P[r - 1] != T[j - 1]);",
                               "int64_t diag = prev[j - 1];"),
     "check_cigar_allows_x_on_equal": ("if (P[pi] == T[ti]) return -4;", ""),
+    "filter_rightmost_start": ("if (prev[e] <= best) { best = prev[e]; best_e = e; }",
+                               "if (prev[e] < best) { best = prev[e]; best_e = e; }"),
+    "filter_free_read_start": ("cur[0] = (int64_t)r;", "cur[0] = 0;"),
+    "filter_strings_not_reversed": ("const uint8_t tc = T[n - e];", "const uint8_t tc = T[e - 1];"),
 }
 
 PIN_TESTS = [
@@ -43,6 +47,7 @@ PIN_TESTS = [
     (pins.test_single_window_equals_sellers, ()),
     (pins.test_improved_equals_uncompressed_fuzz, ()),
     (pins.test_check_cigar_rejects_wrong_alignments, ()),
+    (pins.test_filter_matches_brute_force, ()),
 ]
 
 

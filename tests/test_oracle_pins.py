@@ -90,6 +90,41 @@ def test_sellers_closed_forms(oracle_lib):
 
 
 # --------------------------------------------------------------------------
+# Pre-alignment filter: best substring for the whole read
+# --------------------------------------------------------------------------
+
+def test_filter_matches_brute_force(oracle_lib):
+    # distance: least Levenshtein distance over every substring T[a:b];
+    # start: the least a that reaches it; -1 above k
+    rng = np.random.default_rng(17)
+    for _ in range(300):
+        P = rand_str(rng, int(rng.integers(0, 7)))
+        T = rand_str(rng, int(rng.integers(0, 10)))
+        best = {a: min(lev(P, T[a:b]) for b in range(a, len(T) + 1)) for a in range(len(T) + 1)}
+        d = min(best.values())
+        a0 = min(a for a, v in best.items() if v == d)
+        for k in (0, 1, 3, 10):
+            got = oracle_lib.filter_pair(P, T, k)
+            assert got == ((d, a0) if d <= k else (-1, 0)), (P, T, k, got, d, a0)
+
+
+def test_filter_closed_forms(oracle_lib):
+    rng = np.random.default_rng(18)
+    for _ in range(60):
+        T = rand_str(rng, int(rng.integers(1, 200)))
+        a = int(rng.integers(0, len(T)))
+        b = int(rng.integers(a + 1, len(T) + 1))
+        # an exact occurrence costs nothing and starts at its first occurrence
+        assert oracle_lib.filter_pair(T[a:b], T, 0) == (0, T.find(T[a:b]))
+        P = rand_str(rng, int(rng.integers(0, 60)))
+        assert oracle_lib.filter_pair("", T, 0) == (0, 0)
+        assert oracle_lib.filter_pair(P, "", len(P)) == (len(P), 0)
+        d, _ = oracle_lib.filter_pair(P, T, 1000)
+        assert d == oracle_lib.sellers(P, T)
+        assert oracle_lib.filter_pair(P, T, d - 1) == (-1, 0) if d > 0 else True
+
+
+# --------------------------------------------------------------------------
 # DC recurrence: every bit against its meaning
 # --------------------------------------------------------------------------
 
