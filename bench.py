@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--workers-per-cu", type=int, default=0)
     ap.add_argument("--hard-row", type=int, default=0)
     ap.add_argument("--hard-lanes", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default launch instead of the autotuner's pick")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB "
@@ -227,6 +229,17 @@ def main():
     torch.cuda.synchronize()
     assert int(bad.item()) == 0
     log("warm-up done")
+    tuned = None
+    if not args.no_autotune and not kw:
+        # the library's autotuner times its candidate launches on this batch
+        t0 = time.time()
+        batched, tms, _, _ = ctx.autotune_dev(reads2b, roff, refs2b, foff, ps.k, ps.W, ps.O,
+                                              out=out, cigar=cigar, reps=2, total_read_bases=nr,
+                                              total_ref_bases=nf, max_ref_len=max_ref)
+        tuned = {"tuner_seconds": time.time() - t0, "best_ms": tms}
+        log(f"autotune: hard_row {batched.hard_row}, hard_lanes {batched.hard_lanes}, lds_rows "
+            f"{batched.lds_rows}, workers_per_cu {batched.workers_per_cu}, search_lanes "
+            f"{batched.search_lanes} ({tms:.2f} ms) in {tuned['tuner_seconds']:.1f} s")
 
     # timed region: K steps, library profiling on (HIP events around each stage on
     # the same stream), one profile read per step for the window-kernel time
@@ -299,7 +312,9 @@ def main():
                    "pairs": ps.n_pairs, "k": ps.k, "W": ps.W, "O": ps.O, "form": "batched",
                    "group_lanes": batched.group_lanes, "lds_rows": batched.lds_rows,
                    "workers_per_cu": batched.workers_per_cu, "hard_row": batched.hard_row,
-                   "hard_lanes": batched.hard_lanes},
+                   "hard_lanes": batched.hard_lanes, "search_lanes": batched.search_lanes,
+                   "autotuned": tuned is not None},
+        "autotune": tuned,
         "gcups": cells / (ms_step / 1e3) / 1e9,
         "window_kernel_ms": float(np.mean(win_ms)),
         "search_ms": float(np.mean(search_ms)),

@@ -201,6 +201,30 @@ int genasm_filter_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t*
                       void* stream);
 
 /*
+ * Autotuner for the batched form. Runs the device-form call above on the given
+ * batch with each candidate launch configuration (lanes per pair for the
+ * decoy-like queue and its threshold row, table rows kept in LDS, resident
+ * workers per compute unit, lanes per pair in the start search), `reps` timed
+ * runs each after one untimed run, and writes the fastest to *best (and its
+ * time in ms to *best_ms if not NULL). Every run writes complete results, so
+ * d_out/d_cigar hold the batch's alignment afterwards. The pick is cached in
+ * the context under the batch's signature (pair count and mean read length to
+ * the nearest power of two below, k, W, O); later genasm_batch_align_dev and
+ * genasm_batch_align calls with launch == NULL and a matching signature use
+ * it. Synchronizes `stream`.
+ */
+int genasm_autotune_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
+                        const uint8_t* d_refs2b, const uint64_t* d_ref_off, uint64_t n_pairs,
+                        uint64_t total_read_bases, uint64_t total_ref_bases, uint32_t max_ref_len,
+                        int32_t k, int32_t W, int32_t O, genasm_result* d_out, uint32_t* d_cigar,
+                        uint64_t cigar_cap, int32_t reps, void* stream, genasm_launch* best,
+                        float* best_ms);
+/* Tuning cache as text, one signature per line; load merges into the context's cache. */
+int genasm_tune_cache_save(genasm_ctx* ctx, const char* path);
+int genasm_tune_cache_load(genasm_ctx* ctx, const char* path);
+int genasm_tune_cache_size(genasm_ctx* ctx);
+
+/*
  * Packs n ASCII bases (host memory) into 2-bit codes (host memory, (n+3)/4
  * bytes, layout as for genasm_batch_align_dev). Returns GENASM_E_ALPHABET and
  * sets *bad_index (if not NULL) to the first offending byte.

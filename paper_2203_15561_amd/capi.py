@@ -139,7 +139,8 @@ EXPORTS = [
     "genasm_pack_dev", "genasm_validate", "genasm_version", "genasm_profile_enable",
     "genasm_profile_read", "genasm_server_create", "genasm_submit", "genasm_poll",
     "genasm_completion_release", "genasm_server_stats_read", "genasm_server_destroy",
-    "genasm_now_ns", "genasm_filter", "genasm_filter_dev",
+    "genasm_now_ns", "genasm_filter", "genasm_filter_dev", "genasm_autotune_dev",
+    "genasm_tune_cache_save", "genasm_tune_cache_load", "genasm_tune_cache_size",
 ]
 
 _c = ctypes
@@ -176,6 +177,14 @@ _SIGS = {
     "genasm_server_stats_read": (_c.c_int, [_c.c_void_p, _c.POINTER(ServerStats)]),
     "genasm_server_destroy": (None, [_c.c_void_p]),
     "genasm_now_ns": (_c.c_uint64, []),
+    "genasm_autotune_dev": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                       _c.c_void_p, _c.c_uint64, _c.c_uint64, _c.c_uint64,
+                                       _c.c_uint32, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p,
+                                       _c.c_void_p, _c.c_uint64, _c.c_int32, _c.c_void_p,
+                                       _c.POINTER(Launch), _c.POINTER(_c.c_float)]),
+    "genasm_tune_cache_save": (_c.c_int, [_c.c_void_p, _c.c_char_p]),
+    "genasm_tune_cache_load": (_c.c_int, [_c.c_void_p, _c.c_char_p]),
+    "genasm_tune_cache_size": (_c.c_int, [_c.c_void_p]),
     "genasm_filter": (_c.c_int, [_c.c_void_p, _c.c_char_p, _u64p, _c.c_char_p, _u64p, _c.c_uint64,
                                  _c.c_int32, _c.c_void_p, _c.c_void_p]),
     "genasm_filter_dev": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
@@ -399,6 +408,43 @@ class Context:
                                      dist.data_ptr(), start.data_ptr(), stream)
         self._check(rc, "genasm_filter_dev")
         return dist, start
+
+    def autotune_dev(self, reads2b, read_off, refs2b, ref_off, k: int, W: int = 64, O: int = 24,
+                     out=None, cigar=None, reps: int = 1, stream=None, total_read_bases=None,
+                     total_ref_bases=None, max_ref_len: int = 0):
+        """Times the batched-form candidates on this batch; returns (Launch, ms, out, cigar)
+        and caches the pick for calls without an explicit launch."""
+        import torch
+        n = read_off.numel() - 1
+        if total_read_bases is None:
+            total_read_bases = int(read_off[-1] - read_off[0])
+        if total_ref_bases is None:
+            total_ref_bases = int(ref_off[-1] - ref_off[0])
+        if out is None:
+            out = torch.empty((max(n, 1), 32), dtype=torch.uint8, device=read_off.device)
+        cap = total_read_bases + total_ref_bases
+        if cigar is None:
+            cigar = torch.empty(max(cap, 1), dtype=torch.int32, device=read_off.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(read_off.device).cuda_stream
+        best = Launch()
+        ms = ctypes.c_float(0.0)
+        rc = lib().genasm_autotune_dev(
+            self._ctx, reads2b.data_ptr(), read_off.data_ptr(), refs2b.data_ptr(),
+            ref_off.data_ptr(), n, total_read_bases, total_ref_bases, max_ref_len, k, W, O,
+            out.data_ptr(), cigar.data_ptr(), cigar.numel(), reps, stream, ctypes.byref(best),
+            ctypes.byref(ms))
+        self._check(rc, "genasm_autotune_dev")
+        return best, float(ms.value), out, cigar
+
+    def tune_cache_save(self, path: str):
+        self._check(lib().genasm_tune_cache_save(self._ctx, path.encode()), "genasm_tune_cache_save")
+
+    def tune_cache_load(self, path: str):
+        self._check(lib().genasm_tune_cache_load(self._ctx, path.encode()), "genasm_tune_cache_load")
+
+    def tune_cache_size(self) -> int:
+        return int(lib().genasm_tune_cache_size(self._ctx))
 
     def profile(self, on: bool = True):
         self._check(lib().genasm_profile_enable(self._ctx, int(on)), "genasm_profile_enable")

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 
 #include "genasm.h"
@@ -34,6 +35,12 @@ struct genasm_ctx {
     size_t stats_cap = 0;
     uint64_t prof_pairs = 0;
     int prof_form = 0;
+    // autotuner cache: workload signature -> fastest launch and its time
+    struct Tuned {
+        genasm_launch launch;
+        float ms;
+    };
+    std::map<std::string, Tuned> tune;
 };
 
 namespace genasm {

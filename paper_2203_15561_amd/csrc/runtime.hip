@@ -95,6 +95,15 @@ bool valid_wko(int32_t k, int32_t W, int32_t O) {
     return W >= 2 && W <= 64 && O >= 0 && O < W && k >= 0;
 }
 
+// Workload signature of a batch for the tuning cache: powers of two of the
+// pair count and of the mean read length, and k, W, O.
+std::string tune_key(uint64_t n_pairs, uint64_t total_read_bases, int32_t k, int32_t W, int32_t O) {
+    auto lg = [](uint64_t x) { int e = 0; while (x > 1) { x >>= 1; ++e; } return e; };
+    const uint64_t mean = n_pairs ? total_read_bases / n_pairs : 0;
+    return "n" + std::to_string(lg(n_pairs)) + "_m" + std::to_string(lg(mean)) + "_k" +
+           std::to_string(std::min(k, W)) + "_W" + std::to_string(W) + "_O" + std::to_string(O);
+}
+
 int resolve_launch(const genasm_launch* in, genasm_launch* out) {
     genasm_default_launch(in ? in->form : GENASM_FORM_BATCHED, out);
     if (!in) return GENASM_OK;
@@ -304,6 +313,10 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     if (cigar_cap < total_read_bases + total_ref_bases)
         return set_err(ctx, GENASM_E_NOSPACE, "cigar_cap below total read + reference bases");
     genasm_launch L;
+    if (!launch && !ctx->tune.empty()) {
+        auto it = ctx->tune.find(tune_key(n_pairs, total_read_bases, k, W, O));
+        if (it != ctx->tune.end()) launch = &it->second.launch;
+    }
     int rc = resolve_launch(launch, &L);
     if (rc) return set_err(ctx, rc, "bad launch parameters");
     hipStream_t s = (hipStream_t)stream;  // NULL: the null stream
@@ -454,6 +467,113 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     CHECK_HIP(ctx, mark(3));
     return GENASM_OK;
 }
+
+int genasm_autotune_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
+                        const uint8_t* d_refs2b, const uint64_t* d_ref_off, uint64_t n_pairs,
+                        uint64_t total_read_bases, uint64_t total_ref_bases, uint32_t max_ref_len,
+                        int32_t k, int32_t W, int32_t O, genasm_result* d_out, uint32_t* d_cigar,
+                        uint64_t cigar_cap, int32_t reps, void* stream, genasm_launch* best,
+                        float* best_ms) {
+    if (!ctx || !best) return GENASM_E_INVAL;
+    if (reps < 1) reps = 1;
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    // Candidates: lanes per pair for the decoy-like queue (16: four pairs per
+    // wavefront; 64: one) and its start-row threshold, table rows kept in LDS
+    // per 16-lane group (the rest spill), and resident workers per CU.
+    std::vector<genasm_launch> cands;
+    auto add = [&](int hard_row, int hard_lanes, int lds_rows, int workers, int search_lanes) {
+        genasm_launch c;
+        genasm_default_launch(GENASM_FORM_BATCHED, &c);
+        c.hard_row = hard_row;
+        c.hard_lanes = hard_lanes;
+        c.lds_rows = lds_rows;
+        c.workers_per_cu = workers;
+        c.search_lanes = search_lanes;
+        cands.push_back(c);
+    };
+    for (int hr : {12, 16, 24, 65}) add(hr, 16, 16, 0, 16);
+    add(16, 64, 16, 0, 16);
+    add(0, 64, 16, 0, 16);     // every pair one per wavefront
+    add(16, 16, 32, 0, 16);
+    add(16, 16, 16, 4, 16);
+    add(16, 16, 16, 0, 64);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    CHECK_HIP(ctx, hipEventCreate(&e0));
+    CHECK_HIP(ctx, hipEventCreate(&e1));
+    int rc = GENASM_OK;
+    float best_t = 1e30f;
+    for (const genasm_launch& c : cands) {
+        // a first run sizes the scratch for this shape, then timed runs
+        rc = genasm_batch_align_dev(ctx, d_reads2b, d_read_off, d_refs2b, d_ref_off, n_pairs,
+                                    total_read_bases, total_ref_bases, max_ref_len, k, W, O, d_out,
+                                    d_cigar, cigar_cap, &c, stream);
+        if (rc) break;
+        float t_min = 1e30f;
+        for (int r = 0; r < reps && !rc; ++r) {
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = GENASM_E_DEVICE; break; }
+            rc = genasm_batch_align_dev(ctx, d_reads2b, d_read_off, d_refs2b, d_ref_off, n_pairs,
+                                        total_read_bases, total_ref_bases, max_ref_len, k, W, O,
+                                        d_out, d_cigar, cigar_cap, &c, stream);
+            float ms = 0.f;
+            if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = GENASM_E_DEVICE;
+            t_min = std::min(t_min, ms);
+        }
+        if (rc) break;
+        if (t_min < best_t) {
+            best_t = t_min;
+            *best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc == GENASM_E_DEVICE ? set_err(ctx, rc, "autotune timing failed") : rc;
+    ctx->tune[tune_key(n_pairs, total_read_bases, k, W, O)] = genasm_ctx::Tuned{*best, best_t};
+    if (best_ms) *best_ms = best_t;
+    return GENASM_OK;
+}
+
+int genasm_tune_cache_save(genasm_ctx* ctx, const char* path) {
+    if (!ctx || !path) return GENASM_E_INVAL;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return set_err(ctx, GENASM_E_INVAL, "cannot open tune cache file for writing");
+    std::fprintf(f, "# key form group_lanes search_lanes lds_rows workers_per_cu lpt_order hard_row "
+                    "hard_lanes ms\n");
+    for (const auto& kv : ctx->tune) {
+        const genasm_launch& L = kv.second.launch;
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %.4f\n", kv.first.c_str(), L.form, L.group_lanes,
+                     L.search_lanes, L.lds_rows, L.workers_per_cu, L.lpt_order, L.hard_row,
+                     L.hard_lanes, kv.second.ms);
+    }
+    const bool ok = std::fclose(f) == 0;
+    return ok ? GENASM_OK : set_err(ctx, GENASM_E_INVAL, "writing the tune cache failed");
+}
+
+int genasm_tune_cache_load(genasm_ctx* ctx, const char* path) {
+    if (!ctx || !path) return GENASM_E_INVAL;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return set_err(ctx, GENASM_E_INVAL, "cannot open tune cache file");
+    char line[512];
+    int rc = GENASM_OK;
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        char key[256];
+        genasm_launch L{};
+        float ms = 0.f;
+        const int got = std::sscanf(line, "%255s %d %d %d %d %d %d %d %d %f", key, &L.form,
+                                    &L.group_lanes, &L.search_lanes, &L.lds_rows,
+                                    &L.workers_per_cu, &L.lpt_order, &L.hard_row, &L.hard_lanes, &ms);
+        genasm_launch chk;
+        if (got != 10 || resolve_launch(&L, &chk) != GENASM_OK) { rc = GENASM_E_INVAL; break; }
+        ctx->tune[key] = genasm_ctx::Tuned{L, ms};
+    }
+    std::fclose(f);
+    return rc ? set_err(ctx, rc, "malformed tune cache line") : GENASM_OK;
+}
+
+int genasm_tune_cache_size(genasm_ctx* ctx) { return ctx ? (int)ctx->tune.size() : GENASM_E_INVAL; }
 
 int genasm_profile_enable(genasm_ctx* ctx, int on) {
     if (!ctx) return GENASM_E_INVAL;

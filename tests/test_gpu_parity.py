@@ -270,3 +270,38 @@ def test_work_counters_match_oracle(ctx, form, variant):
     assert pr["windows"] == int(res["n_windows"].sum())
     if variant == "uncompressed":
         assert pr["tb_reads"] == int(res["words_read"].sum())
+
+
+def test_autotune_picks_caches_and_reloads(ctx, tmp_path):
+    import torch
+    ps = gen.make("uneven", 400, start=1200)
+    want = expected(ps)
+    dev = torch.device("cuda:0")
+    r2 = torch.from_numpy(ga.pack(ps.reads)).to(dev)
+    f2 = torch.from_numpy(ga.pack(ps.refs)).to(dev)
+    ro = torch.from_numpy(ps.read_off.astype(np.int64)).to(dev)
+    fo = torch.from_numpy(ps.ref_off.astype(np.int64)).to(dev)
+    tctx = ga.Context(0)
+    try:
+        best, ms, out, cigar = tctx.autotune_dev(r2, ro, f2, fo, ps.k)
+        torch.cuda.synchronize()
+        assert ms > 0 and tctx.tune_cache_size() == 1
+        assert best.form == ga.FORM_BATCHED
+        assert_same(ps, want, _decode_dev(out, cigar, ps.n_pairs), "autotune runs")
+        # a call without a launch takes the cached pick; results are unchanged
+        out.zero_()
+        tctx.align_dev(r2, ro, f2, fo, ps.k, out=out, cigar=cigar)
+        torch.cuda.synchronize()
+        assert_same(ps, want, _decode_dev(out, cigar, ps.n_pairs), "cached launch")
+        path = str(tmp_path / "tune.txt")
+        tctx.tune_cache_save(path)
+        fields = [ln.split() for ln in open(path) if not ln.startswith("#")]
+        assert len(fields) == 1 and int(fields[0][7]) == best.hard_row
+        other = ga.Context(0)
+        try:
+            other.tune_cache_load(path)
+            assert other.tune_cache_size() == 1
+        finally:
+            other.close()
+    finally:
+        tctx.close()
