@@ -28,6 +28,26 @@ if ROOT not in sys.path:
 # int32 VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 INT32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
+# HBM traffic of the window kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# scaled by a copy kernel of known size; valid only for the kernel source it was
+# measured on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_windows_long10k_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2203_15561_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic(workload: str):
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(KERNEL_SRC, "rb") as f:
+            src_hash = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_sha256") != src_hash or rec.get("workload") != workload:
+        return None  # the kernel changed since the counters were taken
+    return rec
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -325,6 +345,13 @@ def main():
         "work": {k: int(v) for k, v in pr.items() if not k.endswith("_ms")},
         "verified_pairs": verified,
     }
+
+    traffic = measured_traffic(args.workload) if ps.n_pairs == 20000 else None
+    if traffic:
+        line["roofline"]["traffic"] = traffic["hbm_bytes_per_launch"]
+        line["roofline"]["traffic_detail"] = {k: traffic[k] for k in
+                                              ("fetch_bytes", "write_bytes", "fetch_scale",
+                                               "write_scale", "source")}
 
     if not args.no_plain:
         torch.cuda.synchronize()
