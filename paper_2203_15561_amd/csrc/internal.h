@@ -97,8 +97,12 @@ struct AlignParams {
     SearchOut* search;          // per pair
     const uint32_t* order;      // window-kernel pair order (null = identity)
     uint32_t* counters;         // device queue heads and list lengths (see kCounter*)
-    const uint32_t* list_in;    // search kernel: pairs to search (null = all pairs)
-    uint32_t* list_out;         // search kernel: pairs that need more rows
+    const uint32_t* list_in;    // search items / finalize: pairs to search (null = all pairs)
+    uint32_t* list_out;         // (unused)
+    const uint64_t* items_in;   // search stage: (pair << 24 | chunk) items to search
+    uint64_t* items_out;        // search: items for the next stage (or stage 0, from k_search_items)
+    unsigned long long* search_key;  // per pair: least (row << 32 | column) hit found so far
+    uint32_t search_chunk;      // reference columns per search item (0 = whole reference)
     unsigned long long* spill;  // window table rows >= lds_rows, per worker
     int32_t lds_rows;
     int32_t list_slot;          // which counters[] pair this search stage uses
@@ -137,6 +141,7 @@ constexpr int kCounterEasyLen = 10;
 constexpr int kCounterEasyHead = 11;
 constexpr int kCounterHardLen = 12;
 constexpr int kCounterHardHead = 13;
+constexpr int kCounterPairs = 14;    // pairs the search items / finalize kernels walk
 constexpr int kCounterCount = 16;
 
 // LDS words per group, by kernel.
@@ -166,7 +171,19 @@ hipError_t launch_search(const AlignParams& p, int group_lanes, int rows_per_lan
 hipError_t launch_windows(const AlignParams& p, int blocks, hipStream_t s);
 hipError_t launch_pack(const char* ascii, uint64_t n, uint8_t* packed, uint32_t* bad,
                        hipStream_t s);
-hipError_t launch_init_counters(uint32_t* counters, uint32_t stage0_len, hipStream_t s);
+hipError_t launch_init_counters(uint32_t* counters, uint32_t n_pairs, hipStream_t s);
+// Start search: stage-0 items of the listed pairs (list_in, count in
+// counters[kCounterPairs]; all pairs when list_in is null), the stages, then
+// the per-pair outcome and window routing.
+hipError_t launch_search_items(const AlignParams& p, uint32_t max_pairs, hipStream_t s);
+hipError_t launch_search_finalize(const AlignParams& p, uint32_t max_pairs, hipStream_t s);
+// Reference columns per start-search item: batched calls and the serving loop.
+constexpr uint32_t kBatchSearchChunk = 4096;
+constexpr uint32_t kServeSearchChunk = 1024;
+// Upper bound of the search items of a batch.
+inline uint64_t search_item_cap(uint64_t n_pairs, uint64_t total_ref_bases, uint32_t chunk) {
+    return chunk ? n_pairs + total_ref_bases / chunk + 1 : n_pairs + 1;
+}
 // Serving: stage-0 search list length and the easy window list length come
 // from a device parameter block (set by a copy before the launch or a replay).
 hipError_t launch_init_counters_dev(uint32_t* counters, const uint32_t* params, hipStream_t s);

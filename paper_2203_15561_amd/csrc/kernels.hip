@@ -265,7 +265,7 @@ __device__ void dc_pass(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int
 // column, or row = -1 when rows 0..min(Kr, RS*G-1) have none.
 template <int G, int RS>
 __device__ void search_rows(u64* lds, int gl, int lane, const uint8_t* refs, uint64_t fb, int n,
-                            int m1, int Kr, int* row_out, int* col_out) {
+                            int m1, int Kr, int* row_out, int* col_out, int out_hi = 0x7fffffff) {
     const u64 p0 = lds[OFF_PM + 0], p1 = lds[OFF_PM + 1], p2 = lds[OFF_PM + 2],
               p3 = lds[OFF_PM + 3];
     u64* ring = lds + OFF_RING;
@@ -327,7 +327,7 @@ __device__ void search_rows(u64* lds, int gl, int lane, const uint8_t* refs, uin
                 const u64 x = Dp[s] & (((Dp[s] & up) << 1) | li);
                 R[s] = x & ((R[s] << 1) | pm_t);
                 Dp[s] = up;
-                const bool h = i >= 0 && !((R[s] >> top) & 1ull);
+                const bool h = i >= 0 && i < out_hi && !((R[s] >> top) & 1ull);
                 hit[s] = h ? i : hit[s];
             }
         }
@@ -1096,6 +1096,39 @@ __device__ __forceinline__ uint32_t group_pop(uint32_t* head, u64* lds, int gl) 
     return v;
 }
 
+// Start search over reference chunks. An item is (pair, chunk): chunk c's
+// output columns are [cC, min(n, (c+1)C)) for C = search_chunk (the whole
+// reference when 0). R[d][i] depends only on T[i .. i + m1 + d), so the chunk
+// scans its output columns plus the next m1 + 64 columns with the text end put
+// there, which gives exactly the full-reference values on its output columns.
+// Each chunk's least hit row and leftmost hit column go into the pair's key
+// (row << 32 | column) by an atomic minimum; the least key over the chunks is
+// the full search's answer (least row, then leftmost column).
+__device__ __forceinline__ uint32_t search_pairs(const AlignParams& P) {
+    return P.list_in ? __hip_atomic_load(P.counters + kCounterPairs, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT)
+                     : (uint32_t)P.n_pairs;
+}
+
+__device__ __forceinline__ uint32_t search_chunks(const AlignParams& P, int n) {
+    return P.search_chunk ? max(1u, ((uint32_t)n + P.search_chunk - 1) / P.search_chunk) : 1u;
+}
+
+// One thread per pair of the list (or of the batch): clears the pair's key and
+// appends its chunk items to the stage-0 item list.
+__global__ void k_search_items(AlignParams P) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n_items = search_pairs(P);
+    if (k >= n_items) return;
+    const uint64_t pair = P.list_in ? P.list_in[k] : k;
+    P.search_key[pair] = ~0ull;
+    const PairCursor pc = pair_cursor(P, pair);
+    if (pc.m == 0) return;  // settled by the finalize kernel
+    const uint32_t nc = search_chunks(P, pc.n);
+    const uint32_t at = atomicAdd(P.counters + kCounterListBase, nc);
+    for (uint32_t c = 0; c < nc; ++c) P.items_out[at + c] = (pair << 24) | c;
+}
+
 template <int G, int RS>
 __global__ __launch_bounds__(64) void k_search(AlignParams P) {
     extern __shared__ u64 smem[];
@@ -1105,53 +1138,109 @@ __global__ __launch_bounds__(64) void k_search(AlignParams P) {
     uint32_t* len_in = P.counters + kCounterListBase + 2 * P.list_slot;
     uint32_t* head = len_in + 1;
     uint32_t* len_out = len_in + 2;
-    const uint32_t n_items = P.list_in ? __hip_atomic_load(len_in, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT)
-                                       : (uint32_t)P.n_pairs;
+    const uint32_t n_items = __hip_atomic_load(len_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int rows_before = P.list_slot == 0 ? 0 : (P.list_slot == 1 ? 16 : 32);
     // A group takes at most n_items items, which bounds the loop.
     for (uint32_t iter = 0; iter <= n_items; ++iter) {
         const uint32_t item = group_pop(head, lds, gl);
         if (item >= n_items) break;
-        const uint64_t pair = P.list_in ? P.list_in[item] : item;
+        const uint64_t it = P.items_in[item];
+        const uint64_t pair = it >> 24;
+        const uint32_t chunk = (uint32_t)(it & 0xffffffull);
+        if (rows_before && (P.search_key[pair] >> 32) < (uint64_t)rows_before)
+            continue;  // an earlier stage already found the pair's least row
         const PairCursor pc = pair_cursor(P, pair);
-        if (pc.m == 0) {
-            if (gl == 0) {
-                finish_without_windows(P, pair, 0);
-                P.search[pair] = SearchOut{kSearchDone, 0};
-            }
-            continue;
-        }
         const int m1 = min(P.W, pc.m);
         const int Kr = min(P.K, m1 - 1);
+        const int c0 = P.search_chunk ? (int)(chunk * P.search_chunk) : 0;
+        const int c1 = P.search_chunk ? min(pc.n, c0 + (int)P.search_chunk) : pc.n;
+        const int e = min(pc.n, c1 + m1 + 64);
         build_pm<G>(lds, gl, P.reads, pc.rb, m1, false);
         int row, col;
-        search_rows<G, RS>(lds, gl, lane, P.refs, pc.fb, pc.n, m1, Kr, &row, &col);
+        search_rows<G, RS>(lds, gl, lane, P.refs, pc.fb + c0, e - c0, m1, Kr, &row, &col, c1 - c0);
         if (gl == 0) {
-            const bool final = row >= 0 || Kr < RS * G;
-            const int srow = row >= 0 ? row : (m1 <= P.K ? m1 : Kr);
-            search_stats(P, pair, pc.n, m1, final ? srow : 0, (u64)G * RS * (pc.n + RS * G - 1),
-                         P.list_slot == 0);
-            if (row < 0 && !final) {
+            if (P.stats)
+                atomicAdd(P.stats + pair * kStatCount + kStatSearchLaneSteps,
+                          (u64)G * RS * (u64)(e - c0 + RS * G - 1));
+            if (row >= 0) {
+                atomicMin(P.search_key + pair, ((u64)(unsigned)row << 32) | (u64)(unsigned)(c0 + col));
+            } else if (Kr >= RS * G) {
                 const uint32_t pos = atomicAdd(len_out, 1u);
-                P.list_out[pos] = (uint32_t)pair;
-                P.search[pair] = SearchOut{kSearchPending, 0};
-            } else if (row < 0 && m1 > P.K) {
-                // every needed row was computed without a hit: the pair fails
-                finish_without_windows(P, pair, -1);
-                P.search[pair] = SearchOut{kSearchFailed, 0};
-            } else {
-                // a hit, or row m1 (every column hits there); route to a window queue
-                const int r = row >= 0 ? row : m1;
-                P.search[pair] = SearchOut{r, row >= 0 ? (uint32_t)col : 0u};
-                if (P.route) {
-                    const bool hard = r >= P.hard_row;
-                    uint32_t* len = P.counters + (hard ? kCounterHardLen : kCounterEasyLen);
-                    const uint32_t pos = atomicAdd(len, 1u);
-                    (hard ? P.hard_list : P.easy_list)[pos] = (uint32_t)pair;
-                }
+                P.items_out[pos] = it;
             }
         }
     }
+}
+
+// The search outcome of one pair from its key: ends the pairs that need no
+// window (empty read: score 0; no hit within K rows: -1) and returns the start
+// row of the others (-1 for the ended ones).
+__device__ int search_outcome(const AlignParams& P, uint64_t pair) {
+    const PairCursor pc = pair_cursor(P, pair);
+    if (pc.m == 0) {
+        finish_without_windows(P, pair, 0);
+        P.search[pair] = SearchOut{kSearchDone, 0};
+        return -1;
+    }
+    const int m1 = min(P.W, pc.m);
+    const u64 key = P.search_key[pair];
+    int row, col;
+    if (key != ~0ull) {
+        row = (int)(key >> 32);
+        col = (int)(uint32_t)key;
+    } else if (m1 <= P.K) {
+        row = m1;  // row m1 hits in every column
+        col = 0;
+    } else {
+        row = -1;
+        col = 0;
+    }
+    if (P.stats) {
+        u64* st = P.stats + pair * kStatCount;
+        st[kStatSearchWordOps] = (u64)pc.n * (2 + 6 * (u64)(row >= 0 ? row : min(P.K, m1 - 1)));
+        st[kStatSearchCells] = (u64)m1 * pc.n;
+    }
+    if (row < 0) {
+        finish_without_windows(P, pair, -1);
+        P.search[pair] = SearchOut{kSearchFailed, 0};
+        return -1;
+    }
+    P.search[pair] = SearchOut{row, (uint32_t)col};
+    return row;
+}
+
+// Appends the calling lanes with `want` set to a device list with one atomic
+// per wavefront; returns each such lane's position.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* len, bool want) {
+    const u64 bits = __ballot(want);
+    const int lane = threadIdx.x & 63;
+    const int leader = bits ? __builtin_ctzll(bits) : 0;
+    uint32_t base = 0;
+    if (want && lane == leader) base = atomicAdd(len, (uint32_t)__builtin_popcountll(bits));
+    base = __shfl(base, leader);
+    return base + (uint32_t)__builtin_popcountll(bits & ((1ull << lane) - 1ull));
+}
+
+// One thread per pair of the list (or of the batch): the pair's search outcome,
+// then its window queue (one device atomic per wavefront and queue).
+__global__ void k_search_finalize(AlignParams P) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n_items = search_pairs(P);
+    bool easy = false, hard = false;
+    uint64_t pair = 0;
+    if (k < n_items) {
+        pair = P.list_in ? P.list_in[k] : k;
+        const int row = search_outcome(P, pair);
+        if (row >= 0 && P.route) {
+            hard = row >= P.hard_row;
+            easy = !hard;
+        }
+    }
+    if (!P.route) return;
+    const uint32_t pe = wave_append(P.counters + kCounterEasyLen, easy);
+    const uint32_t ph = wave_append(P.counters + kCounterHardLen, hard);
+    if (easy) P.easy_list[pe] = (uint32_t)pair;
+    if (hard) P.hard_list[ph] = (uint32_t)pair;
 }
 
 // Window kernel of the batched form. Each workgroup is one wavefront. Pairs
@@ -1232,9 +1321,9 @@ __global__ void k_pack(const char* ascii, uint64_t n, uint8_t* packed, uint32_t*
 // Resets the queue heads and list lengths; stage 0's list length is set when
 // stage 0 walks an explicit list. A kernel rather than a memset so that the
 // whole pipeline can be captured in a graph.
-__global__ void k_init_counters(uint32_t* counters, uint32_t stage0_len) {
+__global__ void k_init_counters(uint32_t* counters, uint32_t n_pairs) {
     const int i = threadIdx.x;
-    if (i < kCounterCount) counters[i] = i == kCounterListBase ? stage0_len : 0u;
+    if (i < kCounterCount) counters[i] = i == kCounterPairs ? n_pairs : 0u;
 }
 
 __global__ void k_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v) {
@@ -1333,7 +1422,7 @@ __global__ void k_gather_runs(const genasm_result* out, const uint32_t* list, ui
 __global__ void k_init_counters_dev(uint32_t* counters, const uint32_t* params) {
     const int i = threadIdx.x;
     if (i < kCounterCount)
-        counters[i] = i == kCounterListBase ? params[0] : i == kCounterEasyLen ? params[1] : 0u;
+        counters[i] = i == kCounterPairs ? params[0] : i == kCounterEasyLen ? params[1] : 0u;
 }
 
 // Longest-first order by a counting sort over length buckets: bucket 0 holds
@@ -1348,10 +1437,19 @@ __device__ __forceinline__ uint32_t lpt_bucket(uint64_t len) {
     return kLptBuckets - 2 - key;
 }
 
+// Per-block bucket counts in LDS, then one device atomic per (block, bucket):
+// most pairs of a batch share a few buckets, so per-pair device atomics would
+// serialize on them.
 __global__ void k_lpt_count(const uint64_t* read_off, uint64_t n_pairs, uint32_t* hist) {
+    extern __shared__ u64 smem[];
+    uint32_t* lh = reinterpret_cast<uint32_t*>(smem);
+    for (int t = threadIdx.x; t < kLptBuckets; t += blockDim.x) lh[t] = 0u;
+    __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pairs) return;
-    atomicAdd(&hist[lpt_bucket(read_off[i + 1] - read_off[i])], 1u);
+    if (i < n_pairs) atomicAdd(&lh[lpt_bucket(read_off[i + 1] - read_off[i])], 1u);
+    __syncthreads();
+    for (int t = threadIdx.x; t < kLptBuckets; t += blockDim.x)
+        if (lh[t]) atomicAdd(&hist[t], lh[t]);
 }
 
 // Exclusive prefix sum of the bucket counts, in place (one block of kLptBuckets threads).
@@ -1369,12 +1467,26 @@ __global__ void k_lpt_scan(uint32_t* hist) {
     hist[t] = t == 0 ? 0u : v[t - 1];
 }
 
+// Places pairs at their bucket positions: each block reserves one range per
+// bucket it holds (one device atomic per bucket), then numbers its pairs
+// inside the ranges with LDS atomics.
 __global__ void k_lpt_place(const uint64_t* read_off, uint64_t n_pairs, uint32_t* pos,
                             uint32_t* order) {
+    extern __shared__ u64 smem[];
+    uint32_t* lh = reinterpret_cast<uint32_t*>(smem);  // counts, then base positions
+    uint32_t* lpos = lh + kLptBuckets;
+    for (int t = threadIdx.x; t < kLptBuckets; t += blockDim.x) lh[t] = 0u;
+    __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pairs) return;
-    const uint32_t at = atomicAdd(&pos[lpt_bucket(read_off[i + 1] - read_off[i])], 1u);
-    order[at] = (uint32_t)i;
+    const uint32_t b = i < n_pairs ? lpt_bucket(read_off[i + 1] - read_off[i]) : 0u;
+    if (i < n_pairs) atomicAdd(&lh[b], 1u);
+    __syncthreads();
+    for (int t = threadIdx.x; t < kLptBuckets; t += blockDim.x) {
+        lpos[t] = lh[t] ? atomicAdd(&pos[t], lh[t]) : 0u;
+        lh[t] = 0u;
+    }
+    __syncthreads();
+    if (i < n_pairs) order[lpos[b] + atomicAdd(&lh[b], 1u)] = (uint32_t)i;
 }
 
 __global__ void k_zero_u32(uint32_t* p, uint32_t n) {
@@ -1433,6 +1545,18 @@ hipError_t launch_search(const AlignParams& p, int group_lanes, int rows_per_lan
     } else {
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_search_items(const AlignParams& p, uint32_t max_pairs, hipStream_t s) {
+    if (max_pairs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_search_items, dim3((max_pairs + 255) / 256), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_search_finalize(const AlignParams& p, uint32_t max_pairs, hipStream_t s) {
+    if (max_pairs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_search_finalize, dim3((max_pairs + 255) / 256), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 
@@ -1512,9 +1636,10 @@ hipError_t launch_lpt_order(const uint64_t* read_off, uint64_t n_pairs, uint32_t
     if (n_pairs == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((n_pairs + 255) / 256);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kLptBuckets), 0, s, hist, (uint32_t)kLptBuckets);
-    hipLaunchKernelGGL(k_lpt_count, dim3(blocks), dim3(256), 0, s, read_off, n_pairs, hist);
+    hipLaunchKernelGGL(k_lpt_count, dim3(blocks), dim3(256), kLptBuckets * 4, s, read_off, n_pairs, hist);
     hipLaunchKernelGGL(k_lpt_scan, dim3(1), dim3(kLptBuckets), 0, s, hist);
-    hipLaunchKernelGGL(k_lpt_place, dim3(blocks), dim3(256), 0, s, read_off, n_pairs, hist, order);
+    hipLaunchKernelGGL(k_lpt_place, dim3(blocks), dim3(256), 2 * kLptBuckets * 4, s, read_off, n_pairs,
+                       hist, order);
     return hipGetLastError();
 }
 

@@ -409,23 +409,34 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     const int search_blocks = ctx->num_cus * 8;
     const uint64_t workers = (uint64_t)win_blocks * 4;
     const int spill_rows = 64 - L.lds_rows;
+    // Search chunks: at least kBatchSearchChunk columns, and large enough that
+    // the batch makes about two items per search group, so that a long
+    // reference splits only when the groups would otherwise sit idle.
+    {
+        const uint64_t groups = (uint64_t)search_blocks * 4;
+        const uint64_t want = (total_ref_bases + 2 * groups - 1) / (2 * groups);
+        p.search_chunk = (uint32_t)std::min<uint64_t>(
+            std::max<uint64_t>(kBatchSearchChunk, (want + 1023) / 1024 * 1024), 1u << 30);
+    }
+    const uint64_t item_cap = search_item_cap(n_pairs, total_ref_bases, p.search_chunk);
     auto carve = [&](Carver& c) {
         p.search = c.take<SearchOut>(n_pairs);
         p.counters = c.take<uint32_t>(kCounterCount);
-        uint32_t* lists = c.take<uint32_t>(2 * n_pairs);
+        p.search_key = c.take<unsigned long long>(n_pairs);
+        uint64_t* items = c.take<uint64_t>(2 * item_cap);
         p.easy_list = c.take<uint32_t>(n_pairs);
         p.hard_list = c.take<uint32_t>(n_pairs);
         p.spill = spill_rows > 0 ? c.take<unsigned long long>(workers * spill_rows * p.stride) : nullptr;
         uint32_t* hist = c.take<uint32_t>(kLptBuckets);
         uint32_t* order = c.take<uint32_t>(n_pairs);
-        return std::make_tuple(lists, hist, order);
+        return std::make_tuple(items, hist, order);
     };
     Carver dry{nullptr};
     carve(dry);
     rc = ensure(ctx, &ctx->scratch, &ctx->scratch_cap, dry.off + 256);
     if (rc) return rc;
     Carver real{ctx->scratch};
-    auto [lists, hist, order] = carve(real);
+    auto [items, hist, order] = carve(real);
 
     CHECK_HIP(ctx, mark(0));
     CHECK_HIP(ctx, launch_planes(d_reads2b, d_read_off, total_read_bases,
@@ -438,31 +449,37 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
         CHECK_HIP(ctx, launch_lpt_order(d_read_off, n_pairs, hist, order, s));
         p.order = order;
     }
-    // Start search: stage 0 over all pairs (longest first when ordered), then
-    // stages 1-2 retry the pairs that need more rows.
+    // Start search over reference chunks: the items of every pair (longest
+    // reads first when ordered), stage 0 with 16 rows, stages 1-2 with 32 and 64
+    // rows for the items that found no hit, then each pair's outcome and queue.
     CHECK_HIP(ctx, mark(1));
     const int SG = L.search_lanes;
     p.list_in = p.order;
     CHECK_HIP(ctx, launch_init_counters(p.counters, (uint32_t)n_pairs, s));
+    p.items_out = items;
+    CHECK_HIP(ctx, launch_search_items(p, (uint32_t)n_pairs, s));
     p.list_slot = 0;
-    p.list_out = lists;
+    p.items_in = items;
+    p.items_out = items + item_cap;
     if (SG == 64) {
         CHECK_HIP(ctx, launch_search(p, 64, 1, search_blocks, s));
     } else {
         CHECK_HIP(ctx, launch_search(p, 16, 1, search_blocks, s));
-        p.list_in = lists;
-        p.list_out = lists + n_pairs;
+        p.items_in = items + item_cap;
+        p.items_out = items;
         p.list_slot = 1;
         CHECK_HIP(ctx, launch_search(p, 16, 2, search_blocks, s));
-        p.list_in = lists + n_pairs;
-        p.list_out = lists;  // never written: 4 rows per lane cover all 64 rows
+        p.items_in = items;
+        p.items_out = items + item_cap;  // never written: 4 rows per lane cover all 64 rows
         p.list_slot = 2;
         CHECK_HIP(ctx, launch_search(p, 16, 4, search_blocks, s));
     }
+    CHECK_HIP(ctx, launch_search_finalize(p, (uint32_t)n_pairs, s));
     // Windows: persistent workers pull pairs (longest first) from the queue.
     CHECK_HIP(ctx, mark(2));
     p.list_in = nullptr;
-    p.list_out = nullptr;
+    p.items_in = nullptr;
+    p.items_out = nullptr;
     CHECK_HIP(ctx, launch_windows(p, win_blocks, s));
     CHECK_HIP(ctx, mark(3));
     return GENASM_OK;

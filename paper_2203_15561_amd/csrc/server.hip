@@ -141,8 +141,10 @@ struct genasm_server {
     genasm_result* d_out = nullptr;
     PairState* d_state = nullptr;
     SearchOut* d_search = nullptr;
-    uint32_t *d_counters = nullptr, *d_lists = nullptr, *d_new = nullptr, *d_active = nullptr,
-             *d_params = nullptr;
+    uint32_t *d_counters = nullptr, *d_new = nullptr, *d_active = nullptr, *d_params = nullptr;
+    uint64_t* d_items = nullptr;          // two start-search item lists
+    unsigned long long* d_key = nullptr;  // per-slot search key
+    uint64_t item_cap = 0;
     unsigned long long* d_spill = nullptr;
     uint8_t* d_upload = nullptr;
     uint64_t *d_up_src = nullptr, *d_up_dst = nullptr, *d_up_word = nullptr;
@@ -210,18 +212,23 @@ hipError_t enqueue_iteration(genasm_server* srv) {
     if ((e = launch_windows(srv->P, srv->win_blocks, srv->s2))) return e;
     if ((e = hipEventRecord(srv->ev_join, srv->s2))) return e;
     AlignParams S = srv->S;
+    const uint64_t cap = srv->item_cap;
     S.list_in = srv->d_new;
-    S.list_out = srv->d_lists;
+    S.items_out = srv->d_items;
+    if ((e = launch_search_items(S, n_slots, srv->s))) return e;
     S.list_slot = 0;
+    S.items_in = srv->d_items;
+    S.items_out = srv->d_items + cap;
     if ((e = launch_search(S, 16, 1, srv->search_blocks, srv->s))) return e;
-    S.list_in = srv->d_lists;
-    S.list_out = srv->d_lists + n_slots;
+    S.items_in = srv->d_items + cap;
+    S.items_out = srv->d_items;
     S.list_slot = 1;
     if ((e = launch_search(S, 16, 2, srv->search_blocks, srv->s))) return e;
-    S.list_in = srv->d_lists + n_slots;
-    S.list_out = srv->d_lists;
+    S.items_in = srv->d_items;
+    S.items_out = srv->d_items + cap;
     S.list_slot = 2;
     if ((e = launch_search(S, 16, 4, srv->search_blocks, srv->s))) return e;
+    if ((e = launch_search_finalize(S, n_slots, srv->s))) return e;
     return hipStreamWaitEvent(srv->s, srv->ev_join, 0);
 }
 
@@ -279,7 +286,8 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     D(srv->d_read_off, NS); D(srv->d_ref_off, NS); D(srv->d_run_base, NS);
     D(srv->d_read_len, NS); D(srv->d_ref_len, NS);
     D(srv->d_out, NS); D(srv->d_state, NS); D(srv->d_search, NS);
-    D(srv->d_counters, kCounterCount); D(srv->d_lists, 2 * (size_t)NS);
+    srv->item_cap = search_item_cap(NS, cfg.pool_bases, kServeSearchChunk);
+    D(srv->d_counters, kCounterCount); D(srv->d_items, 2 * srv->item_cap); D(srv->d_key, NS);
     D(srv->d_new, NS); D(srv->d_active, NS); D(srv->d_params, 4);
     D(srv->d_spill, workers * (64 - lds_rows) * stride);
     D(srv->d_upload, srv->upload_cap);
@@ -342,6 +350,8 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     p.route = 0;
     p.state = srv->d_state;
     p.window_budget = cfg.window_budget;
+    p.search_key = srv->d_key;
+    p.search_chunk = kServeSearchChunk;
     p.easy_list = srv->d_active;
     p.hard_list = srv->d_active;  // never used: the hard queue is empty
     srv->S = p;
@@ -454,7 +464,7 @@ void genasm_server_destroy(genasm_server* srv) {
     if (srv->graph) (void)hipGraphDestroy(srv->graph);
     void* dev[] = {srv->d_pool, srv->d_plo, srv->d_phi, srv->d_up_word, srv->d_up_bases, srv->d_cigar, srv->d_read_off, srv->d_ref_off, srv->d_run_base,
                    srv->d_read_len, srv->d_ref_len, srv->d_out, srv->d_state, srv->d_search,
-                   srv->d_counters, srv->d_lists, srv->d_new, srv->d_active, srv->d_params,
+                   srv->d_counters, srv->d_items, srv->d_key, srv->d_new, srv->d_active, srv->d_params,
                    srv->d_spill, srv->d_upload, srv->d_up_src, srv->d_up_dst, srv->d_up_len,
                    srv->d_gather_list, srv->d_gather_off, srv->d_gather};
     for (void* p : dev)

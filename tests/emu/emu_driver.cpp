@@ -5,8 +5,8 @@
 //   emu_driver IN OUT
 // IN : int64 form (0 plain, 1 batched, 2 serving loop, 3 unimproved, 4 filter), group_lanes, search_lanes,
 //      lds_rows, k, W, O, n_pairs, read_bytes, ref_bytes, hard_row, window_budget,
-//      slots, admit_per_iteration, hard_lanes; then the packed read bytes, the
-//      packed reference bytes, read_off[n+1], ref_off[n+1] (uint64).
+//      slots, admit_per_iteration, hard_lanes, search_chunk; then the packed read
+//      bytes, the packed reference bytes, read_off[n+1], ref_off[n+1] (uint64).
 // OUT: n genasm_result records, then (read bases + ref bases) CIGAR elements;
 //      for the filter, n int32 distances then n uint32 starts.
 #include "../../paper_2203_15561_amd/csrc/kernels.hip"
@@ -26,7 +26,7 @@ int main(int argc, char** argv) {
     if (argc != 3) { fprintf(stderr, "usage: emu_driver IN OUT\n"); return 2; }
     FILE* f = fopen(argv[1], "rb");
     if (!f) { perror("open IN"); return 2; }
-    int64_t h[15];
+    int64_t h[16];
     if (!read_all(f, h, sizeof h)) return 2;
     const int form = (int)h[0], G = (int)h[1], SG = (int)h[2], lds_rows = (int)h[3];
     const int k = (int)h[4], W = (int)h[5], O = (int)h[6];
@@ -34,6 +34,7 @@ int main(int argc, char** argv) {
     const int hard_row = (int)h[10];
     const uint32_t budget = (uint32_t)h[11], n_slots = (uint32_t)h[12], per_iter = (uint32_t)h[13];
     const int hard_lanes = (int)h[14];
+    const uint32_t chunk = (uint32_t)h[15];
     std::vector<uint8_t> reads(nrb + 8), refs(nfb + 8);
     std::vector<uint64_t> roff(n + 1), foff(n + 1);
     if (!read_all(f, reads.data(), nrb) || !read_all(f, refs.data(), nfb) ||
@@ -102,7 +103,10 @@ int main(int argc, char** argv) {
         const uint64_t workers = (uint64_t)blocks * 4;
         const int spill_rows = 64 - lds_rows;
         std::vector<SearchOut> search(n_slots, SearchOut{kSearchPending, 0});
-        std::vector<uint32_t> counters(kCounterCount, 0), lists(2 * n_slots + 1);
+        std::vector<uint32_t> counters(kCounterCount, 0);
+        const uint64_t icap = search_item_cap(n_slots, foff[n], chunk);
+        std::vector<uint64_t> items(2 * icap);
+        std::vector<unsigned long long> key(n_slots);
         std::vector<uint32_t> fresh_list(n_slots + 1), active(n_slots + 1), params(4, 0);
         std::vector<unsigned long long> spill(std::max<uint64_t>(workers * spill_rows * p.stride, 1));
         std::vector<uint64_t> s_roff(n_slots), s_foff(n_slots), s_base(n_slots);
@@ -130,6 +134,8 @@ int main(int argc, char** argv) {
         p.window_budget = budget;
         p.easy_list = active.data();
         p.hard_list = active.data();
+        p.search_key = key.data();
+        p.search_chunk = chunk;
         uint64_t next = 0, finished_n = 0, iters = 0;
         std::vector<uint32_t> fresh;
         while (finished_n < n) {
@@ -156,17 +162,21 @@ int main(int argc, char** argv) {
             launch_windows(p, blocks, nullptr);
             AlignParams S = p;
             S.list_in = fresh_list.data();
-            S.list_out = lists.data();
+            S.items_out = items.data();
+            launch_search_items(S, n_slots, nullptr);
             S.list_slot = 0;
+            S.items_in = items.data();
+            S.items_out = items.data() + icap;
             launch_search(S, 16, 1, blocks, nullptr);
-            S.list_in = lists.data();
-            S.list_out = lists.data() + n_slots;
+            S.items_in = items.data() + icap;
+            S.items_out = items.data();
             S.list_slot = 1;
             launch_search(S, 16, 2, blocks, nullptr);
-            S.list_in = lists.data() + n_slots;
-            S.list_out = lists.data();
+            S.items_in = items.data();
+            S.items_out = items.data() + icap;
             S.list_slot = 2;
             launch_search(S, 16, 4, blocks, nullptr);
+            launch_search_finalize(S, n_slots, nullptr);
             std::vector<uint32_t> still;
             auto settle = [&](uint32_t q) {
                 if (state[q].flags & kStateDone) {
@@ -203,7 +213,10 @@ int main(int argc, char** argv) {
         const uint64_t workers = (uint64_t)blocks * 4;
         const int spill_rows = 64 - lds_rows;
         std::vector<SearchOut> search(n, SearchOut{kSearchPending, 0});
-        std::vector<uint32_t> counters(kCounterCount, 0), lists(2 * n + 1), order(n);
+        std::vector<uint32_t> counters(kCounterCount, 0), order(n);
+        const uint64_t icap = search_item_cap(n, foff[n] - foff[0], chunk);
+        std::vector<uint64_t> items(2 * icap);
+        std::vector<unsigned long long> key(n);
         std::vector<uint32_t> easy(n + 1), hard(n + 1);
         std::vector<unsigned long long> spill(std::max<uint64_t>(workers * spill_rows * p.stride, 1));
         std::iota(order.begin(), order.end(), 0u);
@@ -220,24 +233,32 @@ int main(int argc, char** argv) {
         p.hard_lanes = G == 64 ? 64 : hard_lanes;
         p.route = 1;
         p.lds_rows = lds_rows;
+        p.search_key = key.data();
+        p.search_chunk = chunk;
         launch_init_counters(p.counters, (uint32_t)n, nullptr);
         p.list_in = p.order;
-        p.list_out = lists.data();
+        p.items_out = items.data();
+        emu::group_lanes = 64;
+        launch_search_items(p, (uint32_t)n, nullptr);
         p.list_slot = 0;
+        p.items_in = items.data();
+        p.items_out = items.data() + icap;
         emu::group_lanes = SG;
         if (SG == 64) {
             launch_search(p, 64, 1, blocks, nullptr);
         } else {
             launch_search(p, 16, 1, blocks, nullptr);
-            p.list_in = lists.data();
-            p.list_out = lists.data() + n;
+            p.items_in = items.data() + icap;
+            p.items_out = items.data();
             p.list_slot = 1;
             launch_search(p, 16, 2, blocks, nullptr);
-            p.list_in = lists.data() + n;
-            p.list_out = lists.data();
+            p.items_in = items.data();
+            p.items_out = items.data() + icap;
             p.list_slot = 2;
             launch_search(p, 16, 4, blocks, nullptr);
         }
+        emu::group_lanes = 64;
+        launch_search_finalize(p, (uint32_t)n, nullptr);
         for (uint64_t i = 0; i < n; ++i) {
             if (search[i].row == kSearchPending) {
                 fprintf(stderr, "pair %llu left pending by the search\n", (unsigned long long)i);
@@ -245,7 +266,8 @@ int main(int argc, char** argv) {
             }
         }
         p.list_in = nullptr;
-        p.list_out = nullptr;
+        p.items_in = nullptr;
+        p.items_out = nullptr;
         const uint32_t n_easy = counters[kCounterEasyLen], n_hard = counters[kCounterHardLen];
         if (p.hard_lanes == 64) {
             // The window kernel changes lane-group width between its two queues;

@@ -112,9 +112,23 @@ inline unsigned long long ballot(bool p) {
     unsigned long long m = 0;
     const int g0 = lane / b->group_lanes * b->group_lanes;
     for (int l = g0; l < g0 + b->group_lanes; ++l)
-        if (b->pred[l]) m |= 1ull << l;
+        if (b->pred[l]) m |= 1ull << (l & 63);
     group_barrier();
     return m;
+}
+
+// Value of `v` in lane `src` of the calling lane's group.
+template <class T>
+inline T shfl(T v, int src) {
+    BlockState* b = cur.blk;
+    const int lane = (int)cur.tid;
+    group_barrier();
+    b->slot[lane] = (unsigned long long)v;
+    group_barrier();
+    const int g0 = lane / b->group_lanes * b->group_lanes;
+    const T out = (T)b->slot[g0 + (src % b->group_lanes)];
+    group_barrier();
+    return out;
 }
 
 constexpr unsigned long long kCanary = 0xC0FFEE11DEADBEEFull;
@@ -181,6 +195,7 @@ inline void __syncthreads() {
 #define __builtin_amdgcn_wave_barrier() emu::group_barrier()
 #define __builtin_amdgcn_fence(order, scope) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __ballot(p) emu::ballot(p)
+#define __shfl(v, src) emu::shfl(v, src)
 #define __HIP_MEMORY_SCOPE_AGENT 0
 #define __HIP_MEMORY_SCOPE_WAVEFRONT 0
 #define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_SEQ_CST)
@@ -189,6 +204,14 @@ template <class T>
 inline T atomicAdd(T* p, T v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
 template <class T>
 inline T atomicOr(T* p, T v) { return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST); }
+template <class T>
+inline T atomicMin(T* p, T v) {
+    T cur = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+    while (v < cur && !__atomic_compare_exchange_n(p, &cur, v, false, __ATOMIC_SEQ_CST,
+                                                   __ATOMIC_SEQ_CST)) {
+    }
+    return cur;
+}
 
 namespace genasm { extern unsigned long long smem[]; }
 constexpr size_t kEmuLdsWords = 160 * 1024 / 8;

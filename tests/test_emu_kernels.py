@@ -149,3 +149,17 @@ def test_filter_kernel(driver):
         for i in range(ps.n_pairs):
             want = oracle.filter_pair(ps.read(i), ps.ref(i), k)
             assert (int(dist[i]), int(start[i]) if dist[i] >= 0 else 0) == want, (i, k)
+
+
+@pytest.mark.parametrize("chunk", [1, 7, 0])
+def test_chunked_start_search(driver, chunk):
+    # the start search split into reference chunks (1 column each, 7, or the
+    # whole reference) combines to the same start row and leftmost column
+    pairs = gen.fuzz(6161 + chunk, 24, max_len=140)
+    ps = gen.from_lists("chunks", [p[0] for p in pairs], [p[1] for p in pairs], 64)
+    want = expected(ps)
+    res, cig = emu.run(driver, ps, 1, 16, 16, 16, search_chunk=chunk)
+    got = [(int(r["edit_distance"]), c, int(r["ref_begin"]), int(r["ref_end"]), int(r["n_windows"]))
+           for r, c in zip(res, cig)]
+    bad = [i for i in range(ps.n_pairs) if want[i] != got[i]]
+    assert not bad, (chunk, bad[:5], want[bad[0]], got[bad[0]])
