@@ -37,6 +37,17 @@ __device__ __forceinline__ u64 init_word(int d) { return d >= 64 ? 0ull : (~0ull
 
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return min(max(x, lo), hi); }
 
+// min(max(x, lo), hi) in one v_med3_i32 (lo <= hi).
+__device__ __forceinline__ int med3i(int x, int lo, int hi) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+#else
+    return min(max(x, lo), hi);
+#endif
+}
+
 // Shift a 64-bit value by one lane with a DPP move; lanes without a source lane
 // inside their DPP row (or the wavefront, for wave_shr) receive `old`.
 template <int CTRL>
@@ -119,6 +130,20 @@ constexpr int OFF_BC = 154;    // broadcast slots (4 words)
 constexpr int OFF_TAB = 160;   // stored table rows, `stride` words each
 static_assert(OFF_TAB == kGroupHeaderWords, "layout");
 constexpr int OFF_RING = 4;    // start search: 128-word text-mask ring (reuses PMT + BROW)
+
+// Layout of a 16-lane window group (in step order, so that a DC step needs no
+// address arithmetic): PMT16[x] = PM[T[nw-1-x]] at word OFF_PMT16 + x for
+// x in -15..63 (~0 below 0 and from nw on); BROW16[z] = the pass's last row at
+// column nw-1-z at word OFF_BROW16 + z, written for z in -15..nw-1 and read
+// for z in 0..nw+18. Lane g at step t reads PMT16[t-g]; lane 0 reads BROW16[t];
+// lane 15 writes BROW16[t-15]. The regions nobody needs overlap: PMT16 past
+// x = 63 (read only by finished lanes) with BROW16 below z = 0 (written only
+// by lanes ahead of the text), and BROW16 past z = 63 (read only by finished
+// lanes) with the broadcast slots and the first table row.
+constexpr int OFF_PMT16 = 15;
+constexpr int OFF_BROW16 = 94;
+constexpr int OFF_RUNS16 = OFF_BROW16;  // traceback run records (the DC arrays are dead then)
+static_assert(OFF_PMT16 + 64 + 15 == OFF_BROW16, "layout");
 
 // ---------------------------------------------------------------------------
 // Pattern masks
@@ -204,6 +229,19 @@ __device__ __forceinline__ void store_pmt(u64* lds, int gl, const u64 pm[4], u64
     if (gl == 0) pmt[64] = ~0ull;
 }
 
+// PMT16 of a 16-lane group (see OFF_PMT16): entries x = -15..64.
+__device__ __forceinline__ void store_pmt16(u64* lds, int gl, const u64 pm[4], u64 tl, u64 th, int nw) {
+    u64* pmt = lds + OFF_PMT16;
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+        const int x = gl - 15 + 16 * u;
+        const int i = nw - 1 - x;  // column
+        const int sh = i & 63;
+        const int c = (int)((tl >> sh) & 1ull) | ((int)((th >> sh) & 1ull) << 1);
+        pmt[x] = (x >= 0 && x < nw) ? pick_pm(pm[0], pm[1], pm[2], pm[3], c) : ~0ull;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // DC: one pass of G rows over a window
 // ---------------------------------------------------------------------------
@@ -251,6 +289,52 @@ __device__ void dc_pass(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int
             Dp = up;
             trow[1 + clampi(i, -1, Lc + 1)] = R;
             if (gl == G - 1) brow[1 + clampi(i, -1, nw + 1)] = R;
+        }
+    }
+}
+
+// dc_pass for 16-lane groups on the step-ordered layout (see OFF_PMT16): the
+// same computation, with the operand reads and the boundary-row write at
+// per-step constant offsets and one clamp for the table store.
+template <bool SPILL, bool FIRST>
+__device__ void dc_pass16(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int stride,
+                          int lds_rows) {
+    constexpr int G = 16;
+    const int d = c * G + gl;
+    u64* trow = SPILL ? spill + (size_t)(d - lds_rows) * stride : lds + OFF_TAB + d * stride;
+    const u64* pp = lds + OFF_PMT16 - gl;  // + t: PMT16[t - gl]
+    const u64* bp = lds + OFF_BROW16;      // + t: BROW16[t]
+    u64* bw = lds + OFF_BROW16 - 15;       // + t: BROW16[t - 15]
+    u64 R = init_word(d);
+    u64 Dp = d == 0 ? ~0ull : init_word(d - 1);
+    const u64 lowin = d == 0 ? 1ull : 0ull;
+    if (Lc == nw) trow[1 + nw] = R;  // lane 0 of a pass never computes column nw
+    const int slot0 = nw + gl;       // table slot 1 + i at t = 0 (column i = nw - 1 - t + gl)
+    const int hi_slot = Lc + 2;
+    const int steps = nw + G - 1;
+    constexpr int U = 4;
+    u64 qpm[U], qov[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        qpm[u] = pp[u];
+        qov[u] = FIRST ? ~0ull : bp[u];
+    }
+    for (int t0 = 0; t0 < steps; t0 += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u;
+            const u64 pm_t = qpm[u];
+            const u64 ov = qov[u];
+            // operands of step t+U; the boundary entry it reads was written by lane 15
+            // at step t+U+15-15 = t+U of the previous pass
+            qpm[u] = pp[t + U];
+            if (!FIRST) qov[u] = bp[t + U];
+            const u64 up = LaneShift<G>::up(ov, R);
+            const u64 x = Dp & (((Dp & up) << 1) | lowin);
+            R = x & ((R << 1) | pm_t);
+            Dp = up;
+            trow[med3i(slot0 - t, 0, hi_slot)] = R;
+            if (gl == G - 1) bw[t] = R;
         }
     }
 }
@@ -510,7 +594,7 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
                              uint32_t budget) {
     const uint64_t run_base = pair_run_base(P, pair);
     const uint64_t run_limit = min(P.cigar_cap, run_base + (uint64_t)pc.m + (uint64_t)pc.n);
-    uint32_t* runs = reinterpret_cast<uint32_t*>(lds + OFF_BROW);
+    uint32_t* runs = reinterpret_cast<uint32_t*>(lds + (G == 16 ? OFF_RUNS16 : OFF_BROW));
     RunState rs{st.cur_op, st.cur_len, st.cur_op >= 0 ? 0 : -1};
     bool overflow = (st.flags & kStateOverflow) != 0;
     bool failed = false, internal = false;
@@ -548,7 +632,8 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
         if (Kr >= 0) {
             u64 pm[4];
             pm_from_planes(pl, ph, mw, pm);
-            store_pmt<G>(lds, gl, pm, tl, th, nw);
+            if constexpr (G == 16) store_pmt16(lds, gl, pm, tl, th, nw);
+            else store_pmt<G>(lds, gl, pm, tl, th, nw);
             wave_sync();
         }
         int dstar = -1;
@@ -556,13 +641,24 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
         for (int c = 0; c * G <= Kr; ++c) {
             st_steps += (u64)G * (nw + G - 1);
             const bool spill_pass = c * G >= lds_rows;
-            if (spill_pass) {
-                dc_pass<G, true, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
-                mem_sync();
+            if constexpr (G == 16) {
+                if (spill_pass) {
+                    dc_pass16<true, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    mem_sync();
+                } else {
+                    if (c == 0) dc_pass16<false, true>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    else dc_pass16<false, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    wave_sync();
+                }
             } else {
-                if (c == 0) dc_pass<G, false, true>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
-                else dc_pass<G, false, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
-                wave_sync();
+                if (spill_pass) {
+                    dc_pass<G, true, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    mem_sync();
+                } else {
+                    if (c == 0) dc_pass<G, false, true>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    else dc_pass<G, false, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    wave_sync();
+                }
             }
             const int d = c * G + gl;
             const u64 r0 = spill_pass ? load_spill(spill + (size_t)(d - lds_rows) * P.stride + 1)
