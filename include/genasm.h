@@ -277,10 +277,22 @@ typedef struct {
     uint64_t dc_cycles;        /* shader-clock cycles in DC passes (window setup included), summed over pairs */
     uint64_t tb_cycles;        /* shader-clock cycles in tracebacks and CIGAR stores, summed over pairs */
     uint64_t pair_cycles;      /* shader-clock cycles from a pair's first to last window, summed */
+    uint64_t window_workgroups;/* resident workgroups of the batched window kernel (4 groups each) */
 } genasm_profile;
 
 int genasm_profile_enable(genasm_ctx* ctx, int on);
 int genasm_profile_read(genasm_ctx* ctx, genasm_profile* out);
+/*
+ * Per-pair counters of the last profiled call: GENASM_PROFILE_WORDS uint64
+ * words per pair, in pair order: window word ops, search word ops, window
+ * cells, search cells, table words, traceback reads, window lane-steps, search
+ * lane-steps, windows, DC cycles, traceback cycles, window-loop cycles, and
+ * the device's 100 MHz clock when the pair's windows started and ended.
+ * *words receives n_pairs * GENASM_PROFILE_WORDS; GENASM_E_NOSPACE (nothing
+ * copied) when max_words is smaller.
+ */
+#define GENASM_PROFILE_WORDS 14
+int genasm_profile_pairs(genasm_ctx* ctx, uint64_t* out, uint64_t max_words, uint64_t* words);
 
 /*
  * Serving form: continuous batching of single-pair requests.

@@ -83,6 +83,7 @@ class Profile(ctypes.Structure):
         ("dc_cycles", ctypes.c_uint64),
         ("tb_cycles", ctypes.c_uint64),
         ("pair_cycles", ctypes.c_uint64),
+        ("window_workgroups", ctypes.c_uint64),
     ]
 
     def as_dict(self):
@@ -141,6 +142,7 @@ EXPORTS = [
     "genasm_completion_release", "genasm_server_stats_read", "genasm_server_destroy",
     "genasm_now_ns", "genasm_filter", "genasm_filter_dev", "genasm_autotune_dev",
     "genasm_tune_cache_save", "genasm_tune_cache_load", "genasm_tune_cache_size",
+    "genasm_profile_pairs",
 ]
 
 _c = ctypes
@@ -182,6 +184,7 @@ _SIGS = {
                                        _c.c_uint32, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p,
                                        _c.c_void_p, _c.c_uint64, _c.c_int32, _c.c_void_p,
                                        _c.POINTER(Launch), _c.POINTER(_c.c_float)]),
+    "genasm_profile_pairs": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_uint64, _u64p]),
     "genasm_tune_cache_save": (_c.c_int, [_c.c_void_p, _c.c_char_p]),
     "genasm_tune_cache_load": (_c.c_int, [_c.c_void_p, _c.c_char_p]),
     "genasm_tune_cache_size": (_c.c_int, [_c.c_void_p]),
@@ -453,6 +456,22 @@ class Context:
         pr = Profile()
         self._check(lib().genasm_profile_read(self._ctx, ctypes.byref(pr)), "genasm_profile_read")
         return pr.as_dict()
+
+    PROFILE_FIELDS = ("window_word_ops", "search_word_ops", "window_cells", "search_cells",
+                      "table_words", "tb_reads", "window_lane_steps", "search_lane_steps",
+                      "windows", "dc_cycles", "tb_cycles", "pair_cycles", "start_clock",
+                      "end_clock")
+
+    def profile_pairs(self) -> np.ndarray:
+        """Per-pair counters of the last profiled call, shape (n_pairs, 14)."""
+        words = ctypes.c_uint64(0)
+        rc = lib().genasm_profile_pairs(self._ctx, None, 0, ctypes.byref(words))
+        if rc not in (0, E_NOSPACE):
+            self._check(rc, "genasm_profile_pairs")
+        out = np.zeros(int(words.value), dtype=np.uint64)
+        self._check(lib().genasm_profile_pairs(self._ctx, out.ctypes.data, out.size,
+                                               ctypes.byref(words)), "genasm_profile_pairs")
+        return out.reshape(-1, len(self.PROFILE_FIELDS))
 
     def pack_dev(self, ascii_dev, packed_dev, bad_dev, stream=None):
         import torch

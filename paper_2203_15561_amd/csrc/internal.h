@@ -35,6 +35,7 @@ struct genasm_ctx {
     size_t stats_cap = 0;
     uint64_t prof_pairs = 0;
     int prof_form = 0;
+    int prof_window_blocks = 0;
     // autotuner cache: workload signature -> fastest launch and its time
     struct Tuned {
         genasm_launch launch;
@@ -90,7 +91,7 @@ struct AlignParams {
     int32_t K;                  // min(k, W)
     int32_t W;
     int32_t L;                  // W - O: bases committed per window at most
-    int32_t stride;             // words per stored table row: L + 3
+    int32_t stride;             // words per stored table row: L + 2 (see kernels.hip, OFF_TAB)
     genasm_result* out;
     uint32_t* cigar;            // CIGAR elements
     uint64_t cigar_cap;
@@ -133,7 +134,9 @@ constexpr int kStatWindows = 8;         // windows processed
 constexpr int kStatDcCycles = 9;        // shader-clock cycles: window setup and DC passes
 constexpr int kStatTbCycles = 10;       // shader-clock cycles: traceback and run stores
 constexpr int kStatPairCycles = 11;     // shader-clock cycles of the pair's window loop
-constexpr int kStatCount = 12;
+constexpr int kStatPairStart = 12;      // device clock (100 MHz) when the pair's windows started
+constexpr int kStatPairEnd = 13;        // device clock (100 MHz) when they ended
+constexpr int kStatCount = 14;
 
 // counters[] layout: queue heads and list lengths for the batched pipeline.
 constexpr int kCounterListBase = 2;  // search stage s: counters[2 + 2s] = list length, [3 + 2s] = head
@@ -145,11 +148,17 @@ constexpr int kCounterPairs = 14;    // pairs the search items / finalize kernel
 constexpr int kCounterCount = 16;
 
 // LDS words per group, by kernel.
-constexpr int kGroupHeaderWords = 160;
+constexpr int kGroupHeaderWords = 158;   // window groups: PM columns, boundary row, broadcast
+// A window group: header, lds_rows table rows, one end word (the last row's
+// right dummy slot).
 __host__ __device__ inline int window_group_words(int lds_rows, int stride) {
-    return kGroupHeaderWords + lds_rows * stride;
+    return kGroupHeaderWords + lds_rows * stride + 1;
 }
-constexpr int kSearchGroupWords = kGroupHeaderWords;  // PM, ring, broadcast slots
+// Words of the table stride, the spill of one worker and its end word.
+inline uint64_t spill_words(uint64_t workers, int spill_rows, int stride) {
+    return workers * (uint64_t)spill_rows * (uint64_t)stride + 1;
+}
+constexpr int kSearchGroupWords = 160;   // start search: PM, ring, broadcast slots
 
 // Kernel launchers (kernels.hip). All return hipError_t of the launch.
 hipError_t launch_plain(const AlignParams& p, hipStream_t s);
@@ -169,6 +178,8 @@ hipError_t launch_unimproved(const AlignParams& p, unsigned long long* table, hi
 hipError_t launch_search(const AlignParams& p, int group_lanes, int rows_per_lane, int blocks,
                          hipStream_t s);
 hipError_t launch_windows(const AlignParams& p, int blocks, hipStream_t s);
+// Window workgroups one compute unit holds at once (registers and LDS), 0 on error.
+int windows_blocks_per_cu(const AlignParams& p);
 hipError_t launch_pack(const char* ascii, uint64_t n, uint8_t* packed, uint32_t* bad,
                        hipStream_t s);
 hipError_t launch_init_counters(uint32_t* counters, uint32_t n_pairs, hipStream_t s);

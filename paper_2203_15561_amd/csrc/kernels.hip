@@ -127,7 +127,11 @@ constexpr int OFF_PMT = 4;     // PM[T[i]] for i in 0..nw, ~0 at nw..64 (66 word
 constexpr int OFF_BROW = 70;   // boundary row between passes: slot 1+i, i in -1..nw+1 (68 words)
 constexpr int OFF_CH = 138;    // 64 pattern bytes, 64 text bytes (16 words)
 constexpr int OFF_BC = 154;    // broadcast slots (4 words)
-constexpr int OFF_TAB = 160;   // stored table rows, `stride` words each
+// Stored table rows, `stride` = W-O+2 words each: slot 0 and slot W-O+2 are
+// dummies that absorb the stores of steps outside columns 0..W-O; the right
+// dummy of row r is the left dummy of row r+1 (both only ever hold garbage),
+// and the group's last row has an end word of its own.
+constexpr int OFF_TAB = 158;
 static_assert(OFF_TAB == kGroupHeaderWords, "layout");
 constexpr int OFF_RING = 4;    // start search: 128-word text-mask ring (reuses PMT + BROW)
 
@@ -603,6 +607,7 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
     const bool timing = P.stats != nullptr;
     u64 cyc_dc = 0, cyc_tb = 0;
     const u64 cyc_start = timing ? clock64() : 0;
+    const u64 wall_start = timing ? wall_clock64() : 0;
     // Every window commits at least one base, so a pair has at most m + n
     // windows; the cap keeps the loop finite even if that ever failed.
     const uint32_t max_windows = (uint32_t)pc.m + (uint32_t)pc.n + 1u;
@@ -746,6 +751,8 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
         stp[kStatDcCycles] += cyc_dc;
         stp[kStatTbCycles] += cyc_tb;
         stp[kStatPairCycles] += clock64() - cyc_start;
+        if (!stp[kStatPairStart]) stp[kStatPairStart] = wall_start;
+        stp[kStatPairEnd] = wall_clock64();
     }
 }
 
@@ -1654,6 +1661,14 @@ hipError_t launch_search_finalize(const AlignParams& p, uint32_t max_pairs, hipS
     if (max_pairs == 0) return hipSuccess;
     hipLaunchKernelGGL(k_search_finalize, dim3((max_pairs + 255) / 256), dim3(256), 0, s, p);
     return hipGetLastError();
+}
+
+int windows_blocks_per_cu(const AlignParams& p) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_windows, 64,
+                                                     window_lds_bytes(p.lds_rows, p.stride)) != hipSuccess)
+        return 0;
+    return n;
 }
 
 hipError_t launch_windows(const AlignParams& p, int blocks, hipStream_t s) {

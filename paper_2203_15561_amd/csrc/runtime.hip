@@ -331,7 +331,7 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     p.K = std::min(k, W);
     p.W = W;
     p.L = W - O;
-    p.stride = p.L + 3;
+    p.stride = p.L + 2;
     p.out = d_out;
     p.cigar = d_cigar;
     p.cigar_cap = cigar_cap;
@@ -400,12 +400,14 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     p.hard_row = L.hard_row;
     p.hard_lanes = L.hard_lanes;
     p.route = 1;
-    const int win_lds = window_lds_bytes(p.lds_rows, p.stride);
     int per_cu = L.workers_per_cu;
     if (per_cu == 0) {
-        per_cu = std::max(1, std::min(8, (160 * 1024) / win_lds));
+        // as many as stay resident together (LDS and registers), so that no
+        // workgroup of the persistent grid waits for another to finish
+        per_cu = std::max(1, std::min(16, windows_blocks_per_cu(p)));
     }
     const int win_blocks = ctx->num_cus * per_cu;
+    ctx->prof_window_blocks = win_blocks;
     const int search_blocks = ctx->num_cus * 8;
     const uint64_t workers = (uint64_t)win_blocks * 4;
     const int spill_rows = 64 - L.lds_rows;
@@ -426,7 +428,7 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
         uint64_t* items = c.take<uint64_t>(2 * item_cap);
         p.easy_list = c.take<uint32_t>(n_pairs);
         p.hard_list = c.take<uint32_t>(n_pairs);
-        p.spill = spill_rows > 0 ? c.take<unsigned long long>(workers * spill_rows * p.stride) : nullptr;
+        p.spill = spill_rows > 0 ? c.take<unsigned long long>(spill_words(workers, spill_rows, p.stride)) : nullptr;
         uint32_t* hist = c.take<uint32_t>(kLptBuckets);
         uint32_t* order = c.take<uint32_t>(n_pairs);
         return std::make_tuple(items, hist, order);
@@ -603,6 +605,18 @@ int genasm_profile_enable(genasm_ctx* ctx, int on) {
     return GENASM_OK;
 }
 
+int genasm_profile_pairs(genasm_ctx* ctx, uint64_t* out, uint64_t max_words, uint64_t* words) {
+    if (!ctx || !words) return GENASM_E_INVAL;
+    if (!ctx->have_profile) return set_err(ctx, GENASM_E_INVAL, "no profiled call yet");
+    const uint64_t n = ctx->prof_pairs * kStatCount;
+    *words = n;
+    if (!out || max_words < n) return n ? GENASM_E_NOSPACE : GENASM_OK;
+    CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    CHECK_HIP(ctx, hipEventSynchronize(ctx->ev[3]));
+    if (n) CHECK_HIP(ctx, hipMemcpy(out, ctx->stats, n * 8, hipMemcpyDeviceToHost));
+    return GENASM_OK;
+}
+
 int genasm_profile_read(genasm_ctx* ctx, genasm_profile* out) {
     if (!ctx || !out) return GENASM_E_INVAL;
     if (!ctx->have_profile) return set_err(ctx, GENASM_E_INVAL, "no profiled call yet");
@@ -632,6 +646,7 @@ int genasm_profile_read(genasm_ctx* ctx, genasm_profile* out) {
     out->dc_cycles = sum[kStatDcCycles];
     out->tb_cycles = sum[kStatTbCycles];
     out->pair_cycles = sum[kStatPairCycles];
+    out->window_workgroups = (uint64_t)ctx->prof_window_blocks;
     return GENASM_OK;
 }
 

@@ -259,9 +259,14 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     if (hipSetDevice(ctx->device) != hipSuccess) { delete srv; return GENASM_E_DEVICE; }
     const uint32_t NS = cfg.max_slots;
     const uint64_t pool_bytes = cfg.pool_bases / 4;
-    const int L = cfg.W - cfg.O, stride = L + 3;
+    const int L = cfg.W - cfg.O, stride = L + 2;
     const int lds_rows = 16;
-    const int per_cu = std::max(1, std::min(8, (160 * 1024) / window_lds_bytes(lds_rows, stride)));
+    // window workgroups per CU: one fewer than fit, leaving room for the start
+    // search of newly admitted pairs, which runs beside the window kernel
+    AlignParams occ{};
+    occ.lds_rows = lds_rows;
+    occ.stride = stride;
+    const int per_cu = std::max(1, std::min(16, windows_blocks_per_cu(occ)) - 1);
     srv->win_blocks = ctx->num_cus * per_cu;
     srv->search_blocks = ctx->num_cus * 8;
     const uint64_t workers = (uint64_t)srv->win_blocks * 4;
@@ -289,7 +294,7 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     srv->item_cap = search_item_cap(NS, cfg.pool_bases, kServeSearchChunk);
     D(srv->d_counters, kCounterCount); D(srv->d_items, 2 * srv->item_cap); D(srv->d_key, NS);
     D(srv->d_new, NS); D(srv->d_active, NS); D(srv->d_params, 4);
-    D(srv->d_spill, workers * (64 - lds_rows) * stride);
+    D(srv->d_spill, spill_words(workers, 64 - lds_rows, stride));
     D(srv->d_upload, srv->upload_cap);
     D(srv->d_up_src, 2 * (size_t)NS); D(srv->d_up_dst, 2 * (size_t)NS); D(srv->d_up_len, 2 * (size_t)NS);
     D(srv->d_up_word, 2 * (size_t)NS); D(srv->d_up_bases, 2 * (size_t)NS);

@@ -58,7 +58,7 @@ int main(int argc, char** argv) {
     p.K = std::min(k, W);
     p.W = W;
     p.L = W - O;
-    p.stride = p.L + 3;
+    p.stride = p.L + 2;
     p.out = out.data();
     p.cigar = cigar.data();
     p.cigar_cap = cap;
@@ -108,7 +108,7 @@ int main(int argc, char** argv) {
         std::vector<uint64_t> items(2 * icap);
         std::vector<unsigned long long> key(n_slots);
         std::vector<uint32_t> fresh_list(n_slots + 1), active(n_slots + 1), params(4, 0);
-        std::vector<unsigned long long> spill(std::max<uint64_t>(workers * spill_rows * p.stride, 1));
+        std::vector<unsigned long long> spill(spill_words(workers, spill_rows, p.stride));
         std::vector<uint64_t> s_roff(n_slots), s_foff(n_slots), s_base(n_slots);
         std::vector<uint32_t> s_rlen(n_slots), s_flen(n_slots);
         std::vector<PairState> state(n_slots);
@@ -218,7 +218,7 @@ int main(int argc, char** argv) {
         std::vector<uint64_t> items(2 * icap);
         std::vector<unsigned long long> key(n);
         std::vector<uint32_t> easy(n + 1), hard(n + 1);
-        std::vector<unsigned long long> spill(std::max<uint64_t>(workers * spill_rows * p.stride, 1));
+        std::vector<unsigned long long> spill(spill_words(workers, spill_rows, p.stride));
         std::iota(order.begin(), order.end(), 0u);
         std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
             return roff[a + 1] - roff[a] > roff[b + 1] - roff[b];

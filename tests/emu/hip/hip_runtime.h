@@ -38,6 +38,11 @@ enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
 typedef struct ihipStream_t* hipStream_t;
 typedef struct ihipEvent_t* hipEvent_t;
 inline hipError_t hipGetLastError() { return hipSuccess; }
+template <class K>
+inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, K, int, size_t) {
+    *n = 1;
+    return hipSuccess;
+}
 
 template <class A, class B>
 inline auto min(A a, B b) -> decltype(a < b ? a : b) { return a < b ? a : b; }
@@ -184,6 +189,7 @@ inline unsigned long long bitreverse64(unsigned long long x) {
 }  // namespace emu
 #define __builtin_bitreverse64 emu::bitreverse64
 inline unsigned long long clock64() { return 0ull; }
+inline unsigned long long wall_clock64() { return 0ull; }
 #define __builtin_amdgcn_update_dpp emu::update_dpp
 // Block-wide barriers and static shared arrays are not emulated (kernels that
 // use them, such as the ordering scan, do not run under the emulation).
