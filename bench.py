@@ -189,6 +189,8 @@ def main():
                     help="open-loop arrival rates (req/s) below the saturated rate, comma-separated")
     ap.add_argument("--no-graph", action="store_true", help="skip timing the graph-captured step")
     ap.add_argument("--no-filter", action="store_true", help="skip the pre-alignment filter leg")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the batched-vs-plain legs on the 250 bp and uneven workloads")
     ap.add_argument("--filter-pairs", type=int, default=20000,
                     help="pairs of the 250 bp workload for the filter leg")
     ap.add_argument("--no-unimproved", action="store_true",
@@ -475,6 +477,49 @@ def main():
                           "gcups": cells / (fms / 1e3) / 1e9,
                           "accepted": float((dist.cpu().numpy() >= 0).mean())}
         log(f"filter: {fms:.3f} ms for {fps.n_pairs} pairs ({line['filter']['gcups']:.0f} GCUPS)")
+
+    if not args.no_other_configs:
+        # the other batch workloads: batched (autotuned) against the plain launch
+        line["other_configs"] = {}
+        for wname in ("short250", "uneven"):
+            ops = gen.make(wname)
+            o_r2 = torch.from_numpy(ga.pack(ops.reads)).to(dev)
+            o_f2 = torch.from_numpy(ga.pack(ops.refs)).to(dev)
+            o_ro = torch.from_numpy(ops.read_off.astype(np.int64)).to(dev)
+            o_fo = torch.from_numpy(ops.ref_off.astype(np.int64)).to(dev)
+            o_best, _, o_out, o_cig = ctx.autotune_dev(o_r2, o_ro, o_f2, o_fo, ops.k, ops.W, ops.O)
+            o_cells = None
+            res_o = {}
+            for form, L in (("batched", o_best), ("plain", ga.make_launch(ga.FORM_PLAIN))):
+                ctx.align_dev(o_r2, o_ro, o_f2, o_fo, ops.k, ops.W, ops.O, launch=L, out=o_out,
+                              cigar=o_cig)
+                torch.cuda.synchronize()
+                ctx.profile(True)
+                ctx.align_dev(o_r2, o_ro, o_f2, o_fo, ops.k, ops.W, ops.O, launch=L, out=o_out,
+                              cigar=o_cig)
+                pr_o = ctx.profile_read()
+                ctx.profile(False)
+                o0, o1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                o0.record()
+                for _ in range(args.steps):
+                    ctx.align_dev(o_r2, o_ro, o_f2, o_fo, ops.k, ops.W, ops.O, launch=L, out=o_out,
+                                  cigar=o_cig)
+                o1.record()
+                torch.cuda.synchronize()
+                oms = o0.elapsed_time(o1) / args.steps
+                o_cells = pr_o["window_cells"] + pr_o["search_cells"]
+                res_o[form] = {"ms": oms, "alignments_per_s": ops.n_pairs / (oms / 1e3),
+                               "gcups": o_cells / (oms / 1e3) / 1e9}
+                res_o[form + "_scores"] = o_out.cpu().numpy().view(ga.RESULT_DTYPE)["edit_distance"].copy()
+            assert (res_o["batched_scores"] == res_o["plain_scores"]).all()
+            del res_o["batched_scores"], res_o["plain_scores"]
+            res_o["pairs"] = ops.n_pairs
+            res_o["workload"] = gen.DESCRIPTIONS[wname]
+            res_o["batched_over_plain"] = res_o["plain"]["ms"] / res_o["batched"]["ms"]
+            line["other_configs"][wname] = res_o
+            log(f"{wname}: batched {res_o['batched']['ms']:.2f} ms, plain {res_o['plain']['ms']:.2f} ms "
+                f"({res_o['batched_over_plain']:.2f}x)")
+            del o_r2, o_f2, o_ro, o_fo, o_out, o_cig
 
     if not args.no_serving:
         line["serving"] = serving_leg(ga, gen, ctx, args)

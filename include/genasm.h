@@ -102,6 +102,9 @@ typedef struct {
     int32_t hard_lanes;      /* batched: lanes per pair for that queue: 16 (the ordinary
                                 groups, table rows past lds_rows spilled) or 64 (one pair per
                                 wavefront, the whole 64-row table in LDS); 0 = default (16) */
+    int32_t tb_prefetch;     /* batched: 1 = tracebacks over spilled rows load the next row
+                                ahead through the group's lanes, 0 = one load per edit;
+                                -1 = default */
 } genasm_launch;
 
 typedef struct genasm_ctx genasm_ctx;

@@ -61,6 +61,7 @@ class Launch(ctypes.Structure):
         ("lpt_order", ctypes.c_int32),
         ("hard_row", ctypes.c_int32),
         ("hard_lanes", ctypes.c_int32),
+        ("tb_prefetch", ctypes.c_int32),
     ]
 
 

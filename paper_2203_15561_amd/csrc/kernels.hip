@@ -316,7 +316,7 @@ __device__ void dc_pass16(u64* lds, u64* spill, int gl, int c, int nw, int Lc, i
     const int slot0 = nw + gl;       // table slot 1 + i at t = 0 (column i = nw - 1 - t + gl)
     const int hi_slot = Lc + 2;
     const int steps = nw + G - 1;
-    constexpr int U = 4;
+    constexpr int U = 8;
     u64 qpm[U], qov[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -503,13 +503,25 @@ __device__ __forceinline__ int ctz64(u64 x) { return x ? __builtin_ctzll(x) : 64
 // deletion test R[d-1][i+1] (bit p-1 and bit p), insertion tests R[d-1][i]
 // (bit p-1), with "p == 0 or bit p-1 is 0" taken as bit p of the word
 // shifted left by one.
+//
+// Rows at or above lds_rows come from the group's spill in device memory. Each
+// edit there also loads, one word per lane of the group, columns i..i+G-1 of
+// the row below (the row the next edit reads, since every edit lowers d by
+// one); when the next edit's two columns fall inside that range it takes them
+// from the loading lanes instead of from memory, so a spilled edit waits for
+// one load issued an edit earlier rather than for its own.
+template <int G>
 __device__ TbOut traceback_planes(const u64* lds, const u64* spill, uint32_t* runs, RunState& rs,
                                   bool writer, u64 pl, u64 ph, u64 tl, u64 th, int mw, int nw,
-                                  int dstar, int L, int stride, int lds_rows) {
+                                  int dstar, int L, int stride, int lds_rows, int gl, int lane,
+                                  bool prefetch) {
     const u64* tab = lds + OFF_TAB + 1;  // column c of a row sits in slot c + 1
     const int jmax = min(mw, L);
     int i = 0, j = 0, d = dstar;
     TbOut o{0, 0, 0, 0u, false};
+    u64 pf = 0;            // this lane's word of the prefetched row
+    int pf_row = -1, pf_col = 0;
+    const int gbase = lane - gl;
     // every pass of the loop consumes a read or text base, or leaves it
     for (int it = 0; it <= 2 * L; ++it) {
         if (j >= jmax || i >= L) break;
@@ -533,8 +545,24 @@ __device__ TbOut traceback_planes(const u64* lds, const u64* spill, uint32_t* ru
             B = row[i + 1];
         } else {
             const u64* row = spill + (size_t)(r - lds_rows) * stride + 1;
-            C = load_spill(row + i);
-            B = load_spill(row + i + 1);
+            const bool hit = r == pf_row && i >= pf_col && i + 1 < pf_col + G;
+            const int src = gbase + (i - pf_col);
+            const u64 have = pf;
+            // the row below, for the next edit, before this edit waits for its words
+            if (prefetch && r - 1 >= lds_rows) {
+                pf = load_spill(row - stride + min(i + gl, L));
+                pf_row = r - 1;
+                pf_col = i;
+            } else {
+                pf_row = -1;
+            }
+            if (hit) {
+                C = __shfl(have, src);
+                B = __shfl(have, src + 1);
+            } else {
+                C = load_spill(row + i);
+                B = load_spill(row + i + 1);
+            }
         }
         const bool intext = i < nw;
         const bool s_ok = intext && !(((B << 1) >> p) & 1ull);
@@ -686,8 +714,8 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
             run_push(runs, rs, GENASM_OP_INS, (uint32_t)k, writer);
             t = TbOut{0, k, k, 0u, false};
         } else {
-            t = traceback_planes(lds, spill, runs, rs, writer, pl, ph, tl, th, mw, nw, dstar, P.L,
-                                 P.stride, lds_rows);
+            t = traceback_planes<G>(lds, spill, runs, rs, writer, pl, ph, tl, th, mw, nw, dstar, P.L,
+                                    P.stride, lds_rows, gl, lane, P.tb_prefetch != 0);
         }
         st.score += t.edits;
         st_tb += t.reads;

@@ -117,6 +117,8 @@ int resolve_launch(const genasm_launch* in, genasm_launch* out) {
     if (in->lpt_order >= 0) out->lpt_order = in->lpt_order;
     if (in->hard_row) out->hard_row = in->hard_row;
     if (in->hard_lanes) out->hard_lanes = in->hard_lanes;
+    if (in->tb_prefetch >= 0) out->tb_prefetch = in->tb_prefetch;
+    if (out->tb_prefetch != 0 && out->tb_prefetch != 1) return GENASM_E_INVAL;
     if (out->hard_lanes != 16 && out->hard_lanes != 64) return GENASM_E_INVAL;
     if (out->group_lanes != 16 && out->group_lanes != 64) return GENASM_E_INVAL;
     if (out->search_lanes != 16 && out->search_lanes != 64) return GENASM_E_INVAL;
@@ -162,6 +164,7 @@ int genasm_default_launch(int32_t form, genasm_launch* out) {
     out->lpt_order = 1;
     out->hard_row = 16;
     out->hard_lanes = 16;
+    out->tb_prefetch = 0;
     return GENASM_OK;
 }
 
@@ -399,6 +402,7 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     p.lds_rows = L.lds_rows;
     p.hard_row = L.hard_row;
     p.hard_lanes = L.hard_lanes;
+    p.tb_prefetch = L.tb_prefetch;
     p.route = 1;
     int per_cu = L.workers_per_cu;
     if (per_cu == 0) {
@@ -517,6 +521,12 @@ int genasm_autotune_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_
     add(16, 16, 32, 0, 16);
     add(16, 16, 16, 4, 16);
     add(16, 16, 16, 0, 64);
+    {
+        genasm_launch c;
+        genasm_default_launch(GENASM_FORM_BATCHED, &c);
+        c.tb_prefetch = 1;
+        cands.push_back(c);
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     CHECK_HIP(ctx, hipEventCreate(&e0));
     CHECK_HIP(ctx, hipEventCreate(&e1));
@@ -559,12 +569,12 @@ int genasm_tune_cache_save(genasm_ctx* ctx, const char* path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return set_err(ctx, GENASM_E_INVAL, "cannot open tune cache file for writing");
     std::fprintf(f, "# key form group_lanes search_lanes lds_rows workers_per_cu lpt_order hard_row "
-                    "hard_lanes ms\n");
+                    "hard_lanes tb_prefetch ms\n");
     for (const auto& kv : ctx->tune) {
         const genasm_launch& L = kv.second.launch;
-        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %.4f\n", kv.first.c_str(), L.form, L.group_lanes,
-                     L.search_lanes, L.lds_rows, L.workers_per_cu, L.lpt_order, L.hard_row,
-                     L.hard_lanes, kv.second.ms);
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %.4f\n", kv.first.c_str(), L.form,
+                     L.group_lanes, L.search_lanes, L.lds_rows, L.workers_per_cu, L.lpt_order,
+                     L.hard_row, L.hard_lanes, L.tb_prefetch, kv.second.ms);
     }
     const bool ok = std::fclose(f) == 0;
     return ok ? GENASM_OK : set_err(ctx, GENASM_E_INVAL, "writing the tune cache failed");
@@ -581,11 +591,12 @@ int genasm_tune_cache_load(genasm_ctx* ctx, const char* path) {
         char key[256];
         genasm_launch L{};
         float ms = 0.f;
-        const int got = std::sscanf(line, "%255s %d %d %d %d %d %d %d %d %f", key, &L.form,
+        const int got = std::sscanf(line, "%255s %d %d %d %d %d %d %d %d %d %f", key, &L.form,
                                     &L.group_lanes, &L.search_lanes, &L.lds_rows,
-                                    &L.workers_per_cu, &L.lpt_order, &L.hard_row, &L.hard_lanes, &ms);
+                                    &L.workers_per_cu, &L.lpt_order, &L.hard_row, &L.hard_lanes,
+                                    &L.tb_prefetch, &ms);
         genasm_launch chk;
-        if (got != 10 || resolve_launch(&L, &chk) != GENASM_OK) { rc = GENASM_E_INVAL; break; }
+        if (got != 11 || resolve_launch(&L, &chk) != GENASM_OK) { rc = GENASM_E_INVAL; break; }
         ctx->tune[key] = genasm_ctx::Tuned{L, ms};
     }
     std::fclose(f);

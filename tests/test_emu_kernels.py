@@ -32,15 +32,16 @@ def expected(ps):
             for i in range(ps.n_pairs)]
 
 
-def emulated(driver, ps, form, hard_row=16, hard_lanes=16):
-    res, cig = emu.run(driver, ps, form, 16, 16, 16, hard_row=hard_row, hard_lanes=hard_lanes)
+def emulated(driver, ps, form, hard_row=16, hard_lanes=16, tb_prefetch=0):
+    res, cig = emu.run(driver, ps, form, 16, 16, 16, hard_row=hard_row, hard_lanes=hard_lanes,
+                       tb_prefetch=tb_prefetch)
     assert (res["flags"] == 0).all()
     return [(int(r["edit_distance"]), c, int(r["ref_begin"]), int(r["ref_end"]), int(r["n_windows"]))
             for r, c in zip(res, cig)]
 
 
-def check(driver, ps, form, hard_row=16, hard_lanes=16):
-    want, got = expected(ps), emulated(driver, ps, form, hard_row, hard_lanes)
+def check(driver, ps, form, hard_row=16, hard_lanes=16, tb_prefetch=0):
+    want, got = expected(ps), emulated(driver, ps, form, hard_row, hard_lanes, tb_prefetch)
     bad = [i for i in range(ps.n_pairs) if want[i] != got[i]]
     assert not bad, (bad[:5], want[bad[0]], got[bad[0]])
 
@@ -93,8 +94,8 @@ def test_edge_cases_batched(driver):
         check(driver, ps, 1)
 
 
-@pytest.mark.parametrize("hard_row,hard_lanes", [(16, 16), (16, 64)])
-def test_long_read_prefixes_with_decoy(driver, hard_row, hard_lanes):
+@pytest.mark.parametrize("hard_row,hard_lanes,tb_prefetch", [(16, 16, 0), (16, 64, 0), (16, 16, 1)])
+def test_long_read_prefixes_with_decoy(driver, hard_row, hard_lanes, tb_prefetch):
     # 1,200-base prefixes of a true pair and a decoy pair: the decoy's windows
     # need most of the 64 rows (spilled rows with 16 lanes, the whole-wavefront
     # path with 64)
@@ -102,7 +103,7 @@ def test_long_read_prefixes_with_decoy(driver, hard_row, hard_lanes):
     assert ps.decoy.tolist() == [True, False]
     cut = gen.from_lists("long-prefix", [ps.read(i)[:1200] for i in range(2)],
                          [ps.ref(i)[:1300] for i in range(2)], 64)
-    check(driver, cut, 1, hard_row, hard_lanes)
+    check(driver, cut, 1, hard_row, hard_lanes, tb_prefetch)
 
 
 @pytest.mark.parametrize("budget", [1, 3])

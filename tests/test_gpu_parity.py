@@ -107,6 +107,7 @@ LAUNCH_VARIANTS = {
     "no_hard": dict(hard_row=65),
     "hard_from_8": dict(hard_row=8),
     "hard_g64": dict(hard_row=16, hard_lanes=64),
+    "tb_prefetch": dict(tb_prefetch=1),
 }
 
 
@@ -297,6 +298,7 @@ def test_autotune_picks_caches_and_reloads(ctx, tmp_path):
         tctx.tune_cache_save(path)
         fields = [ln.split() for ln in open(path) if not ln.startswith("#")]
         assert len(fields) == 1 and int(fields[0][7]) == best.hard_row
+        assert int(fields[0][9]) == best.tb_prefetch
         other = ga.Context(0)
         try:
             other.tune_cache_load(path)
