@@ -98,10 +98,12 @@ typedef struct {
     int32_t hard_row;        /* batched: pairs whose start search needs this many edit rows or
                                 more (decoy-like pairs, whose windows cost several DC passes)
                                 go to a separate queue that the window workers drain first;
-                                0 = default (16); 65 = no separate queue */
+                                0 = default (16); -1 = every pair; 65 = no separate queue */
     int32_t hard_lanes;      /* batched: lanes per pair for that queue: 16 (the ordinary
-                                groups, table rows past lds_rows spilled) or 64 (one pair per
-                                wavefront, the whole 64-row table in LDS); 0 = default (16) */
+                                groups, table rows past lds_rows spilled), 32 (two pairs per
+                                wavefront, 32 rows per DC pass and in LDS; needs lds_rows
+                                <= 48) or 64 (one pair per wavefront, the whole 64-row table
+                                in LDS); 0 = default (16) */
     int32_t tb_prefetch;     /* batched: 1 = tracebacks over spilled rows load the next row
                                 ahead through the group's lanes, 0 = one load per edit;
                                 -1 = default */

@@ -155,6 +155,12 @@ constexpr int kGroupHeaderWords = 158;   // window groups: PM columns, boundary 
 __host__ __device__ inline int window_group_words(int lds_rows, int stride) {
     return kGroupHeaderWords + lds_rows * stride + 1;
 }
+// 32-lane window groups have a longer header (their PM column and boundary
+// arrays each span 31 more words).
+constexpr int kGroupHeaderWords32 = 192;
+__host__ __device__ inline int window_group_words32(int lds_rows, int stride) {
+    return kGroupHeaderWords32 + lds_rows * stride + 1;
+}
 // Words of the table stride, the spill of one worker and its end word.
 inline uint64_t spill_words(uint64_t workers, int spill_rows, int stride) {
     return workers * (uint64_t)spill_rows * (uint64_t)stride + 1;

@@ -76,6 +76,19 @@ template <> struct LaneShift<64> {
     static __device__ __forceinline__ u64 up(u64 old, u64 v) { return dpp64<kDppWaveShr1>(old, v); }
     static __device__ __forceinline__ u64 rot(u64 v) { return dpp64<kDppWaveRor1>(v, v); }
 };
+// Two 32-lane groups per wavefront: a shift over the whole wavefront, after
+// which lane 32 holds lane 31's value; shift_up gives it `old` instead.
+template <> struct LaneShift<32> {
+    static __device__ __forceinline__ u64 up(u64 old, u64 v) { return dpp64<kDppWaveShr1>(old, v); }
+};
+
+// Value of lane gl-1 of the group; lane 0 of the group gets `old`.
+template <int G>
+__device__ __forceinline__ u64 shift_up(u64 old, u64 v, int gl) {
+    const u64 s = LaneShift<G>::up(old, v);
+    if constexpr (G == 32) return gl == 0 ? old : s;
+    return s;
+}
 
 // Orders the LDS accesses of one wavefront: the compiler may not move memory
 // operations across it, and it waits for the wavefront's outstanding LDS
@@ -148,6 +161,28 @@ constexpr int OFF_PMT16 = 15;
 constexpr int OFF_BROW16 = 94;
 constexpr int OFF_RUNS16 = OFF_BROW16;  // traceback run records (the DC arrays are dead then)
 static_assert(OFF_PMT16 + 64 + 15 == OFF_BROW16, "layout");
+
+// The same step-ordered layout for G-lane groups (G = 16 or 32): PMT at word
+// G-1+x for x in -(G-1)..64, BROW at word 2(G-1)+64+z, written for z in
+// -(G-1)..nw-1 and read for z in 0..nw+G+6, the table after the header. The
+// 32-lane header ends past BROW[63] (word 189); the reads past it go into the
+// first table row, and the broadcast slot lies inside BROW (group_pop uses it
+// only between pairs). Run records go at OFF_BROW16 (16 lanes) or OFF_BROW
+// (words 70..133 at most: at most 2 min(L, d*) + 1 <= 127 runs of 32 bits).
+template <int G> struct SoLayout {
+    static_assert(G == 16 || G == 32, "step-ordered layout: 16 or 32 lanes");
+    static constexpr int pmt = G - 1;
+    static constexpr int brow = 2 * (G - 1) + 64;
+    static constexpr int tab = G == 16 ? kGroupHeaderWords : kGroupHeaderWords32;
+};
+static_assert(SoLayout<16>::pmt == OFF_PMT16 && SoLayout<16>::brow == OFF_BROW16 &&
+              SoLayout<16>::tab == OFF_TAB, "layout");
+static_assert(SoLayout<32>::brow + 64 <= kGroupHeaderWords32, "layout");
+static_assert(OFF_BROW + 64 <= SoLayout<32>::tab, "layout");
+
+// First table word and run-record word of a G-lane group.
+template <int G> constexpr int tab_off() { return G == 32 ? kGroupHeaderWords32 : OFF_TAB; }
+template <int G> constexpr int runs_off() { return G == 16 ? OFF_RUNS16 : OFF_BROW; }
 
 // ---------------------------------------------------------------------------
 // Pattern masks
@@ -233,12 +268,14 @@ __device__ __forceinline__ void store_pmt(u64* lds, int gl, const u64 pm[4], u64
     if (gl == 0) pmt[64] = ~0ull;
 }
 
-// PMT16 of a 16-lane group (see OFF_PMT16): entries x = -15..64.
-__device__ __forceinline__ void store_pmt16(u64* lds, int gl, const u64 pm[4], u64 tl, u64 th, int nw) {
-    u64* pmt = lds + OFF_PMT16;
+// PMT of a G-lane group on the step-ordered layout (see SoLayout): entries
+// x = -(G-1)..64.
+template <int G>
+__device__ __forceinline__ void store_pmt_so(u64* lds, int gl, const u64 pm[4], u64 tl, u64 th, int nw) {
+    u64* pmt = lds + SoLayout<G>::pmt;
 #pragma unroll
-    for (int u = 0; u < 5; ++u) {
-        const int x = gl - 15 + 16 * u;
+    for (int u = 0; u < (64 + G + G - 1) / G; ++u) {
+        const int x = gl - (G - 1) + G * u;
         const int i = nw - 1 - x;  // column
         const int sh = i & 63;
         const int c = (int)((tl >> sh) & 1ull) | ((int)((th >> sh) & 1ull) << 1);
@@ -287,7 +324,7 @@ __device__ void dc_pass(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int
             const int ip = i - U;
             qpm[u] = pmt[clampi(ip, 0, nw)];
             if (!FIRST) qov[u] = brow[1 + clampi(ip, -1, nw + 1)];
-            const u64 up = LaneShift<G>::up(ov, R);
+            const u64 up = shift_up<G>(ov, R, gl);
             const u64 x = Dp & (((Dp & up) << 1) | lowin);
             R = x & ((R << 1) | pm_t);
             Dp = up;
@@ -297,18 +334,19 @@ __device__ void dc_pass(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int
     }
 }
 
-// dc_pass for 16-lane groups on the step-ordered layout (see OFF_PMT16): the
-// same computation, with the operand reads and the boundary-row write at
-// per-step constant offsets and one clamp for the table store.
-template <bool SPILL, bool FIRST>
-__device__ void dc_pass16(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int stride,
-                          int lds_rows) {
-    constexpr int G = 16;
+// dc_pass for 16- and 32-lane groups on the step-ordered layout (see
+// SoLayout): the same computation, with the operand reads and the
+// boundary-row write at per-step constant offsets and one clamp for the table
+// store.
+template <int G, bool SPILL, bool FIRST>
+__device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int stride,
+                           int lds_rows) {
+    using Lay = SoLayout<G>;
     const int d = c * G + gl;
-    u64* trow = SPILL ? spill + (size_t)(d - lds_rows) * stride : lds + OFF_TAB + d * stride;
-    const u64* pp = lds + OFF_PMT16 - gl;  // + t: PMT16[t - gl]
-    const u64* bp = lds + OFF_BROW16;      // + t: BROW16[t]
-    u64* bw = lds + OFF_BROW16 - 15;       // + t: BROW16[t - 15]
+    u64* trow = SPILL ? spill + (size_t)(d - lds_rows) * stride : lds + Lay::tab + d * stride;
+    const u64* pp = lds + Lay::pmt - gl;   // + t: PMT[t - gl]
+    const u64* bp = lds + Lay::brow;       // + t: BROW[t]
+    u64* bw = lds + Lay::brow - (G - 1);   // + t: BROW[t - (G-1)]
     u64 R = init_word(d);
     u64 Dp = d == 0 ? ~0ull : init_word(d - 1);
     const u64 lowin = d == 0 ? 1ull : 0ull;
@@ -329,11 +367,11 @@ __device__ void dc_pass16(u64* lds, u64* spill, int gl, int c, int nw, int Lc, i
             const int t = t0 + u;
             const u64 pm_t = qpm[u];
             const u64 ov = qov[u];
-            // operands of step t+U; the boundary entry it reads was written by lane 15
-            // at step t+U+15-15 = t+U of the previous pass
+            // operands of step t+U; the boundary entry it reads was written by lane
+            // G-1 at step t+U of the previous pass
             qpm[u] = pp[t + U];
             if (!FIRST) qov[u] = bp[t + U];
-            const u64 up = LaneShift<G>::up(ov, R);
+            const u64 up = shift_up<G>(ov, R, gl);
             const u64 x = Dp & (((Dp & up) << 1) | lowin);
             R = x & ((R << 1) | pm_t);
             Dp = up;
@@ -515,7 +553,7 @@ __device__ TbOut traceback_planes(const u64* lds, const u64* spill, uint32_t* ru
                                   bool writer, u64 pl, u64 ph, u64 tl, u64 th, int mw, int nw,
                                   int dstar, int L, int stride, int lds_rows, int gl, int lane,
                                   bool prefetch) {
-    const u64* tab = lds + OFF_TAB + 1;  // column c of a row sits in slot c + 1
+    const u64* tab = lds + tab_off<G>() + 1;  // column c of a row sits in slot c + 1
     const int jmax = min(mw, L);
     int i = 0, j = 0, d = dstar;
     TbOut o{0, 0, 0, 0u, false};
@@ -626,7 +664,7 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
                              uint32_t budget) {
     const uint64_t run_base = pair_run_base(P, pair);
     const uint64_t run_limit = min(P.cigar_cap, run_base + (uint64_t)pc.m + (uint64_t)pc.n);
-    uint32_t* runs = reinterpret_cast<uint32_t*>(lds + (G == 16 ? OFF_RUNS16 : OFF_BROW));
+    uint32_t* runs = reinterpret_cast<uint32_t*>(lds + runs_off<G>());
     RunState rs{st.cur_op, st.cur_len, st.cur_op >= 0 ? 0 : -1};
     bool overflow = (st.flags & kStateOverflow) != 0;
     bool failed = false, internal = false;
@@ -665,8 +703,8 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
         if (Kr >= 0) {
             u64 pm[4];
             pm_from_planes(pl, ph, mw, pm);
-            if constexpr (G == 16) store_pmt16(lds, gl, pm, tl, th, nw);
-            else store_pmt<G>(lds, gl, pm, tl, th, nw);
+            if constexpr (G == 64) store_pmt<G>(lds, gl, pm, tl, th, nw);
+            else store_pmt_so<G>(lds, gl, pm, tl, th, nw);
             wave_sync();
         }
         int dstar = -1;
@@ -674,13 +712,13 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
         for (int c = 0; c * G <= Kr; ++c) {
             st_steps += (u64)G * (nw + G - 1);
             const bool spill_pass = c * G >= lds_rows;
-            if constexpr (G == 16) {
+            if constexpr (G != 64) {
                 if (spill_pass) {
-                    dc_pass16<true, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    dc_pass_so<G, true, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
                     mem_sync();
                 } else {
-                    if (c == 0) dc_pass16<false, true>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
-                    else dc_pass16<false, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    if (c == 0) dc_pass_so<G, false, true>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    else dc_pass_so<G, false, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
                     wave_sync();
                 }
             } else {
@@ -695,7 +733,7 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
             }
             const int d = c * G + gl;
             const u64 r0 = spill_pass ? load_spill(spill + (size_t)(d - lds_rows) * P.stride + 1)
-                                      : lds[OFF_TAB + d * P.stride + 1];
+                                      : lds[tab_off<G>() + d * P.stride + 1];
             const bool sol = d <= Kr && !((r0 >> (mw - 1)) & 1ull);
             const u64 bits = group_ballot(sol, G, lane);
             if (bits) { dstar = c * G + __builtin_ctzll(bits); break; }
@@ -1380,9 +1418,10 @@ __global__ void k_search_finalize(AlignParams P) {
 // easy queue, and a worker drains the hard queue first, so that the costliest
 // pairs start first and the queue tail is made of cheap ones. With hard_lanes
 // 64 a hard pair takes a whole wavefront (all 64 rows in one pass, the full
-// table in LDS); otherwise every pair runs in a 16-lane group, four pairs per
-// wavefront, with `lds_rows` table rows in LDS and the rows above spilled to
-// device memory.
+// table in LDS); with 32, half a wavefront (32 rows per pass, 32 rows in LDS);
+// otherwise, and always for the easy queue, every pair runs in a 16-lane group,
+// four pairs per wavefront, with `lds_rows` table rows in LDS and the rows
+// above spilled to device memory.
 __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
     extern __shared__ u64 smem[];
     const int lane = threadIdx.x & 63;
@@ -1399,6 +1438,23 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
             if (so.row < 0) continue;  // ended in the search (result already written)
             run_pair<64>(P, smem, nullptr, 64, lane, lane, pair, (int)so.col);
         }
+    } else if (P.hard_lanes == 32) {
+        // two 32-lane groups, each with 32 table rows in LDS (the space of two
+        // 16-lane groups) and rows 32..63 in the spill areas of those two groups
+        // (2 (64 - lds_rows) >= 32 rows, as lds_rows <= 48)
+        const int gl32 = lane & 31;
+        const int h = lane >> 5;
+        u64* lds32 = smem + h * window_group_words32(32, P.stride);
+        u64* spill32 = P.spill + ((uint64_t)blockIdx.x * 4 + 2 * h) * (uint64_t)(64 - P.lds_rows) *
+                                     P.stride;
+        for (uint32_t iter = 0; iter <= n_hard; ++iter) {
+            const uint32_t item = group_pop(P.counters + kCounterHardHead, lds32, gl32);
+            if (item >= n_hard) break;
+            const uint64_t pair = P.hard_list[item];
+            const SearchOut so = P.search[pair];
+            if (so.row < 0) continue;  // ended in the search (result already written)
+            run_pair<32>(P, lds32, spill32, 32, gl32, lane, pair, (int)so.col);
+        }
     }
     const int gl = lane & 15;
     const int grp = lane >> 4;
@@ -1406,7 +1462,7 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
     const int spill_rows = 64 - P.lds_rows;
     u64* spill = spill_rows > 0
         ? P.spill + ((uint64_t)blockIdx.x * 4 + grp) * (uint64_t)spill_rows * P.stride : nullptr;
-    for (int q = P.hard_lanes == 64 ? 1 : 0; q < 2; ++q) {
+    for (int q = P.hard_lanes == 16 ? 0 : 1; q < 2; ++q) {
         const uint32_t* list = q == 0 ? P.hard_list : P.easy_list;
         const uint32_t n = q == 0 ? n_hard : n_easy;
         uint32_t* head = P.counters + (q == 0 ? kCounterHardHead : kCounterEasyHead);

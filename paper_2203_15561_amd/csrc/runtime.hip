@@ -115,16 +115,20 @@ int resolve_launch(const genasm_launch* in, genasm_launch* out) {
     if (in->lds_rows) out->lds_rows = in->lds_rows;
     out->workers_per_cu = in->workers_per_cu;
     if (in->lpt_order >= 0) out->lpt_order = in->lpt_order;
-    if (in->hard_row) out->hard_row = in->hard_row;
+    if (in->hard_row < -1) return GENASM_E_INVAL;
+    if (in->hard_row) out->hard_row = in->hard_row < 0 ? 0 : in->hard_row;  // -1: every pair
     if (in->hard_lanes) out->hard_lanes = in->hard_lanes;
     if (in->tb_prefetch >= 0) out->tb_prefetch = in->tb_prefetch;
     if (out->tb_prefetch != 0 && out->tb_prefetch != 1) return GENASM_E_INVAL;
-    if (out->hard_lanes != 16 && out->hard_lanes != 64) return GENASM_E_INVAL;
+    if (out->hard_lanes != 16 && out->hard_lanes != 32 && out->hard_lanes != 64)
+        return GENASM_E_INVAL;
     if (out->group_lanes != 16 && out->group_lanes != 64) return GENASM_E_INVAL;
     if (out->search_lanes != 16 && out->search_lanes != 64) return GENASM_E_INVAL;
     if (out->lds_rows < 16 || out->lds_rows > 64 || out->lds_rows % 16) return GENASM_E_INVAL;
     if (out->workers_per_cu < 0 || out->workers_per_cu > 32) return GENASM_E_INVAL;
     if (out->hard_row < 0 || out->hard_row > 65) return GENASM_E_INVAL;
+    // 32-lane hard groups spill rows 32..63 into two 16-lane groups' spill areas
+    if (out->hard_lanes == 32 && out->lds_rows > 48) return GENASM_E_INVAL;
     if (out->group_lanes == 64) {
         // every pair on the whole-wavefront path
         out->hard_row = 0;
@@ -517,7 +521,8 @@ int genasm_autotune_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_
     };
     for (int hr : {12, 16, 24, 65}) add(hr, 16, 16, 0, 16);
     add(16, 64, 16, 0, 16);
-    add(0, 64, 16, 0, 16);     // every pair one per wavefront
+    for (int hr : {12, 16, 24}) add(hr, 32, 16, 0, 16);
+    add(-1, 64, 16, 0, 16);    // every pair one per wavefront
     add(16, 16, 32, 0, 16);
     add(16, 16, 16, 4, 16);
     add(16, 16, 16, 0, 64);

@@ -271,11 +271,11 @@ int main(int argc, char** argv) {
         p.items_in = nullptr;
         p.items_out = nullptr;
         const uint32_t n_easy = counters[kCounterEasyLen], n_hard = counters[kCounterHardLen];
-        if (p.hard_lanes == 64) {
+        if (p.hard_lanes != 16) {
             // The window kernel changes lane-group width between its two queues;
             // the emulation runs it once per queue with the matching group width.
             counters[kCounterEasyLen] = 0;
-            emu::group_lanes = 64;
+            emu::group_lanes = p.hard_lanes;
             launch_windows(p, blocks, nullptr);
             counters[kCounterEasyLen] = n_easy;
             counters[kCounterEasyHead] = 0;  // the first launch's easy loop popped past the end

@@ -100,10 +100,16 @@ inline int update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, b
     if (from < 0) out = bound_ctrl ? 0 : old;
     else {
         if (from / b->group_lanes != lane / b->group_lanes) {
-            std::fprintf(stderr, "emu: DPP read across lane groups (%d <- %d)\n", lane, from);
-            std::abort();
+            // 32-lane groups shift with wave_shr:1 and replace what lane 32 reads
+            // from lane 31; a poison value stands in for it
+            if (!(ctrl == 0x138 && b->group_lanes == 32)) {
+                std::fprintf(stderr, "emu: DPP read across lane groups (%d <- %d)\n", lane, from);
+                std::abort();
+            }
+            out = (int)0x5EED5EEDu;
+        } else {
+            out = (int)(unsigned)b->slot[from];
         }
-        out = (int)(unsigned)b->slot[from];
     }
     group_barrier();
     return out;

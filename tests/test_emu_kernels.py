@@ -70,7 +70,8 @@ def test_unimproved_fuzz_and_edges(driver):
         check(driver, ps, emu.UNIMPROVED)
 
 
-@pytest.mark.parametrize("hard_row,hard_lanes", [(16, 16), (0, 64), (65, 16), (4, 64)])
+@pytest.mark.parametrize("hard_row,hard_lanes", [(16, 16), (0, 64), (65, 16), (4, 64), (0, 32),
+                                               (4, 32)])
 def test_fuzz_batched(driver, hard_row, hard_lanes):
     # hard_row 0 with 64 hard lanes sends every pair through the whole-wavefront
     # path, whose 64-lane emulation is slow: fewer and shorter pairs there
@@ -94,11 +95,12 @@ def test_edge_cases_batched(driver):
         check(driver, ps, 1)
 
 
-@pytest.mark.parametrize("hard_row,hard_lanes,tb_prefetch", [(16, 16, 0), (16, 64, 0), (16, 16, 1)])
+@pytest.mark.parametrize("hard_row,hard_lanes,tb_prefetch", [(16, 16, 0), (16, 64, 0), (16, 16, 1),
+                                                              (16, 32, 0), (16, 32, 1)])
 def test_long_read_prefixes_with_decoy(driver, hard_row, hard_lanes, tb_prefetch):
     # 1,200-base prefixes of a true pair and a decoy pair: the decoy's windows
-    # need most of the 64 rows (spilled rows with 16 lanes, the whole-wavefront
-    # path with 64)
+    # need most of the 64 rows (spilled rows with 16 lanes and past row 31 with
+    # 32, the whole-wavefront path with 64)
     ps = gen.make("long10k", 2, start=4)  # pair 4 is a decoy, pair 5 is not
     assert ps.decoy.tolist() == [True, False]
     cut = gen.from_lists("long-prefix", [ps.read(i)[:1200] for i in range(2)],

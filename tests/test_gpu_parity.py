@@ -102,11 +102,15 @@ LAUNCH_VARIANTS = {
     "search64": dict(search_lanes=64),
     "input_order": dict(lpt_order=0),
     "one_worker": dict(workers_per_cu=1),
-    "all_hard": dict(hard_row=0),
-    "all_hard_g64": dict(hard_row=0, hard_lanes=64),
+    "all_hard": dict(hard_row=-1),
+    "all_hard_g64": dict(hard_row=-1, hard_lanes=64),
     "no_hard": dict(hard_row=65),
     "hard_from_8": dict(hard_row=8),
     "hard_g64": dict(hard_row=16, hard_lanes=64),
+    "hard_g32": dict(hard_row=16, hard_lanes=32),
+    "all_hard_g32": dict(hard_row=-1, hard_lanes=32),
+    "hard_g32_rows48": dict(hard_row=12, hard_lanes=32, lds_rows=48),
+    "hard_g32_prefetch": dict(hard_row=16, hard_lanes=32, tb_prefetch=1),
     "tb_prefetch": dict(tb_prefetch=1),
 }
 
