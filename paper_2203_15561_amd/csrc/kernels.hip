@@ -1481,6 +1481,53 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
 // Packing, ordering, compaction
 // ---------------------------------------------------------------------------
 
+// 2-bit code of one ASCII base (case folded): A 0, C 1, G 2, T 3, from bits 1
+// and 2 of the byte; *ok is false for any other byte (coded 0).
+__device__ __forceinline__ unsigned base_code(unsigned ch, bool* ok) {
+    ch &= ~0x20u;
+    *ok = ch == 'A' || ch == 'C' || ch == 'G' || ch == 'T';
+    return *ok ? ((ch >> 1) ^ (ch >> 2)) & 3u : 0u;
+}
+
+// Sixteen bases per thread: one 16-byte load, one 4-byte store. Needs `ascii`
+// 16-byte aligned and `packed` 4-byte aligned; the last partial chunk takes
+// the byte path.
+__global__ void k_pack16(const char* ascii, uint64_t n, uint8_t* packed, uint32_t* bad) {
+    const uint64_t chunk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t b0 = chunk * 16;
+    if (b0 >= n) return;
+    unsigned nbad = 0;
+    if (b0 + 16 <= n) {
+        const uint4 w = *reinterpret_cast<const uint4*>(ascii + b0);
+        const unsigned words[4] = {w.x, w.y, w.z, w.w};
+        unsigned out = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bool ok;
+                out |= base_code((words[q] >> (8 * u)) & 0xFFu, &ok) << (8 * q + 2 * u);
+                nbad += ok ? 0u : 1u;
+            }
+        }
+        *reinterpret_cast<uint32_t*>(packed + chunk * 4) = out;
+    } else {
+        for (uint64_t byte = chunk * 4; byte * 4 < n; ++byte) {
+            unsigned v = 0;
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t b = byte * 4 + u;
+                if (b < n) {
+                    bool ok;
+                    v |= base_code((unsigned char)ascii[b], &ok) << (2 * u);
+                    nbad += ok ? 0u : 1u;
+                }
+            }
+            packed[byte] = (uint8_t)v;
+        }
+    }
+    if (nbad) atomicAdd(bad, nbad);
+}
+
 __global__ void k_pack(const char* ascii, uint64_t n, uint8_t* packed, uint32_t* bad) {
     const uint64_t byte = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (byte * 4 >= n) return;
@@ -1765,6 +1812,12 @@ hipError_t launch_pack(const char* ascii, uint64_t n, uint8_t* packed, uint32_t*
                        hipStream_t s) {
     const uint64_t bytes = (n + 3) / 4;
     if (bytes == 0) return hipSuccess;
+    if (((uintptr_t)ascii & 15) == 0 && ((uintptr_t)packed & 3) == 0) {
+        const uint64_t chunks = (n + 15) / 16;
+        const unsigned blocks = (unsigned)((chunks + 255) / 256);
+        hipLaunchKernelGGL(k_pack16, dim3(blocks), dim3(256), 0, s, ascii, n, packed, bad);
+        return hipGetLastError();
+    }
     const unsigned blocks = (unsigned)((bytes + 255) / 256);
     hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(256), 0, s, ascii, n, packed, bad);
     return hipGetLastError();

@@ -33,6 +33,9 @@ struct dim3 {
     unsigned x, y, z;
     dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
 };
+struct alignas(16) uint4 {
+    unsigned x, y, z, w;
+};
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorInvalidValue = 1 };
 typedef struct ihipStream_t* hipStream_t;

@@ -190,6 +190,37 @@ def test_device_pack_matches_host_pack(ctx):
     assert int(bad.item()) == 1
 
 
+@pytest.mark.parametrize("offset", [0, 1, 16])
+@pytest.mark.parametrize("n", [0, 1, 15, 16, 17, 33, 4099])
+def test_device_pack_sizes_alignment_and_case(ctx, offset, n):
+    # the 16-bases-per-thread kernel (16-byte aligned input) and the byte path
+    # (any other alignment), ragged tails, lower case and bytes outside ACGT
+    import torch
+    rng = np.random.default_rng(100 + n + offset)
+    text = bytearray(gen.to_ascii(rng.integers(0, 4, n).astype(np.uint8)))
+    for q in range(0, n, 5):
+        text[q] = text[q] | 0x20  # lower case
+    bad_at = [q for q in range(3, n, 37)]
+    for q in bad_at:
+        text[q] = ord("N") if q % 2 else ord("x")
+    dev = torch.device("cuda:0")
+    buf = torch.zeros(n + offset + 16, dtype=torch.uint8, device=dev)
+    buf[offset:offset + n] = torch.frombuffer(bytearray(text) or bytearray(1), dtype=torch.uint8)[:n].to(dev)
+    a = buf[offset:offset + n]
+    packed = torch.full(((n + 3) // 4 + 4,), 0xEE, dtype=torch.uint8, device=dev)
+    bad = torch.zeros(1, dtype=torch.int32, device=dev)
+    ctx.pack_dev(a, packed[:(n + 3) // 4], bad)
+    torch.cuda.synchronize()
+    got = packed.cpu().numpy()
+    assert int(bad.item()) == len(bad_at)
+    # bytes outside ACGT are coded 0 (as A)
+    fixed = bytearray(bytes(text).upper())
+    for q in bad_at:
+        fixed[q] = ord("A")
+    assert (got[:(n + 3) // 4] == ga.pack(bytes(fixed))).all()
+    assert (got[(n + 3) // 4:] == 0xEE).all()  # nothing written past the packed length
+
+
 def test_alphabet_error_is_reported(ctx):
     with pytest.raises(ga.GenasmError) as e:
         ctx.align(["ACGT"], ["ACNT"], 5)
