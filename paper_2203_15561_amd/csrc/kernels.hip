@@ -92,7 +92,11 @@ __device__ __forceinline__ u64 shift_up(u64 old, u64 v, int gl) {
 
 // Orders the LDS accesses of one wavefront: the compiler may not move memory
 // operations across it, and it waits for the wavefront's outstanding LDS
-// operations (LDS executes one wavefront's operations in order).
+// operations (LDS executes one wavefront's operations in order). This holds for
+// DS instructions only, so the kernels must reach a group's LDS through
+// pointers the compiler knows to be LDS: an out-of-line callee would get
+// generic pointers and FLAT accesses. The per-pair functions are forced
+// inline, and tests/test_kernel_asm.py checks that the kernels make no calls.
 // s_waitcnt immediates (gfx9 encoding): lgkmcnt(0) alone, and vmcnt(0) lgkmcnt(0).
 constexpr int kWaitLgkm0 = 0xC07F;
 constexpr int kWaitVm0Lgkm0 = 0x0070;
@@ -549,7 +553,7 @@ __device__ __forceinline__ int ctz64(u64 x) { return x ? __builtin_ctzll(x) : 64
 // from the loading lanes instead of from memory, so a spilled edit waits for
 // one load issued an edit earlier rather than for its own.
 template <int G>
-__device__ TbOut traceback_planes(const u64* lds, const u64* spill, uint32_t* runs, RunState& rs,
+__device__ __forceinline__ TbOut traceback_planes(const u64* lds, const u64* spill, uint32_t* runs, RunState& rs,
                                   bool writer, u64 pl, u64 ph, u64 tl, u64 th, int mw, int nw,
                                   int dstar, int L, int stride, int lds_rows, int gl, int lane,
                                   bool prefetch) {
@@ -659,7 +663,7 @@ __device__ __forceinline__ PairState fresh_state(int s) {
 // consumed, or a window without a solution within K) the result and the last
 // CIGAR run are written and st gets kStateDone.
 template <int G>
-__device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds_rows, int gl,
+__device__ __forceinline__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds_rows, int gl,
                              int lane, uint64_t pair, const PairCursor& pc, int s, PairState& st,
                              uint32_t budget) {
     const uint64_t run_base = pair_run_base(P, pair);
@@ -825,7 +829,7 @@ __device__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds
 // Runs (or resumes, when window state persists in P.state) the windows of a
 // pair whose start search hit at column s.
 template <int G>
-__device__ void run_pair(const AlignParams& P, u64* lds, u64* spill, int lds_rows, int gl,
+__device__ __forceinline__ void run_pair(const AlignParams& P, u64* lds, u64* spill, int lds_rows, int gl,
                          int lane, uint64_t pair, int s) {
     const PairCursor pc = pair_cursor(P, pair);
     if (!P.state) {
