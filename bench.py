@@ -259,7 +259,8 @@ def main():
                                               out=out, cigar=cigar, reps=2, total_read_bases=nr,
                                               total_ref_bases=nf, max_ref_len=max_ref)
         tuned = {"tuner_seconds": time.time() - t0, "best_ms": tms}
-        log(f"autotune: hard_row {batched.hard_row}, hard_lanes {batched.hard_lanes}, lds_rows "
+        log(f"autotune: hard_row {batched.hard_row}, hard_lanes {batched.hard_lanes}, hard_share "
+            f"{batched.hard_share}, lds_rows "
             f"{batched.lds_rows}, workers_per_cu {batched.workers_per_cu}, search_lanes "
             f"{batched.search_lanes} ({tms:.2f} ms) in {tuned['tuner_seconds']:.1f} s")
 
@@ -334,6 +335,7 @@ def main():
                    "pairs": ps.n_pairs, "k": ps.k, "W": ps.W, "O": ps.O, "form": "batched",
                    "group_lanes": batched.group_lanes, "lds_rows": batched.lds_rows,
                    "workers_per_cu": batched.workers_per_cu, "hard_row": batched.hard_row,
+                   "hard_share": batched.hard_share,
                    "hard_lanes": batched.hard_lanes, "search_lanes": batched.search_lanes,
                    "autotuned": tuned is not None},
         "autotune": tuned,

@@ -107,6 +107,9 @@ typedef struct {
     int32_t tb_prefetch;     /* batched: 1 = tracebacks over spilled rows load the next row
                                 ahead through the group's lanes, 0 = one load per edit;
                                 -1 = default */
+    int32_t hard_share;      /* batched: percent (0..100) of the window workers that drain
+                                the hard queue before the easy one (the others the other way
+                                round); -1 = default (50) */
 } genasm_launch;
 
 typedef struct genasm_ctx genasm_ctx;

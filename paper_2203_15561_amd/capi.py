@@ -62,6 +62,7 @@ class Launch(ctypes.Structure):
         ("hard_row", ctypes.c_int32),
         ("hard_lanes", ctypes.c_int32),
         ("tb_prefetch", ctypes.c_int32),
+        ("hard_share", ctypes.c_int32),
     ]
 
 

@@ -113,6 +113,7 @@ struct AlignParams {
     int32_t hard_row;
     int32_t hard_lanes;         // 16: the hard list is drained first by 16-lane groups; 64: by whole wavefronts
     int32_t tb_prefetch;        // tracebacks over spilled rows load the next row ahead
+    int32_t hard_share;         // percent of window workers that start on the hard queue
     int32_t route;              // search: append finished pairs to the window lists
     // Optional per-pair layout (serving: sequences sit anywhere in a device pool).
     const uint32_t* read_len;   // if set, pair i's read is [read_off[i], read_off[i] + read_len[i])

@@ -1419,8 +1419,10 @@ __global__ void k_search_finalize(AlignParams P) {
 // Window kernel of the batched form. Each workgroup is one wavefront. Pairs
 // come from two queues filled by the start search: the hard queue (start row
 // >= hard_row: decoy-like pairs whose windows need several DC passes) and the
-// easy queue, and a worker drains the hard queue first, so that the costliest
-// pairs start first and the queue tail is made of cheap ones. With hard_lanes
+// easy queue. A share of the workers drains the hard queue first, so that the
+// costliest pairs start early and the queue tail is made of cheap ones, while
+// the rest start on the easy queue: hard pairs spill table rows to device
+// memory, and fewer of them at a time keeps that traffic in the caches. With hard_lanes
 // 64 a hard pair takes a whole wavefront (all 64 rows in one pass, the full
 // table in LDS); with 32, half a wavefront (32 rows per pass, 32 rows in LDS);
 // otherwise, and always for the easy queue, every pair runs in a 16-lane group,
@@ -1433,43 +1435,50 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
                                               __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t n_easy = __hip_atomic_load(P.counters + kCounterEasyLen, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
-    if (P.hard_lanes == 64) {
-        for (uint32_t iter = 0; iter <= n_hard; ++iter) {
-            const uint32_t item = group_pop(P.counters + kCounterHardHead, smem, lane);
-            if (item >= n_hard) break;
-            const uint64_t pair = P.hard_list[item];
-            const SearchOut so = P.search[pair];
-            if (so.row < 0) continue;  // ended in the search (result already written)
-            run_pair<64>(P, smem, nullptr, 64, lane, lane, pair, (int)so.col);
-        }
-    } else if (P.hard_lanes == 32) {
-        // two 32-lane groups, each with 32 table rows in LDS (the space of two
-        // 16-lane groups) and rows 32..63 in the spill areas of those two groups
-        // (2 (64 - lds_rows) >= 32 rows, as lds_rows <= 48)
-        const int gl32 = lane & 31;
-        const int h = lane >> 5;
-        u64* lds32 = smem + h * window_group_words32(32, P.stride);
-        u64* spill32 = P.spill + ((uint64_t)blockIdx.x * 4 + 2 * h) * (uint64_t)(64 - P.lds_rows) *
-                                     P.stride;
-        for (uint32_t iter = 0; iter <= n_hard; ++iter) {
-            const uint32_t item = group_pop(P.counters + kCounterHardHead, lds32, gl32);
-            if (item >= n_hard) break;
-            const uint64_t pair = P.hard_list[item];
-            const SearchOut so = P.search[pair];
-            if (so.row < 0) continue;  // ended in the search (result already written)
-            run_pair<32>(P, lds32, spill32, 32, gl32, lane, pair, (int)so.col);
-        }
-    }
+    // the first hard_share percent of the workgroups (spread over the CUs by the
+    // dispatch order) drain the hard queue first, the others the easy queue
+    const bool hard_first = (uint64_t)blockIdx.x * 100u < (uint64_t)gridDim.x * (uint32_t)P.hard_share;
     const int gl = lane & 15;
     const int grp = lane >> 4;
     u64* lds = smem + grp * window_group_words(P.lds_rows, P.stride);
     const int spill_rows = 64 - P.lds_rows;
     u64* spill = spill_rows > 0
         ? P.spill + ((uint64_t)blockIdx.x * 4 + grp) * (uint64_t)spill_rows * P.stride : nullptr;
-    for (int q = P.hard_lanes == 16 ? 0 : 1; q < 2; ++q) {
-        const uint32_t* list = q == 0 ? P.hard_list : P.easy_list;
-        const uint32_t n = q == 0 ? n_hard : n_easy;
-        uint32_t* head = P.counters + (q == 0 ? kCounterHardHead : kCounterEasyHead);
+    for (int phase = 0; phase < 2; ++phase) {
+        const bool hard = (phase == 0) == hard_first;
+        if (hard && P.hard_lanes == 64) {
+            for (uint32_t iter = 0; iter <= n_hard; ++iter) {
+                const uint32_t item = group_pop(P.counters + kCounterHardHead, smem, lane);
+                if (item >= n_hard) break;
+                const uint64_t pair = P.hard_list[item];
+                const SearchOut so = P.search[pair];
+                if (so.row < 0) continue;  // ended in the search (result already written)
+                run_pair<64>(P, smem, nullptr, 64, lane, lane, pair, (int)so.col);
+            }
+            continue;
+        }
+        if (hard && P.hard_lanes == 32) {
+            // two 32-lane groups, each with 32 table rows in LDS (the space of two
+            // 16-lane groups) and rows 32..63 in the spill areas of those two
+            // groups (2 (64 - lds_rows) >= 32 rows, as lds_rows <= 48)
+            const int gl32 = lane & 31;
+            const int h = lane >> 5;
+            u64* lds32 = smem + h * window_group_words32(32, P.stride);
+            u64* spill32 = P.spill + ((uint64_t)blockIdx.x * 4 + 2 * h) *
+                                         (uint64_t)(64 - P.lds_rows) * P.stride;
+            for (uint32_t iter = 0; iter <= n_hard; ++iter) {
+                const uint32_t item = group_pop(P.counters + kCounterHardHead, lds32, gl32);
+                if (item >= n_hard) break;
+                const uint64_t pair = P.hard_list[item];
+                const SearchOut so = P.search[pair];
+                if (so.row < 0) continue;  // ended in the search (result already written)
+                run_pair<32>(P, lds32, spill32, 32, gl32, lane, pair, (int)so.col);
+            }
+            continue;
+        }
+        const uint32_t* list = hard ? P.hard_list : P.easy_list;
+        const uint32_t n = hard ? n_hard : n_easy;
+        uint32_t* head = P.counters + (hard ? kCounterHardHead : kCounterEasyHead);
         for (uint32_t iter = 0; iter <= n; ++iter) {
             const uint32_t item = group_pop(head, lds, gl);
             if (item >= n) break;

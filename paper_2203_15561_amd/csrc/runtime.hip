@@ -120,6 +120,8 @@ int resolve_launch(const genasm_launch* in, genasm_launch* out) {
     if (in->hard_lanes) out->hard_lanes = in->hard_lanes;
     if (in->tb_prefetch >= 0) out->tb_prefetch = in->tb_prefetch;
     if (out->tb_prefetch != 0 && out->tb_prefetch != 1) return GENASM_E_INVAL;
+    if (in->hard_share >= 0) out->hard_share = in->hard_share;
+    if (out->hard_share > 100) return GENASM_E_INVAL;
     if (out->hard_lanes != 16 && out->hard_lanes != 32 && out->hard_lanes != 64)
         return GENASM_E_INVAL;
     if (out->group_lanes != 16 && out->group_lanes != 64) return GENASM_E_INVAL;
@@ -169,6 +171,7 @@ int genasm_default_launch(int32_t form, genasm_launch* out) {
     out->hard_row = 16;
     out->hard_lanes = 16;
     out->tb_prefetch = 0;
+    out->hard_share = 50;
     return GENASM_OK;
 }
 
@@ -407,6 +410,7 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     p.hard_row = L.hard_row;
     p.hard_lanes = L.hard_lanes;
     p.tb_prefetch = L.tb_prefetch;
+    p.hard_share = L.hard_share;
     p.route = 1;
     int per_cu = L.workers_per_cu;
     if (per_cu == 0) {
@@ -531,6 +535,11 @@ int genasm_autotune_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_
         genasm_default_launch(GENASM_FORM_BATCHED, &c);
         c.tb_prefetch = 1;
         cands.push_back(c);
+        genasm_default_launch(GENASM_FORM_BATCHED, &c);
+        for (int share : {25, 75, 100}) {
+            c.hard_share = share;
+            cands.push_back(c);
+        }
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     CHECK_HIP(ctx, hipEventCreate(&e0));
@@ -574,12 +583,12 @@ int genasm_tune_cache_save(genasm_ctx* ctx, const char* path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return set_err(ctx, GENASM_E_INVAL, "cannot open tune cache file for writing");
     std::fprintf(f, "# key form group_lanes search_lanes lds_rows workers_per_cu lpt_order hard_row "
-                    "hard_lanes tb_prefetch ms\n");
+                    "hard_lanes tb_prefetch hard_share ms\n");
     for (const auto& kv : ctx->tune) {
         const genasm_launch& L = kv.second.launch;
-        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %.4f\n", kv.first.c_str(), L.form,
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %.4f\n", kv.first.c_str(), L.form,
                      L.group_lanes, L.search_lanes, L.lds_rows, L.workers_per_cu, L.lpt_order,
-                     L.hard_row, L.hard_lanes, L.tb_prefetch, kv.second.ms);
+                     L.hard_row, L.hard_lanes, L.tb_prefetch, L.hard_share, kv.second.ms);
     }
     const bool ok = std::fclose(f) == 0;
     return ok ? GENASM_OK : set_err(ctx, GENASM_E_INVAL, "writing the tune cache failed");
@@ -596,12 +605,12 @@ int genasm_tune_cache_load(genasm_ctx* ctx, const char* path) {
         char key[256];
         genasm_launch L{};
         float ms = 0.f;
-        const int got = std::sscanf(line, "%255s %d %d %d %d %d %d %d %d %d %f", key, &L.form,
+        const int got = std::sscanf(line, "%255s %d %d %d %d %d %d %d %d %d %d %f", key, &L.form,
                                     &L.group_lanes, &L.search_lanes, &L.lds_rows,
                                     &L.workers_per_cu, &L.lpt_order, &L.hard_row, &L.hard_lanes,
-                                    &L.tb_prefetch, &ms);
+                                    &L.tb_prefetch, &L.hard_share, &ms);
         genasm_launch chk;
-        if (got != 11 || resolve_launch(&L, &chk) != GENASM_OK) { rc = GENASM_E_INVAL; break; }
+        if (got != 12 || resolve_launch(&L, &chk) != GENASM_OK) { rc = GENASM_E_INVAL; break; }
         ctx->tune[key] = genasm_ctx::Tuned{L, ms};
     }
     std::fclose(f);

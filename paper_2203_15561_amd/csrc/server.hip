@@ -352,6 +352,7 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     p.lds_rows = lds_rows;
     p.hard_row = 65;
     p.hard_lanes = 16;
+    p.hard_share = 100;
     p.route = 0;
     p.state = srv->d_state;
     p.window_budget = cfg.window_budget;

@@ -5,8 +5,8 @@
 //   emu_driver IN OUT
 // IN : int64 form (0 plain, 1 batched, 2 serving loop, 3 unimproved, 4 filter), group_lanes, search_lanes,
 //      lds_rows, k, W, O, n_pairs, read_bytes, ref_bytes, hard_row, window_budget,
-//      slots, admit_per_iteration, hard_lanes, search_chunk, tb_prefetch; then the packed read
-//      bytes, the packed reference bytes, read_off[n+1], ref_off[n+1] (uint64).
+//      slots, admit_per_iteration, hard_lanes, search_chunk, tb_prefetch, hard_share; then
+//      the packed read bytes, the packed reference bytes, read_off[n+1], ref_off[n+1] (uint64).
 // OUT: n genasm_result records, then (read bases + ref bases) CIGAR elements;
 //      for the filter, n int32 distances then n uint32 starts.
 #include "../../paper_2203_15561_amd/csrc/kernels.hip"
@@ -26,7 +26,7 @@ int main(int argc, char** argv) {
     if (argc != 3) { fprintf(stderr, "usage: emu_driver IN OUT\n"); return 2; }
     FILE* f = fopen(argv[1], "rb");
     if (!f) { perror("open IN"); return 2; }
-    int64_t h[17];
+    int64_t h[18];
     if (!read_all(f, h, sizeof h)) return 2;
     const int form = (int)h[0], G = (int)h[1], SG = (int)h[2], lds_rows = (int)h[3];
     const int k = (int)h[4], W = (int)h[5], O = (int)h[6];
@@ -36,6 +36,7 @@ int main(int argc, char** argv) {
     const int hard_lanes = (int)h[14];
     const uint32_t chunk = (uint32_t)h[15];
     const int tb_prefetch = (int)h[16];
+    const int hard_share = (int)h[17];
     std::vector<uint8_t> reads(nrb + 8), refs(nfb + 8);
     std::vector<uint64_t> roff(n + 1), foff(n + 1);
     if (!read_all(f, reads.data(), nrb) || !read_all(f, refs.data(), nfb) ||
@@ -130,6 +131,7 @@ int main(int argc, char** argv) {
         p.lds_rows = lds_rows;
         p.hard_row = 65;
         p.hard_lanes = 16;
+        p.hard_share = 100;
         p.route = 0;
         p.state = state.data();
         p.window_budget = budget;
@@ -233,6 +235,7 @@ int main(int argc, char** argv) {
         p.hard_row = G == 64 ? 0 : hard_row;
         p.hard_lanes = G == 64 ? 64 : hard_lanes;
         p.tb_prefetch = tb_prefetch;
+        p.hard_share = hard_share;
         p.route = 1;
         p.lds_rows = lds_rows;
         p.search_key = key.data();

@@ -32,16 +32,17 @@ def expected(ps):
             for i in range(ps.n_pairs)]
 
 
-def emulated(driver, ps, form, hard_row=16, hard_lanes=16, tb_prefetch=0):
+def emulated(driver, ps, form, hard_row=16, hard_lanes=16, tb_prefetch=0, hard_share=50):
     res, cig = emu.run(driver, ps, form, 16, 16, 16, hard_row=hard_row, hard_lanes=hard_lanes,
-                       tb_prefetch=tb_prefetch)
+                       tb_prefetch=tb_prefetch, hard_share=hard_share)
     assert (res["flags"] == 0).all()
     return [(int(r["edit_distance"]), c, int(r["ref_begin"]), int(r["ref_end"]), int(r["n_windows"]))
             for r, c in zip(res, cig)]
 
 
-def check(driver, ps, form, hard_row=16, hard_lanes=16, tb_prefetch=0):
-    want, got = expected(ps), emulated(driver, ps, form, hard_row, hard_lanes, tb_prefetch)
+def check(driver, ps, form, hard_row=16, hard_lanes=16, tb_prefetch=0, hard_share=50):
+    want, got = expected(ps), emulated(driver, ps, form, hard_row, hard_lanes, tb_prefetch,
+                                       hard_share)
     bad = [i for i in range(ps.n_pairs) if want[i] != got[i]]
     assert not bad, (bad[:5], want[bad[0]], got[bad[0]])
 

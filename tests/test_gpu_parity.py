@@ -112,6 +112,10 @@ LAUNCH_VARIANTS = {
     "hard_g32_rows48": dict(hard_row=12, hard_lanes=32, lds_rows=48),
     "hard_g32_prefetch": dict(hard_row=16, hard_lanes=32, tb_prefetch=1),
     "tb_prefetch": dict(tb_prefetch=1),
+    "hard_share_0": dict(hard_share=0),
+    "hard_share_100": dict(hard_share=100),
+    "hard_share_30_g32": dict(hard_share=30, hard_lanes=32),
+    "hard_share_70_g64": dict(hard_share=70, hard_lanes=64),
 }
 
 
@@ -333,7 +337,7 @@ def test_autotune_picks_caches_and_reloads(ctx, tmp_path):
         tctx.tune_cache_save(path)
         fields = [ln.split() for ln in open(path) if not ln.startswith("#")]
         assert len(fields) == 1 and int(fields[0][7]) == best.hard_row
-        assert int(fields[0][9]) == best.tb_prefetch
+        assert int(fields[0][9]) == best.tb_prefetch and int(fields[0][10]) == best.hard_share
         other = ga.Context(0)
         try:
             other.tune_cache_load(path)
