@@ -371,16 +371,18 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
             const int t = t0 + u;
             const u64 pm_t = qpm[u];
             const u64 ov = qov[u];
-            // operands of step t+U; the boundary entry it reads was written by lane
-            // G-1 at step t+U of the previous pass
-            qpm[u] = pp[t + U];
-            if (!FIRST) qov[u] = bp[t + U];
             const u64 up = shift_up<G>(ov, R, gl);
             const u64 x = Dp & (((Dp & up) << 1) | lowin);
             R = x & ((R << 1) | pm_t);
             Dp = up;
             trow[med3i(slot0 - t, 0, hi_slot)] = R;
             if (gl == G - 1) bw[t] = R;
+            // operands of step t+U, loaded after this step's last use of the slots
+            // (no register copies); the boundary entry was written by lane G-1 at
+            // step t+U of the previous pass, and this pass's lane G-1 writes entry
+            // t+U only at step t+U+G-1
+            qpm[u] = pp[t + U];
+            if (!FIRST) qov[u] = bp[t + U];
         }
     }
 }
