@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace genasm {
@@ -365,7 +367,9 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
         qpm[u] = pp[u];
         qov[u] = FIRST ? ~0ull : bp[u];
     }
-    for (int t0 = 0; t0 < steps; t0 += U) {
+    // U steps from t0; the table store is left out while every lane's column is
+    // above Lc + 1 (those stores go to the dummy slot)
+    auto chunk = [&](int t0, auto store) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + u;
@@ -375,7 +379,7 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
             const u64 x = Dp & (((Dp & up) << 1) | lowin);
             R = x & ((R << 1) | pm_t);
             Dp = up;
-            trow[med3i(slot0 - t, 0, hi_slot)] = R;
+            if constexpr (decltype(store)::value) trow[med3i(slot0 - t, 0, hi_slot)] = R;
             if (gl == G - 1) bw[t] = R;
             // operands of step t+U, loaded after this step's last use of the slots
             // (no register copies); the boundary entry was written by lane G-1 at
@@ -384,7 +388,13 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
             qpm[u] = pp[t + U];
             if (!FIRST) qov[u] = bp[t + U];
         }
-    }
+    };
+    // lane g stores into slot min(nw + g - t, Lc + 2): the dummy for every lane
+    // while t <= nw - Lc - 2
+    const int t_free = nw - Lc - 1;
+    int t0 = 0;
+    for (; t0 + U <= t_free; t0 += U) chunk(t0, std::integral_constant<bool, false>{});
+    for (; t0 < steps; t0 += U) chunk(t0, std::integral_constant<bool, true>{});
 }
 
 // ---------------------------------------------------------------------------
