@@ -369,7 +369,7 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
     }
     // U steps from t0; the table store is left out while every lane's column is
     // above Lc + 1 (those stores go to the dummy slot)
-    auto chunk = [&](int t0, auto store) {
+    auto chunk = [&](int t0, auto store, auto brow_store) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + u;
@@ -380,7 +380,9 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
             R = x & ((R << 1) | pm_t);
             Dp = up;
             if constexpr (decltype(store)::value) trow[med3i(slot0 - t, 0, hi_slot)] = R;
-            if (gl == G - 1) bw[t] = R;
+            if constexpr (decltype(brow_store)::value) {
+                if (gl == G - 1) bw[t] = R;
+            }
             // operands of step t+U, loaded after this step's last use of the slots
             // (no register copies); the boundary entry was written by lane G-1 at
             // step t+U of the previous pass, and this pass's lane G-1 writes entry
@@ -390,11 +392,33 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
         }
     };
     // lane g stores into slot min(nw + g - t, Lc + 2): the dummy for every lane
-    // while t <= nw - Lc - 2
+    // while t <= nw - Lc - 2. Lane G-1's boundary-row entries for columns <= Lc
+    // (steps t >= nw + G - 2 - Lc) are left out: the table row holds them, and
+    // fill_brow copies them when a next pass needs the boundary row.
+    using yes = std::integral_constant<bool, true>;
+    using no = std::integral_constant<bool, false>;
     const int t_free = nw - Lc - 1;
+    const int t_bskip = nw + G - 2 - Lc;
     int t0 = 0;
-    for (; t0 + U <= t_free; t0 += U) chunk(t0, std::integral_constant<bool, false>{});
-    for (; t0 < steps; t0 += U) chunk(t0, std::integral_constant<bool, true>{});
+    for (; t0 + U <= t_free; t0 += U) chunk(t0, no{}, yes{});
+    for (; t0 < steps && t0 < t_bskip; t0 += U) chunk(t0, yes{}, yes{});
+    for (; t0 < steps; t0 += U) chunk(t0, yes{}, no{});
+}
+
+// Completes the boundary row entering pass c >= 1 (the last row of pass c-1):
+// its entries for columns 0..Lc come from that row's table slots (LDS, or the
+// spill for rows at or above lds_rows).
+template <int G>
+__device__ __forceinline__ void fill_brow(u64* lds, const u64* spill, int gl, int c, int nw, int Lc,
+                                          int stride, int lds_rows) {
+    const int r = c * G - 1;
+    const u64* row = r >= lds_rows ? spill + (size_t)(r - lds_rows) * stride
+                                   : lds + SoLayout<G>::tab + r * stride;
+    u64* b = lds + SoLayout<G>::brow;
+    for (int col = gl; col <= Lc && col < nw; col += G) {
+        const u64 v = r >= lds_rows ? load_spill(row + 1 + col) : row[1 + col];
+        b[nw - 1 - col] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -729,6 +753,10 @@ __device__ __forceinline__ void advance_pair(const AlignParams& P, u64* lds, u64
             st_steps += (u64)G * (nw + G - 1);
             const bool spill_pass = c * G >= lds_rows;
             if constexpr (G != 64) {
+                if (c >= 1) {
+                    fill_brow<G>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    wave_sync();
+                }
                 if (spill_pass) {
                     dc_pass_so<G, true, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
                     mem_sync();
