@@ -383,12 +383,18 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
             if constexpr (decltype(brow_store)::value) {
                 if (gl == G - 1) bw[t] = R;
             }
-            // operands of step t+U, loaded after this step's last use of the slots
-            // (no register copies); the boundary entry was written by lane G-1 at
-            // step t+U of the previous pass, and this pass's lane G-1 writes entry
-            // t+U only at step t+U+G-1
-            qpm[u] = pp[t + U];
-            if (!FIRST) qov[u] = bp[t + U];
+            // operands of steps t+U-1 and t+U, loaded in pairs of adjacent words
+            // after both slots' last use (no register copies); the boundary
+            // entries were written by lane G-1 at those steps of the previous
+            // pass, and this pass's lane G-1 writes entry t+U only at step t+U+G-1
+            if (u & 1) {
+                qpm[u - 1] = pp[t - 1 + U];
+                qpm[u] = pp[t + U];
+                if (!FIRST) {
+                    qov[u - 1] = bp[t - 1 + U];
+                    qov[u] = bp[t + U];
+                }
+            }
         }
     };
     // lane g stores into slot min(nw + g - t, Lc + 2): the dummy for every lane
