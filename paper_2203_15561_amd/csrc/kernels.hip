@@ -541,9 +541,9 @@ struct TbOut {
 
 // Run-length CIGAR under construction, kept with the same values in every lane
 // of a group. The runs of the current window go to an LDS array (`runs`, the
-// boundary-row area, free during the traceback), written by one lane: slot nr
-// holds the open run and is rewritten at every step, and nr moves on when the
-// op changes, so a step needs no branch. At the end of each window the group
+// boundary-row area, free during the traceback), written with the same value
+// by every lane of the group: slot nr holds the open run and is rewritten at
+// every step, and nr moves on when the op changes, so a step needs no branch. At the end of each window the group
 // copies the closed runs to device memory; the open run is carried into the
 // next window's slot 0, so runs merge across window seams.
 struct RunState {
@@ -558,7 +558,10 @@ __device__ __forceinline__ void run_push(uint32_t* runs, RunState& rs, int op, u
     rs.nr += changed ? 1 : 0;
     rs.cur_len = changed ? count : rs.cur_len + count;
     rs.cur_op = op;
-    if (writer) runs[rs.nr] = (rs.cur_len << 2) | (uint32_t)op;
+    // every lane of the group stores the same word to the same slot: no
+    // execution mask to set up around the store
+    (void)writer;
+    runs[rs.nr] = (rs.cur_len << 2) | (uint32_t)op;
 }
 
 // Before a window's traceback: the open run moves to slot 0.
