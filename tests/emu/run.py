@@ -66,8 +66,9 @@ def run(driver: str, ps, form: int, group_lanes=16, search_lanes=16, lds_rows=16
 def run_filter(driver: str, ps, k: int, timeout=600):
     """Returns (distances, starts) of the filter kernel under emulation."""
     reads2b, refs2b = pack2b(ps.reads), pack2b(ps.refs)
+    # same header layout as run() (the batched-form fields are unused here)
     hdr = np.array([FILTER, 64, 64, 64, k, ps.W, ps.O, ps.n_pairs, len(reads2b), len(refs2b),
-                    65, 0, 0, 0, 16, 0, 0], dtype=np.int64)
+                    65, 0, 0, 0, 16, 0, 0, 100], dtype=np.int64)
     with tempfile.TemporaryDirectory() as tmp:
         fin, fout = os.path.join(tmp, "in.bin"), os.path.join(tmp, "out.bin")
         with open(fin, "wb") as f:
