@@ -89,6 +89,49 @@ def test_long10k_subset(ctx, form):
     assert_same(ps, expected(ps), on_gpu(ctx, ps, FORMS[form]), f"long10k/{form}")
 
 
+def test_long10k_full_batch(ctx):
+    # The headline workload at its full size (20,000 pairs) in the device form with
+    # the default launch, as the benchmark runs it: every pair's CIGAR consumes
+    # exactly its read and its reported reference span and its edits add up to
+    # the reported edit distance; 96 sampled pairs (decoys and true pairs, the
+    # first and the last of the batch) equal the oracle exactly.
+    import torch
+    ps = gen.make("long10k")
+    dev = torch.device("cuda:0")
+    r2 = torch.from_numpy(ga.pack(ps.reads)).to(dev)
+    f2 = torch.from_numpy(ga.pack(ps.refs)).to(dev)
+    ro = torch.from_numpy(ps.read_off.astype(np.int64)).to(dev)
+    fo = torch.from_numpy(ps.ref_off.astype(np.int64)).to(dev)
+    out, cig = ctx.align_dev(r2, ro, f2, fo, ps.k)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().view(ga.RESULT_DTYPE).reshape(-1)[:ps.n_pairs]
+    el = cig.cpu().numpy().view(np.uint32)
+    assert (res["flags"] == 0).all()
+    assert (res["edit_distance"] >= 0).all()
+    m = np.diff(ps.read_off.astype(np.int64))
+    n = np.diff(ps.ref_off.astype(np.int64))
+    off = res["cigar_off"].astype(np.int64)
+    cnt = res["cigar_len"].astype(np.int64)
+    pair = np.repeat(np.arange(ps.n_pairs), cnt)
+    start = np.repeat(off - np.concatenate(([0], np.cumsum(cnt)[:-1])), cnt)
+    e = el[np.arange(cnt.sum()) + start]
+    length, op = (e >> 2).astype(np.int64), e & 3
+    read_used = np.bincount(pair, length * (op != 3), ps.n_pairs)
+    ref_used = np.bincount(pair, length * (op != 2), ps.n_pairs)
+    edits = np.bincount(pair, length * (op != 0), ps.n_pairs)
+    span = res["ref_end"].astype(np.int64) - res["ref_begin"].astype(np.int64)
+    assert (read_used == m).all()
+    assert (ref_used == span).all() and (res["ref_end"] <= n).all()
+    assert (edits == res["edit_distance"]).all()
+    rng = np.random.default_rng(2024)
+    sample = sorted(set([0, 1, ps.n_pairs - 1]) | set(rng.choice(ps.n_pairs, 93, replace=False).tolist()))
+    sub = ps.subset(np.array(sample))
+    assert sub.decoy.any() and not sub.decoy.all()
+    got = [(int(res["edit_distance"][i]), int(res["ref_begin"][i]), int(res["ref_end"][i]),
+            int(res["n_windows"][i]), ga.decode_cigar(el[off[i]:off[i] + cnt[i]])) for i in sample]
+    assert_same(sub, expected(sub), got, "long10k full batch")
+
+
 @pytest.mark.parametrize("form", sorted(FORMS))
 def test_uneven_subset(ctx, form):
     ps = gen.make("uneven", 300)
