@@ -444,9 +444,15 @@ __device__ void search_rows(u64* lds, int gl, int lane, const uint8_t* refs, uin
     constexpr int BPL = 64 / G;  // text bases each lane converts per 64-column block
     constexpr int O = RS * G;
     const int top = m1 - 1;
-    // columns n..n+63 lie past the text end: the all-mismatch mask
+    // columns n..n+63 lie past the text end: the all-mismatch mask. Word 128
+    // repeats word 0, so that the entries of two consecutive steps are always
+    // adjacent words (one paired read)
 #pragma unroll
-    for (int u = 0; u < BPL; ++u) ring[(n + gl * BPL + u) & 127] = ~0ull;
+    for (int u = 0; u < BPL; ++u) {
+        const int w = (n + gl * BPL + u) & 127;
+        ring[w] = ~0ull;
+        if (w == 0) ring[128] = ~0ull;
+    }
 
     u64 R[RS], Dp[RS];
     int hit[RS];
@@ -472,6 +478,7 @@ __device__ void search_rows(u64* lds, int gl, int lane, const uint8_t* refs, uin
 
     const int steps = n + O - 1;
     const int nblk = (steps + 63) / 64;
+    u64 pm_pair[RS][2];
     unsigned cur = fetch(0);
     for (int blk = 0; blk < nblk; ++blk) {
         // fill ring entries of this block's columns, prefetch the next block's bases
@@ -479,21 +486,33 @@ __device__ void search_rows(u64* lds, int gl, int lane, const uint8_t* refs, uin
 #pragma unroll
         for (int u = 0; u < BPL; ++u) {
             const int col = c0 + u;
-            ring[col & 127] = pick_pm(p0, p1, p2, p3, (cur >> (2 * u)) & 3);
+            const u64 v = pick_pm(p0, p1, p2, p3, (cur >> (2 * u)) & 3);
+            ring[col & 127] = v;
+            if ((col & 127) == 0) ring[128] = v;
         }
         cur = fetch(blk + 1);
         wave_sync();
         const int t0 = blk * 64;
-#pragma unroll 8
+#pragma unroll 4
         for (int tt = 0; tt < 64; ++tt) {
             const int t = t0 + tt;
             u64 rot[RS];
 #pragma unroll
             for (int s = 0; s < RS; ++s) rot[s] = LaneShift<G>::rot(R[s]);
+            // even steps read the entries of this step and the next as one pair
+            // (columns i and i-1: words (i-1)&127 + 1 and (i-1)&127)
+            if ((tt & 1) == 0) {
+#pragma unroll
+                for (int s = 0; s < RS; ++s) {
+                    const int b = (n - 2 - t + s * G + gl) & 127;
+                    pm_pair[s][0] = ring[b + 1];
+                    pm_pair[s][1] = ring[b];
+                }
+            }
 #pragma unroll
             for (int s = 0; s < RS; ++s) {
                 const int i = n - 1 - t + s * G + gl;
-                const u64 pm_t = ring[i & 127];
+                const u64 pm_t = pm_pair[s][tt & 1];
                 const u64 up = gl == 0 ? (s == 0 ? ~0ull : rot[s - 1]) : rot[s];
                 const u64 li = s == 0 ? lowin : 0ull;
                 const u64 x = Dp[s] & (((Dp[s] & up) << 1) | li);
