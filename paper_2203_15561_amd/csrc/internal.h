@@ -111,7 +111,7 @@ struct AlignParams {
     uint32_t* easy_list;        // pairs for the 16-lane window groups (filled by the search)
     uint32_t* hard_list;        // pairs for whole-wavefront windows (start row >= hard_row)
     int32_t hard_row;
-    int32_t hard_lanes;         // 16: the hard list is drained first by 16-lane groups; 64: by whole wavefronts
+    int32_t hard_lanes;         // lanes per pair for the hard list: 16, 32 (two pairs per wavefront) or 64
     int32_t tb_prefetch;        // tracebacks over spilled rows load the next row ahead
     int32_t hard_share;         // percent of window workers that start on the hard queue
     int32_t route;              // search: append finished pairs to the window lists

@@ -157,9 +157,12 @@ constexpr int OFF_RING = 4;    // start search: 128-word text-mask ring (reuses 
 // Layout of a 16-lane window group (in step order, so that a DC step needs no
 // address arithmetic): PMT16[x] = PM[T[nw-1-x]] at word OFF_PMT16 + x for
 // x in -15..63 (~0 below 0 and from nw on); BROW16[z] = the pass's last row at
-// column nw-1-z at word OFF_BROW16 + z, written for z in -15..nw-1 and read
-// for z in 0..nw+18. Lane g at step t reads PMT16[t-g]; lane 0 reads BROW16[t];
-// lane 15 writes BROW16[t-15]. The regions nobody needs overlap: PMT16 past
+// column nw-1-z at word OFF_BROW16 + z, written for z from -15 on (by lane 15,
+// for the columns past the stored range; the others are copied from the table
+// row before a next pass) and read for z in 0..nw+29 (the operand loads run U
+// steps ahead of whole U-step chunks). Lane g at step t reads PMT16[t-g]; lane
+// 0 reads BROW16[t]; lane 15 writes BROW16[t-15]. The regions nobody needs
+// overlap: PMT16 past
 // x = 63 (read only by finished lanes) with BROW16 below z = 0 (written only
 // by lanes ahead of the text), and BROW16 past z = 63 (read only by finished
 // lanes) with the broadcast slots and the first table row.
@@ -170,7 +173,7 @@ static_assert(OFF_PMT16 + 64 + 15 == OFF_BROW16, "layout");
 
 // The same step-ordered layout for G-lane groups (G = 16 or 32): PMT at word
 // G-1+x for x in -(G-1)..64, BROW at word 2(G-1)+64+z, written for z in
-// -(G-1)..nw-1 and read for z in 0..nw+G+6, the table after the header. The
+// -(G-1)..nw-1 and read for z in 0..nw+G+13, the table after the header. The
 // 32-lane header ends past BROW[63] (word 189); the reads past it go into the
 // first table row, and the broadcast slot lies inside BROW (group_pop uses it
 // only between pairs). Run records go at OFF_BROW16 (16 lanes) or OFF_BROW
