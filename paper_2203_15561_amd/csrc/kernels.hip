@@ -634,9 +634,9 @@ __device__ __forceinline__ TbOut traceback_planes(const u64* lds, const u64* spi
     // every pass of the loop consumes a read or text base, or leaves it
     for (int it = 0; it <= 2 * L; ++it) {
         if (j >= jmax || i >= L) break;
-        const int delta = i - j;
-        const u64 mis = delta >= 0 ? (((pl ^ (tl >> delta)) | (ph ^ (th >> delta))) >> j)
-                                   : ((((pl >> -delta) ^ tl) | ((ph >> -delta) ^ th)) >> i);
+        // read bases j.. against text bases i.. (j, i < 64 here; the zeros shifted
+        // in past the words are cut by the limits below)
+        const u64 mis = ((pl >> j) ^ (tl >> i)) | ((ph >> j) ^ (th >> i));
         const int k = min(ctz64(mis), min(jmax - j, min(L - i, nw - i)));
         if (k > 0) {
             run_push(runs, rs, GENASM_OP_MATCH, (uint32_t)k, writer);
