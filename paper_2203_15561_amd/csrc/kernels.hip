@@ -638,8 +638,16 @@ __device__ __forceinline__ TbOut traceback_planes(const u64* lds, const u64* spi
         // in past the words are cut by the limits below)
         const u64 mis = ((pl >> j) ^ (tl >> i)) | ((ph >> j) ^ (th >> i));
         const int k = min(ctz64(mis), min(jmax - j, min(L - i, nw - i)));
-        if (k > 0) {
-            run_push(runs, rs, GENASM_OP_MATCH, (uint32_t)k, writer);
+        {
+            // the match run, without a branch: with k = 0 nothing changes and the
+            // open run's record is rewritten (slot 0 before the pair's first op,
+            // which that op then overwrites)
+            const bool push = k > 0;
+            const bool changed = push && rs.cur_op != (int)GENASM_OP_MATCH;
+            rs.nr += changed ? 1 : 0;
+            rs.cur_len = changed ? (uint32_t)k : rs.cur_len + (uint32_t)k;
+            rs.cur_op = push ? (int)GENASM_OP_MATCH : rs.cur_op;
+            runs[max(rs.nr, 0)] = (rs.cur_len << 2) | (uint32_t)rs.cur_op;
             i += k;
             j += k;
             if (j >= jmax || i >= L) break;
