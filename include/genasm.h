@@ -211,8 +211,9 @@ int genasm_filter_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t*
 /*
  * Autotuner for the batched form. Runs the device-form call above on the given
  * batch with each candidate launch configuration (lanes per pair for the
- * decoy-like queue and its threshold row, table rows kept in LDS, resident
- * workers per compute unit, lanes per pair in the start search), `reps` timed
+ * decoy-like queue and its threshold row, the share of workers starting on
+ * that queue, table rows kept in LDS, resident workers per compute unit, lanes
+ * per pair in the start search, traceback prefetch), `reps` timed
  * runs each after one untimed run, and writes the fastest to *best (and its
  * time in ms to *best_ms if not NULL). Every run writes complete results, so
  * d_out/d_cigar hold the batch's alignment afterwards. The pick is cached in
