@@ -222,7 +222,6 @@ def main():
     bad = torch.zeros(1, dtype=torch.int32, device=dev)
     out = torch.empty((ps.n_pairs, 32), dtype=torch.uint8, device=dev)
     cigar = torch.empty(nr + nf, dtype=torch.int32, device=dev)
-    max_ref = int(np.diff(ps.ref_off).max())
 
     ctx = ga.Context(0)
     kw = {}
@@ -243,7 +242,7 @@ def main():
         ctx.pack_dev(reads_ascii, reads2b, bad)
         ctx.pack_dev(refs_ascii, refs2b, bad)
         ctx.align_dev(reads2b, roff, refs2b, foff, ps.k, ps.W, ps.O, launch=launch, out=out,
-                      cigar=cigar, total_read_bases=nr, total_ref_bases=nf, max_ref_len=max_ref)
+                      cigar=cigar, total_read_bases=nr, total_ref_bases=nf)
 
     # warm-up
     for _ in range(args.warmup):
@@ -257,7 +256,7 @@ def main():
         t0 = time.time()
         batched, tms, _, _ = ctx.autotune_dev(reads2b, roff, refs2b, foff, ps.k, ps.W, ps.O,
                                               out=out, cigar=cigar, reps=2, total_read_bases=nr,
-                                              total_ref_bases=nf, max_ref_len=max_ref)
+                                              total_ref_bases=nf)
         tuned = {"tuner_seconds": time.time() - t0, "best_ms": tms}
         log(f"autotune: hard_row {batched.hard_row}, hard_lanes {batched.hard_lanes}, hard_share "
             f"{batched.hard_share}, lds_rows "
@@ -419,7 +418,7 @@ def main():
             gctx.pack_dev(reads_ascii, reads2b, bad)
             gctx.pack_dev(refs_ascii, refs2b, bad)
             gctx.align_dev(reads2b, roff, refs2b, foff, ps.k, ps.W, ps.O, launch=batched, out=out,
-                           cigar=cigar, total_read_bases=nr, total_ref_bases=nf, max_ref_len=max_ref)
+                           cigar=cigar, total_read_bases=nr, total_ref_bases=nf)
 
         with torch.cuda.stream(gs):
             gstep()

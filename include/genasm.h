@@ -52,8 +52,12 @@ extern "C" {
 #define GENASM_E_NOSPACE (-5)   /* output buffer too small; the needed size is reported */
 #define GENASM_E_BUSY (-6)      /* serving: request refused, admission budget exhausted */
 #define GENASM_E_TOOLONG (-7)   /* a sequence is longer than 2^31 - 1 bases */
+#define GENASM_E_PINNED (-8)    /* the context's device buffers are held by a captured graph
+                                   and the call would have to grow them (see genasm_unpin) */
 
-/* Per-pair result. 32 bytes, 8-byte aligned. */
+/* Per-pair result (the alignment the traceback retrieves: Introduction, the
+ * traceback step; its edit count is the sum of the windows' committed edits).
+ * 32 bytes, 8-byte aligned. */
 typedef struct {
     int32_t edit_distance; /* total committed edits, -1 if some window had no solution within k */
     uint32_t ref_begin;    /* alignment covers reference bases [ref_begin, ref_end) */
@@ -116,11 +120,23 @@ typedef struct genasm_ctx genasm_ctx;
 
 /* Creates a context on HIP device `hip_device`. The context owns a stream,
  * device scratch (grown on demand, reused across calls) and kernel handles.
- * Returns GENASM_E_DEVICE if no such device exists or it is not gfx950. */
+ * Returns GENASM_E_DEVICE if no such device exists or it is not gfx950,
+ * GENASM_E_NOMEM if the host allocation fails. (Library plumbing; the paper
+ * defines no such object.) */
 int genasm_create(genasm_ctx** out, int hip_device);
 
 /* Frees everything the context owns. Safe on NULL. */
 void genasm_destroy(genasm_ctx* ctx);
+
+/* Graph capture and the context's buffers. A genasm_batch_align_dev call made
+ * while its stream is being captured records kernels that use the context's
+ * device buffers by address, so such a call pins the context: from then on a
+ * call that would need larger buffers fails with GENASM_E_PINNED instead of
+ * freeing them (size them first with an eager call of the largest shape).
+ * genasm_unpin declares that no captured graph uses them any more (the graphs
+ * were destroyed), after which calls may grow them again. Returns
+ * GENASM_E_INVAL for a NULL context. */
+int genasm_unpin(genasm_ctx* ctx);
 
 /* Message of the last error on this context (never NULL). With ctx == NULL:
  * the reason of the calling thread's last failed genasm_create. */
@@ -133,7 +149,10 @@ const char* genasm_strerror(int code);
 int genasm_default_launch(int32_t form, genasm_launch* out);
 
 /*
- * Host-memory form, synchronous.
+ * Host-memory form, synchronous. Defined by: the paper's Introduction (DP
+ * table of GenASM-DC with key ideas 1-3, then GenASM-TB to retrieve the
+ * alignment) applied to each (read, reference) candidate pair, as in its
+ * Results section; windowing with W and O as in GenASM.
  *   reads, refs      ASCII sequences (ACGT, either case), concatenated.
  *   read_off,        n_pairs + 1 non-decreasing offsets: pair i is
  *   ref_off          reads[read_off[i] .. read_off[i+1]) against
@@ -146,9 +165,13 @@ int genasm_default_launch(int32_t form, genasm_launch* out);
  *                    cigar_cap == 0.
  *   cigar_needed     receives the number of characters the CIGARs need.
  *   launch           NULL for the default batched launch.
- * Returns GENASM_E_NOSPACE (results are still written, CIGAR text is not)
- * when cigar_cap < *cigar_needed. The caller owns every buffer; nothing is
- * retained after the call returns.
+ * Returns GENASM_E_NOSPACE when cigar_cap < *cigar_needed: *cigar_needed is
+ * set and nothing else is written (no partial results; call again with a
+ * buffer of that size). GENASM_E_INVAL for bad k/W/O, null pointers or
+ * decreasing offsets, GENASM_E_TOOLONG for a sequence of 2^31 bases or more,
+ * GENASM_E_ALPHABET for a byte outside ACGTacgt, GENASM_E_NOMEM or
+ * GENASM_E_DEVICE on allocation or HIP failure. The caller owns every buffer;
+ * nothing is retained after the call returns.
  */
 int genasm_batch_align(genasm_ctx* ctx, const char* reads, const uint64_t* read_off,
                        const char* refs, const uint64_t* ref_off, uint64_t n_pairs,
@@ -157,7 +180,8 @@ int genasm_batch_align(genasm_ctx* ctx, const char* reads, const uint64_t* read_
 
 /*
  * Device-memory form, asynchronous on `stream` (a hipStream_t; NULL = the
- * null stream).
+ * null stream). Defined by: as genasm_batch_align (Introduction, key ideas
+ * 1-3 and the traceback step; Results, candidate pairs).
  *   d_reads2b,       2-bit packed sequences in device memory: base b of the
  *   d_refs2b         stream is bits 2*(b%4)..2*(b%4)+1 of byte b/4, codes
  *                    A=0, C=1, G=2, T=3 (see genasm_pack).
@@ -174,21 +198,27 @@ int genasm_batch_align(genasm_ctx* ctx, const char* reads, const uint64_t* read_
  *   total_read_bases, total_ref_bases
  *                    d_read_off[n_pairs] - d_read_off[0] and the same for refs
  *                    (sizes the device scratch without a device-to-host copy).
- *   max_ref_len      an upper bound on the longest reference (sizes scratch).
  * The caller keeps every buffer alive until the stream has passed this call.
  * Scratch is owned by the context; calls on one context are serialized on
  * its device scratch, so do not run two calls of one context on different
- * streams at once.
+ * streams at once. Errors (nothing is launched): GENASM_E_INVAL for bad
+ * k/W/O, null pointers or launch parameters, GENASM_E_NOSPACE when cigar_cap
+ * is below total_read_bases + total_ref_bases, GENASM_E_NOMEM when scratch
+ * cannot grow, GENASM_E_PINNED when it would have to grow on a pinned context
+ * (see genasm_unpin), GENASM_E_DEVICE on a HIP error. The call can be captured
+ * into a HIP graph once the context's buffers are sized for its shape.
  */
 int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
                            const uint8_t* d_refs2b, const uint64_t* d_ref_off, uint64_t n_pairs,
                            uint64_t total_read_bases, uint64_t total_ref_bases,
-                           uint32_t max_ref_len, int32_t k, int32_t W, int32_t O,
+                           int32_t k, int32_t W, int32_t O,
                            genasm_result* d_out, uint32_t* d_cigar, uint64_t cigar_cap,
                            const genasm_launch* launch, void* stream);
 
 /*
- * Pre-alignment filter (score-only mode): the DC recurrence over the whole
+ * Pre-alignment filter (score-only mode). Defined by: the Introduction's
+ * place of edit-distance calculation ahead of alignment (pre-alignment
+ * filtering), with GenASM-DC's recurrence: the DC recurrence over the whole
  * read, with no table and no traceback (GenASM-DC used as a filter ahead of
  * alignment, the use the paper's introduction gives for edit-distance
  * calculation). For pair i, dist[i] = the least edit distance between read i
@@ -209,7 +239,8 @@ int genasm_filter_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t*
                       void* stream);
 
 /*
- * Autotuner for the batched form. Runs the device-form call above on the given
+ * Autotuner for the batched form (library plumbing, no paper passage: picks
+ * the launch geometry of the device form). Runs the device-form call above on the given
  * batch with each candidate launch configuration (lanes per pair for the
  * decoy-like queue and its threshold row, the share of workers starting on
  * that queue, table rows kept in LDS, resident workers per compute unit, lanes
@@ -224,7 +255,7 @@ int genasm_filter_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t*
  */
 int genasm_autotune_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
                         const uint8_t* d_refs2b, const uint64_t* d_ref_off, uint64_t n_pairs,
-                        uint64_t total_read_bases, uint64_t total_ref_bases, uint32_t max_ref_len,
+                        uint64_t total_read_bases, uint64_t total_ref_bases,
                         int32_t k, int32_t W, int32_t O, genasm_result* d_out, uint32_t* d_cigar,
                         uint64_t cigar_cap, int32_t reps, void* stream, genasm_launch* best,
                         float* best_ms);
@@ -234,7 +265,8 @@ int genasm_tune_cache_load(genasm_ctx* ctx, const char* path);
 int genasm_tune_cache_size(genasm_ctx* ctx);
 
 /*
- * Packs n ASCII bases (host memory) into 2-bit codes (host memory, (n+3)/4
+ * Packs n ASCII bases (host memory) into 2-bit codes (input loading of the
+ * candidate pairs of the Results section; host memory, (n+3)/4
  * bytes, layout as for genasm_batch_align_dev). Returns GENASM_E_ALPHABET and
  * sets *bad_index (if not NULL) to the first offending byte.
  */
@@ -260,7 +292,9 @@ int genasm_validate(const char* reads, uint64_t reads_len, const uint64_t* read_
                     uint64_t n_pairs, int32_t k, int32_t W, int32_t O);
 
 /*
- * Profiling of genasm_batch_align_dev calls (off by default). While enabled,
+ * Profiling of genasm_batch_align_dev calls (off by default); the counters
+ * measure what key ideas 1-3 save (Abstract and Introduction: DP-table
+ * footprint and accesses). While enabled,
  * each call records HIP events around its stages on the call's stream and
  * fills per-pair work counters; genasm_profile_read waits for the last
  * profiled call and returns its stage times and the counters summed over
@@ -304,7 +338,9 @@ int genasm_profile_read(genasm_ctx* ctx, genasm_profile* out);
 int genasm_profile_pairs(genasm_ctx* ctx, uint64_t* out, uint64_t max_words, uint64_t* words);
 
 /*
- * Serving form: continuous batching of single-pair requests.
+ * Serving form: continuous batching of single-pair requests (library
+ * plumbing around the same per-pair computation as genasm_batch_align:
+ * Introduction, key ideas 1-3 and the traceback step).
  *
  * A server owns an engine thread and device-resident state: a pool of packed
  * read and reference bases, a pool of CIGAR elements, and per-slot window

@@ -22,6 +22,7 @@ E_DEVICE = -4
 E_NOSPACE = -5
 E_BUSY = -6
 E_TOOLONG = -7
+E_PINNED = -8
 
 FORM_PLAIN = 0
 FORM_BATCHED = 1
@@ -144,7 +145,7 @@ EXPORTS = [
     "genasm_completion_release", "genasm_server_stats_read", "genasm_server_destroy",
     "genasm_now_ns", "genasm_filter", "genasm_filter_dev", "genasm_autotune_dev",
     "genasm_tune_cache_save", "genasm_tune_cache_load", "genasm_tune_cache_size",
-    "genasm_profile_pairs",
+    "genasm_profile_pairs", "genasm_unpin",
 ]
 
 _c = ctypes
@@ -161,7 +162,7 @@ _SIGS = {
                                       _c.c_void_p, _c.c_uint64, _u64p, _c.POINTER(Launch)]),
     "genasm_batch_align_dev": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                           _c.c_void_p, _c.c_uint64, _c.c_uint64, _c.c_uint64,
-                                          _c.c_uint32, _c.c_int32, _c.c_int32, _c.c_int32,
+                                          _c.c_int32, _c.c_int32, _c.c_int32,
                                           _c.c_void_p, _c.c_void_p, _c.c_uint64,
                                           _c.POINTER(Launch), _c.c_void_p]),
     "genasm_pack": (_c.c_int, [_c.c_char_p, _c.c_uint64, _c.c_void_p, _u64p]),
@@ -183,10 +184,11 @@ _SIGS = {
     "genasm_now_ns": (_c.c_uint64, []),
     "genasm_autotune_dev": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                        _c.c_void_p, _c.c_uint64, _c.c_uint64, _c.c_uint64,
-                                       _c.c_uint32, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p,
+                                       _c.c_int32, _c.c_int32, _c.c_int32, _c.c_void_p,
                                        _c.c_void_p, _c.c_uint64, _c.c_int32, _c.c_void_p,
                                        _c.POINTER(Launch), _c.POINTER(_c.c_float)]),
     "genasm_profile_pairs": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_uint64, _u64p]),
+    "genasm_unpin": (_c.c_int, [_c.c_void_p]),
     "genasm_tune_cache_save": (_c.c_int, [_c.c_void_p, _c.c_char_p]),
     "genasm_tune_cache_load": (_c.c_int, [_c.c_void_p, _c.c_char_p]),
     "genasm_tune_cache_size": (_c.c_int, [_c.c_void_p]),
@@ -323,6 +325,10 @@ class Context:
         except Exception:  # noqa: BLE001 - interpreter shutdown
             pass
 
+    def unpin(self):
+        """Declares that no captured graph uses this context's buffers any more."""
+        self._check(lib().genasm_unpin(self._ctx), "genasm_unpin")
+
     def last_error(self) -> str:
         return lib().genasm_last_error(self._ctx).decode()
 
@@ -360,7 +366,7 @@ class Context:
 
     def align_dev(self, reads2b, read_off, refs2b, ref_off, k: int, W: int = 64, O: int = 24,
                   launch: Launch | None = None, out=None, cigar=None, stream=None,
-                  total_read_bases=None, total_ref_bases=None, max_ref_len: int = 0):
+                  total_read_bases=None, total_ref_bases=None):
         """Device-memory form on torch tensors (uint8 packed streams, int64
         offsets). Returns (out uint8 tensor [n, 32], cigar int32 tensor)."""
         import torch
@@ -378,7 +384,7 @@ class Context:
             stream = torch.cuda.current_stream(read_off.device).cuda_stream
         rc = lib().genasm_batch_align_dev(
             self._ctx, reads2b.data_ptr(), read_off.data_ptr(), refs2b.data_ptr(),
-            ref_off.data_ptr(), n, total_read_bases, total_ref_bases, max_ref_len, k, W, O,
+            ref_off.data_ptr(), n, total_read_bases, total_ref_bases, k, W, O,
             out.data_ptr(), cigar.data_ptr(), cigar.numel(),
             ctypes.byref(launch) if launch is not None else None, stream)
         self._check(rc, "genasm_batch_align_dev")
@@ -416,7 +422,7 @@ class Context:
 
     def autotune_dev(self, reads2b, read_off, refs2b, ref_off, k: int, W: int = 64, O: int = 24,
                      out=None, cigar=None, reps: int = 1, stream=None, total_read_bases=None,
-                     total_ref_bases=None, max_ref_len: int = 0):
+                     total_ref_bases=None):
         """Times the batched-form candidates on this batch; returns (Launch, ms, out, cigar)
         and caches the pick for calls without an explicit launch."""
         import torch
@@ -436,7 +442,7 @@ class Context:
         ms = ctypes.c_float(0.0)
         rc = lib().genasm_autotune_dev(
             self._ctx, reads2b.data_ptr(), read_off.data_ptr(), refs2b.data_ptr(),
-            ref_off.data_ptr(), n, total_read_bases, total_ref_bases, max_ref_len, k, W, O,
+            ref_off.data_ptr(), n, total_read_bases, total_ref_bases, k, W, O,
             out.data_ptr(), cigar.data_ptr(), cigar.numel(), reps, stream, ctypes.byref(best),
             ctypes.byref(ms))
         self._check(rc, "genasm_autotune_dev")

@@ -27,6 +27,10 @@ struct genasm_ctx {
     // host-form staging (device)
     char* stage = nullptr;
     size_t stage_cap = 0;
+    // set by a device-form call made under stream capture: a graph may hold
+    // raw pointers into the buffers above, so they must not be freed or moved
+    // until genasm_unpin
+    bool pinned = false;
     // profiling
     bool profiling = false;
     bool have_profile = false;

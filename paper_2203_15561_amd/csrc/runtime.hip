@@ -38,8 +38,15 @@ int set_err(genasm_ctx* ctx, int code, const char* what, hipError_t e = hipSucce
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Grows a device buffer to at least `need` bytes (contents are not kept).
+// A pinned context (one whose buffers a captured graph may use) never frees or
+// moves them: the call fails instead.
 int ensure(genasm_ctx* ctx, char** buf, size_t* cap, size_t need) {
     if (need <= *cap) return GENASM_OK;
+    if (ctx->pinned)
+        return set_err(ctx, GENASM_E_PINNED,
+                       "the context's device buffers are held by a captured graph and cannot grow: "
+                       "size them with an eager call before capture, or call genasm_unpin once "
+                       "no graph uses them");
     if (*buf) {
         // the buffer may be in use by earlier calls on any stream
         hipError_t e = hipDeviceSynchronize();
@@ -155,6 +162,7 @@ const char* genasm_strerror(int code) {
         case GENASM_E_NOSPACE: return "output buffer too small";
         case GENASM_E_BUSY: return "request refused: admission budget exhausted";
         case GENASM_E_TOOLONG: return "sequence longer than 2^31-1 bases";
+        case GENASM_E_PINNED: return "context buffers are held by a captured graph";
         default: return "unknown error";
     }
 }
@@ -234,6 +242,12 @@ void genasm_destroy(genasm_ctx* ctx) {
     delete ctx;
 }
 
+int genasm_unpin(genasm_ctx* ctx) {
+    if (!ctx) return GENASM_E_INVAL;
+    ctx->pinned = false;
+    return GENASM_OK;
+}
+
 const char* genasm_last_error(const genasm_ctx* ctx) {
     return ctx ? ctx->err.c_str() : g_create_err.c_str();
 }
@@ -309,10 +323,9 @@ int genasm_pack_dev(genasm_ctx* ctx, const char* d_ascii, uint64_t n, uint8_t* d
 int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
                            const uint8_t* d_refs2b, const uint64_t* d_ref_off, uint64_t n_pairs,
                            uint64_t total_read_bases, uint64_t total_ref_bases,
-                           uint32_t max_ref_len, int32_t k, int32_t W, int32_t O,
+                           int32_t k, int32_t W, int32_t O,
                            genasm_result* d_out, uint32_t* d_cigar, uint64_t cigar_cap,
                            const genasm_launch* launch, void* stream) {
-    (void)max_ref_len;
     if (!ctx) return GENASM_E_INVAL;
     if (!valid_wko(k, W, O)) return set_err(ctx, GENASM_E_INVAL, "W must be in [2,64], O in [0,W-1], k >= 0");
     if (n_pairs == 0) return GENASM_OK;
@@ -331,6 +344,12 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     if (rc) return set_err(ctx, rc, "bad launch parameters");
     hipStream_t s = (hipStream_t)stream;  // NULL: the null stream
     CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    {
+        // a call recorded into a graph pins the context's buffers
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        CHECK_HIP(ctx, hipStreamIsCapturing(s, &cs));
+        if (cs != hipStreamCaptureStatusNone) ctx->pinned = true;
+    }
 
     AlignParams p{};
     p.reads = d_reads2b;
@@ -501,7 +520,7 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
 
 int genasm_autotune_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
                         const uint8_t* d_refs2b, const uint64_t* d_ref_off, uint64_t n_pairs,
-                        uint64_t total_read_bases, uint64_t total_ref_bases, uint32_t max_ref_len,
+                        uint64_t total_read_bases, uint64_t total_ref_bases,
                         int32_t k, int32_t W, int32_t O, genasm_result* d_out, uint32_t* d_cigar,
                         uint64_t cigar_cap, int32_t reps, void* stream, genasm_launch* best,
                         float* best_ms) {
@@ -549,14 +568,14 @@ int genasm_autotune_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_
     for (const genasm_launch& c : cands) {
         // a first run sizes the scratch for this shape, then timed runs
         rc = genasm_batch_align_dev(ctx, d_reads2b, d_read_off, d_refs2b, d_ref_off, n_pairs,
-                                    total_read_bases, total_ref_bases, max_ref_len, k, W, O, d_out,
+                                    total_read_bases, total_ref_bases, k, W, O, d_out,
                                     d_cigar, cigar_cap, &c, stream);
         if (rc) break;
         float t_min = 1e30f;
         for (int r = 0; r < reps && !rc; ++r) {
             if (hipEventRecord(e0, s) != hipSuccess) { rc = GENASM_E_DEVICE; break; }
             rc = genasm_batch_align_dev(ctx, d_reads2b, d_read_off, d_refs2b, d_ref_off, n_pairs,
-                                        total_read_bases, total_ref_bases, max_ref_len, k, W, O,
+                                        total_read_bases, total_ref_bases, k, W, O,
                                         d_out, d_cigar, cigar_cap, &c, stream);
             float ms = 0.f;
             if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -786,11 +805,9 @@ int genasm_batch_align(genasm_ctx* ctx, const char* reads, const uint64_t* read_
     const uint64_t nr = read_off[n_pairs] - read_off[0];
     const uint64_t nf = ref_off[n_pairs] - ref_off[0];
     std::vector<uint64_t> roff(n_pairs + 1), foff(n_pairs + 1);
-    uint32_t max_ref = 0;
     for (uint64_t i = 0; i <= n_pairs; ++i) {
         roff[i] = read_off[i] - read_off[0];
         foff[i] = ref_off[i] - ref_off[0];
-        if (i) max_ref = std::max<uint32_t>(max_ref, (uint32_t)(foff[i] - foff[i - 1]));
     }
     Carver dry{nullptr};
     auto carve = [&](Carver& c) {
@@ -832,15 +849,18 @@ int genasm_batch_align(genasm_ctx* ctx, const char* reads, const uint64_t* read_
     CHECK_HIP(ctx, hipStreamSynchronize(s));
     if (bad) return set_err(ctx, GENASM_E_ALPHABET, "sequence byte outside ACGTacgt");
 
-    rc = genasm_batch_align_dev(ctx, b.pr, b.or_, b.pf, b.of, n_pairs, nr, nf, max_ref, k, W, O,
+    rc = genasm_batch_align_dev(ctx, b.pr, b.or_, b.pf, b.of, n_pairs, nr, nf, k, W, O,
                                 b.res, b.cig, nr + nf + 1, &L, s);
     if (rc) return rc;
-    CHECK_HIP(ctx, hipMemcpyAsync(out, b.res, n_pairs * sizeof(genasm_result),
+    // results are staged on the host: out[] is written only when the CIGAR
+    // text fits, so GENASM_E_NOSPACE leaves no partial results
+    std::vector<genasm_result> res(n_pairs);
+    CHECK_HIP(ctx, hipMemcpyAsync(res.data(), b.res, n_pairs * sizeof(genasm_result),
                                   hipMemcpyDeviceToHost, s));
     CHECK_HIP(ctx, hipStreamSynchronize(s));
     // Gather the CIGAR elements of all pairs into one dense buffer.
     std::vector<uint64_t> dst(n_pairs + 1, 0);
-    for (uint64_t i = 0; i < n_pairs; ++i) dst[i + 1] = dst[i] + out[i].cigar_len;
+    for (uint64_t i = 0; i < n_pairs; ++i) dst[i + 1] = dst[i] + res[i].cigar_len;
     const uint64_t n_elems = dst[n_pairs];
     std::vector<uint32_t> elems(n_elems);
     if (n_elems) {
@@ -873,20 +893,18 @@ int genasm_batch_align(genasm_ctx* ctx, const char* reads, const uint64_t* read_
     for (uint64_t i = 0; i < n_pairs; ++i) tpos[i + 1] += tpos[i];
     const uint64_t need = tpos[n_pairs];
     *cigar_needed = need;
-    const bool fits = need <= cigar_cap;
+    if (need > cigar_cap) return set_err(ctx, GENASM_E_NOSPACE, "cigar_cap below the CIGAR text size");
+    parallel([&](uint64_t lo, uint64_t hi) {
+        for (uint64_t i = lo; i < hi; ++i) {
+            char* w = cigar_buf + tpos[i];
+            for (uint64_t e = dst[i]; e < dst[i + 1]; ++e) w = cigar_run_text(elems[e], w);
+        }
+    });
     for (uint64_t i = 0; i < n_pairs; ++i) {
-        out[i].cigar_off = tpos[i];
-        out[i].cigar_len = (uint32_t)(tpos[i + 1] - tpos[i]);
+        res[i].cigar_off = tpos[i];
+        res[i].cigar_len = (uint32_t)(tpos[i + 1] - tpos[i]);
     }
-    if (fits) {
-        parallel([&](uint64_t lo, uint64_t hi) {
-            for (uint64_t i = lo; i < hi; ++i) {
-                char* w = cigar_buf + tpos[i];
-                for (uint64_t e = dst[i]; e < dst[i + 1]; ++e) w = cigar_run_text(elems[e], w);
-            }
-        });
-    }
-    if (!fits) return set_err(ctx, GENASM_E_NOSPACE, "cigar_cap below the CIGAR text size");
+    std::memcpy(out, res.data(), n_pairs * sizeof(genasm_result));
     return GENASM_OK;
 }
 

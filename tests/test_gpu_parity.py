@@ -306,7 +306,7 @@ def test_graph_capture_replays(ctx, form):
     gctx = ga.Context(0)
     try:
         kw = dict(launch=FORMS[form], out=out, cigar=cigar, total_read_bases=nr,
-                  total_ref_bases=nf, max_ref_len=int(np.diff(ps.ref_off).max()))
+                  total_ref_bases=nf)
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
@@ -389,3 +389,83 @@ def test_autotune_picks_caches_and_reloads(ctx, tmp_path):
             other.close()
     finally:
         tctx.close()
+
+
+def test_captured_context_refuses_to_grow(ctx):
+    # A call recorded into a graph pins the context: a later call that needs
+    # larger buffers fails with GENASM_E_PINNED instead of freeing what the
+    # graph uses, the graph keeps replaying correct results, and after
+    # genasm_unpin (graph gone) the context grows again.
+    import torch
+    small = gen.make("uneven", 100, start=4000)
+    big = gen.make("uneven", 2000, start=4000)
+    dev = torch.device("cuda:0")
+
+    def tensors(ps):
+        return (torch.from_numpy(ga.pack(ps.reads)).to(dev), torch.from_numpy(ps.read_off.astype(np.int64)).to(dev),
+                torch.from_numpy(ga.pack(ps.refs)).to(dev), torch.from_numpy(ps.ref_off.astype(np.int64)).to(dev))
+
+    ts, tb = tensors(small), tensors(big)
+    nr, nf = int(small.read_off[-1]), int(small.ref_off[-1])
+    out = torch.empty((small.n_pairs, 32), dtype=torch.uint8, device=dev)
+    cigar = torch.empty(nr + nf, dtype=torch.int32, device=dev)
+    want = expected(small)
+    gctx = ga.Context(0)
+    try:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            gctx.align_dev(*ts, small.k, out=out, cigar=cigar)  # sizes the buffers
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            gctx.align_dev(*ts, small.k, out=out, cigar=cigar)
+        with pytest.raises(ga.GenasmError) as e:
+            gctx.align_dev(*tb, big.k)
+        assert e.value.code == ga.capi.E_PINNED
+        torch.cuda.synchronize()
+        for rep in range(2):
+            out.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert_same(small, want, _decode_dev(out, cigar, small.n_pairs), f"pinned replay {rep}")
+        del g
+        torch.cuda.synchronize()
+        gctx.unpin()
+        bout, bcig = gctx.align_dev(*tb, big.k)
+        torch.cuda.synchronize()
+        assert_same(big, expected(big), _decode_dev(bout, bcig, big.n_pairs), "after unpin")
+    finally:
+        gctx.close()
+
+
+def test_host_form_nospace_writes_nothing(ctx):
+    # GENASM_E_NOSPACE reports the size needed and leaves the results untouched
+    import ctypes
+    ps = gen.make("short100", 20)
+    r, roff = ga.capi._concat([ps.read(i) for i in range(ps.n_pairs)])
+    f, foff = ga.capi._concat([ps.ref(i) for i in range(ps.n_pairs)])
+    out = np.full(ps.n_pairs, 0x5A, dtype=np.uint8).repeat(32).view(ga.RESULT_DTYPE)
+    before = out.copy()
+    buf = np.full(8, 0x33, dtype=np.uint8)
+    need = ctypes.c_uint64(0)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    rc = ga.capi.lib().genasm_batch_align(ctx._ctx, r, roff.ctypes.data_as(u64p), f,
+                                          foff.ctypes.data_as(u64p), ps.n_pairs, ps.k, ps.W, ps.O,
+                                          out.ctypes.data, buf.ctypes.data, len(buf),
+                                          ctypes.byref(need), None)
+    assert rc == ga.capi.E_NOSPACE
+    assert need.value > len(buf)
+    assert out.tobytes() == before.tobytes() and (buf == 0x33).all()
+    # with the reported size the call succeeds and matches the oracle
+    buf = np.zeros(need.value, dtype=np.uint8)
+    rc = ga.capi.lib().genasm_batch_align(ctx._ctx, r, roff.ctypes.data_as(u64p), f,
+                                          foff.ctypes.data_as(u64p), ps.n_pairs, ps.k, ps.W, ps.O,
+                                          out.ctypes.data, buf.ctypes.data, len(buf),
+                                          ctypes.byref(need), None)
+    assert rc == 0
+    text = buf.tobytes()
+    got = [(int(x["edit_distance"]), int(x["ref_begin"]), int(x["ref_end"]), int(x["n_windows"]),
+            text[int(x["cigar_off"]):int(x["cigar_off"]) + int(x["cigar_len"])].decode()) for x in out]
+    assert_same(ps, expected(ps), got, "after E_NOSPACE")

@@ -159,3 +159,26 @@ def test_submit_errors(ctx):
         got = drain(srv, [4])
         assert as_tuple(got[4]) == (0, 0, 4, 1, "4=")
         assert srv.stats()["submitted"] == 1
+
+
+def test_many_requests_match_oracle(ctx):
+    # 2,500 requests of the serving mix (70% 150 bp, 30% 1-30 kb), all queued
+    # at once: every completion equals the oracle, CIGAR included
+    ps = gen.make("serving", 2500, start=20000)
+    want = expected(ps)
+    with ga.Server(ctx, ps.k, ps.W, ps.O) as srv:
+        tags = list(range(ps.n_pairs))
+        got = {}
+        for t in tags:
+            while True:
+                rc = srv.submit(ps.read(t), ps.ref(t), t)
+                if rc != ga.capi.E_BUSY:
+                    break
+                for c in srv.poll(timeout_ms=1):
+                    got[c["tag"]] = c
+            assert rc == 0, (t, rc)
+        got.update(drain(srv, [t for t in tags if t not in got], timeout_s=240))
+        st = srv.stats()
+    bad = [t for t in tags if as_tuple(got[t]) != want[t]]
+    assert not bad, (len(bad), bad[:5], want[bad[0]][:4], as_tuple(got[bad[0]])[:4])
+    assert st["completed"] == ps.n_pairs and st["resident"] == 0

@@ -168,6 +168,35 @@ def test_dc_invariants(oracle_lib):
             assert hit == (T[i:i + m] == P), (P, T, i)
 
 
+def test_equal_bases_make_the_match_edge_valid(oracle_lib):
+    """The property the device traceback's match-run shortcut rests on: at a
+    valid cell (bit p of R[d][i] is 0) whose read and text bases agree
+    (P[m-1-p] == T[i], i < n), the match edge is valid too (p == 0, or bit p-1
+    of R[d][i+1] is 0). Checked on every cell of every row of the oracle's DC
+    over random and related pairs, windows of every length up to 64 included."""
+    rng = np.random.default_rng(77)
+    related = gen.fuzz(4242, 400, max_len=140, related=0.9)
+    checked = 0
+    for t in range(700):
+        if t < 400:
+            P, T = codes_to_str(related[t][0][:64]), codes_to_str(related[t][1][:200])
+        else:
+            P, T = rand_str(rng, int(rng.integers(1, 65))), rand_str(rng, int(rng.integers(0, 130)))
+        m, n = len(P), len(T)
+        if m == 0 or n == 0:
+            continue
+        K = min(64, m)
+        R = oracle_lib.dc_rows(P, T, K)
+        used = np.uint64((1 << m) - 1) if m < 64 else np.uint64(~0 & (2**64 - 1))
+        eq = {c: sum(1 << q for q in range(m) if P[m - 1 - q] == c) for c in "ACGT"}
+        E = np.array([eq[T[i]] for i in range(n)], dtype=np.uint64)
+        valid_eq = ~R[:, :n] & E[None, :] & used
+        violated = valid_eq & (R[:, 1:] << np.uint64(1))
+        assert not violated.any(), (P, T, np.argwhere(violated)[:3])
+        checked += int(np.unpackbits(valid_eq.view(np.uint8)).sum())
+    assert checked > 5_000_000, checked
+
+
 # --------------------------------------------------------------------------
 # Whole alignments
 # --------------------------------------------------------------------------
