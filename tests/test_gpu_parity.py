@@ -419,7 +419,10 @@ def test_captured_context_refuses_to_grow(ctx):
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=s):
-            gctx.align_dev(*ts, small.k, out=out, cigar=cigar)
+            # totals given: reading them from the offsets would copy to the host
+            gctx.align_dev(*ts, small.k, out=out, cigar=cigar,
+                           total_read_bases=nr - int(small.read_off[0]),
+                           total_ref_bases=nf - int(small.ref_off[0]))
         with pytest.raises(ga.GenasmError) as e:
             gctx.align_dev(*tb, big.k)
         assert e.value.code == ga.capi.E_PINNED
