@@ -54,6 +54,8 @@ extern "C" {
 #define GENASM_E_TOOLONG (-7)   /* a sequence is longer than 2^31 - 1 bases */
 #define GENASM_E_PINNED (-8)    /* the context's device buffers are held by a captured graph
                                    and the call would have to grow them (see genasm_unpin) */
+#define GENASM_E_SCRATCH (-9)   /* genasm_batch_align_dev_noalloc: the batch needs more device
+                                   scratch than GENASM_NOALLOC_SCRATCH_BYTES */
 
 /* Per-pair result (the alignment the traceback retrieves: Introduction, the
  * traceback step; its edit count is the sum of the windows' committed edits).
@@ -214,6 +216,40 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
                            int32_t k, int32_t W, int32_t O,
                            genasm_result* d_out, uint32_t* d_cigar, uint64_t cigar_cap,
                            const genasm_launch* launch, void* stream);
+
+/*
+ * No-allocation variant of genasm_batch_align_dev, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. Arguments, layouts, ownership and results
+ * are those of genasm_batch_align_dev, for the plain and batched forms. The
+ * device scratch (bit planes of both streams, start-search items and keys,
+ * window queues, the longest-first order, spilled window-table rows) comes
+ * from a static device array of GENASM_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every device it runs on until the process ends; the call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine) and does not
+ * pin the context. With workers_per_cu = 0 the batched form runs the largest
+ * resident window-worker count whose spill fits the array beside the batch.
+ * The bit planes take about (total_read_bases + total_ref_bases) / 4 bytes;
+ * the batched form adds about 40 bytes per pair and 0.3 bytes per reference
+ * base, plus the spill of its window workers (16 KB each at W = 64, O = 24
+ * with 16 table rows in LDS).
+ * All calls on one device share the array, which keeps the last call's
+ * contents; every call rewrites what it reads from it with kernels on its own
+ * stream before reading. Calls that overlap in time on one device, from any
+ * context or stream, race on it and give wrong results: serialize them.
+ * Errors: as genasm_batch_align_dev, plus GENASM_E_SCRATCH (nothing is
+ * launched; genasm_last_error gives the bytes needed) when the batch needs
+ * more than the array, GENASM_E_INVAL for the unimproved form. Profiling
+ * counters (genasm_profile_enable) are not recorded by this call.
+ */
+#define GENASM_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int genasm_batch_align_dev_noalloc(genasm_ctx* ctx, const uint8_t* d_reads2b,
+                                   const uint64_t* d_read_off, const uint8_t* d_refs2b,
+                                   const uint64_t* d_ref_off, uint64_t n_pairs,
+                                   uint64_t total_read_bases, uint64_t total_ref_bases,
+                                   int32_t k, int32_t W, int32_t O,
+                                   genasm_result* d_out, uint32_t* d_cigar, uint64_t cigar_cap,
+                                   const genasm_launch* launch, void* stream);
 
 /*
  * Pre-alignment filter (score-only mode). Defined by: the Introduction's

@@ -23,6 +23,10 @@ E_NOSPACE = -5
 E_BUSY = -6
 E_TOOLONG = -7
 E_PINNED = -8
+E_SCRATCH = -9
+
+# bytes of the static device scratch of the no-allocation device form
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 FORM_PLAIN = 0
 FORM_BATCHED = 1
@@ -145,7 +149,7 @@ EXPORTS = [
     "genasm_completion_release", "genasm_server_stats_read", "genasm_server_destroy",
     "genasm_now_ns", "genasm_filter", "genasm_filter_dev", "genasm_autotune_dev",
     "genasm_tune_cache_save", "genasm_tune_cache_load", "genasm_tune_cache_size",
-    "genasm_profile_pairs", "genasm_unpin",
+    "genasm_profile_pairs", "genasm_unpin", "genasm_batch_align_dev_noalloc",
 ]
 
 _c = ctypes
@@ -165,6 +169,12 @@ _SIGS = {
                                           _c.c_int32, _c.c_int32, _c.c_int32,
                                           _c.c_void_p, _c.c_void_p, _c.c_uint64,
                                           _c.POINTER(Launch), _c.c_void_p]),
+    "genasm_batch_align_dev_noalloc": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                                  _c.c_void_p, _c.c_void_p, _c.c_uint64,
+                                                  _c.c_uint64, _c.c_uint64, _c.c_int32,
+                                                  _c.c_int32, _c.c_int32, _c.c_void_p,
+                                                  _c.c_void_p, _c.c_uint64, _c.POINTER(Launch),
+                                                  _c.c_void_p]),
     "genasm_pack": (_c.c_int, [_c.c_char_p, _c.c_uint64, _c.c_void_p, _u64p]),
     "genasm_pack_dev": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_uint64, _c.c_void_p,
                                    _c.c_void_p, _c.c_void_p]),
@@ -366,9 +376,12 @@ class Context:
 
     def align_dev(self, reads2b, read_off, refs2b, ref_off, k: int, W: int = 64, O: int = 24,
                   launch: Launch | None = None, out=None, cigar=None, stream=None,
-                  total_read_bases=None, total_ref_bases=None):
+                  total_read_bases=None, total_ref_bases=None, noalloc: bool = False):
         """Device-memory form on torch tensors (uint8 packed streams, int64
-        offsets). Returns (out uint8 tensor [n, 32], cigar int32 tensor)."""
+        offsets). Returns (out uint8 tensor [n, 32], cigar int32 tensor).
+        noalloc=True calls genasm_batch_align_dev_noalloc (the library's static
+        device scratch; out and cigar should then be given too, since
+        allocating them here would defeat the purpose)."""
         import torch
         n = read_off.numel() - 1
         if total_read_bases is None:
@@ -382,12 +395,13 @@ class Context:
             cigar = torch.empty(max(cap, 1), dtype=torch.int32, device=read_off.device)
         if stream is None:
             stream = torch.cuda.current_stream(read_off.device).cuda_stream
-        rc = lib().genasm_batch_align_dev(
+        name = "genasm_batch_align_dev_noalloc" if noalloc else "genasm_batch_align_dev"
+        rc = getattr(lib(), name)(
             self._ctx, reads2b.data_ptr(), read_off.data_ptr(), refs2b.data_ptr(),
             ref_off.data_ptr(), n, total_read_bases, total_ref_bases, k, W, O,
             out.data_ptr(), cigar.data_ptr(), cigar.numel(),
             ctypes.byref(launch) if launch is not None else None, stream)
-        self._check(rc, "genasm_batch_align_dev")
+        self._check(rc, name)
         return out, cigar
 
     def filter(self, reads, refs, k: int):

@@ -27,6 +27,9 @@ struct genasm_ctx {
     // host-form staging (device)
     char* stage = nullptr;
     size_t stage_cap = 0;
+    // device address of the static scratch of the no-allocation device form
+    // on this context's device
+    void* static_scratch = nullptr;
     // set by a device-form call made under stream capture: a graph may hold
     // raw pointers into the buffers above, so they must not be freed or moved
     // until genasm_unpin

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -16,7 +17,35 @@
 
 using namespace genasm;
 
+// Device scratch of genasm_batch_align_dev_noalloc, one copy on every GPU the
+// library runs on, held until the process ends. In host code the name stands
+// for a host-side shadow, not a device address: host code reaches the array
+// only through the address static_scratch_ptr obtained for the device.
+static __device__ __align__(256) char scratch[GENASM_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+// Device address of `scratch` on each device, looked up once per device (with
+// that device current) by genasm_create.
+std::mutex g_static_mu;
+constexpr int kMaxDevices = 64;
+void* g_static_ptr[kMaxDevices] = {};
+
+hipError_t static_scratch_ptr(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[device]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_static_ptr[device] = ptr;
+    }
+    *out = g_static_ptr[device];
+    return hipSuccess;
+}
+
 
 #define CHECK_HIP(ctx, expr)                                                              \
     do {                                                                                  \
@@ -163,6 +192,7 @@ const char* genasm_strerror(int code) {
         case GENASM_E_BUSY: return "request refused: admission budget exhausted";
         case GENASM_E_TOOLONG: return "sequence longer than 2^31-1 bases";
         case GENASM_E_PINNED: return "context buffers are held by a captured graph";
+        case GENASM_E_SCRATCH: return "batch needs more than the no-allocation call's static scratch";
         default: return "unknown error";
     }
 }
@@ -222,6 +252,12 @@ int genasm_create(genasm_ctx** out, int hip_device) {
     if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) {
         delete ctx;
         return create_fail(GENASM_E_DEVICE, "hipStreamCreateWithFlags", e);
+    }
+    // the no-allocation entry point's scratch on this device
+    if ((e = static_scratch_ptr(hip_device, &ctx->static_scratch)) != hipSuccess) {
+        (void)hipStreamDestroy(ctx->stream);
+        delete ctx;
+        return create_fail(GENASM_E_DEVICE, "hipGetSymbolAddress of the static scratch", e);
     }
     *out = ctx;
     return GENASM_OK;
@@ -320,12 +356,19 @@ int genasm_pack_dev(genasm_ctx* ctx, const char* d_ascii, uint64_t n, uint8_t* d
     return GENASM_OK;
 }
 
-int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
-                           const uint8_t* d_refs2b, const uint64_t* d_ref_off, uint64_t n_pairs,
-                           uint64_t total_read_bases, uint64_t total_ref_bases,
-                           int32_t k, int32_t W, int32_t O,
-                           genasm_result* d_out, uint32_t* d_cigar, uint64_t cigar_cap,
-                           const genasm_launch* launch, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The device-form call. Scratch (bit planes, search lists, queues, table
+// spill, profiling counters) comes from the context's buffers, grown on
+// demand, or with `noalloc` from the static `scratch` array, in which case
+// nothing is allocated and profiling is not recorded.
+int align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
+              const uint8_t* d_refs2b, const uint64_t* d_ref_off, uint64_t n_pairs,
+              uint64_t total_read_bases, uint64_t total_ref_bases, int32_t k, int32_t W, int32_t O,
+              genasm_result* d_out, uint32_t* d_cigar, uint64_t cigar_cap,
+              const genasm_launch* launch, void* stream, bool noalloc) {
     if (!ctx) return GENASM_E_INVAL;
     if (!valid_wko(k, W, O)) return set_err(ctx, GENASM_E_INVAL, "W must be in [2,64], O in [0,W-1], k >= 0");
     if (n_pairs == 0) return GENASM_OK;
@@ -342,14 +385,20 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     }
     int rc = resolve_launch(launch, &L);
     if (rc) return set_err(ctx, rc, "bad launch parameters");
+    if (noalloc && L.form == GENASM_FORM_UNIMPROVED)
+        return set_err(ctx, GENASM_E_INVAL,
+                       "the no-allocation call runs the plain and batched forms only");
+    if (noalloc && !ctx->static_scratch)
+        return set_err(ctx, GENASM_E_DEVICE, "no static scratch address on this device");
     hipStream_t s = (hipStream_t)stream;  // NULL: the null stream
     CHECK_HIP(ctx, hipSetDevice(ctx->device));
-    {
+    if (!noalloc) {
         // a call recorded into a graph pins the context's buffers
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         CHECK_HIP(ctx, hipStreamIsCapturing(s, &cs));
         if (cs != hipStreamCaptureStatusNone) ctx->pinned = true;
     }
+    const bool profiling = ctx->profiling && !noalloc;
 
     AlignParams p{};
     p.reads = d_reads2b;
@@ -365,20 +414,36 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     p.cigar = d_cigar;
     p.cigar_cap = cigar_cap;
 
-    // bit planes of both streams (window kernels), in the context's plane buffer
-    {
-        const uint64_t rw = plane_words(total_read_bases), fw = plane_words(total_ref_bases);
-        rc = ensure(ctx, &ctx->planes, &ctx->planes_cap, (size_t)(2 * rw + 2 * fw) * 8);
+    // Bit planes of both streams (window kernels): the context's plane buffer,
+    // or the start of the static scratch.
+    const uint64_t rw = plane_words(total_read_bases), fw = plane_words(total_ref_bases);
+    const size_t plane_bytes = (size_t)(2 * rw + 2 * fw) * 8;
+    char* plane_base;
+    if (noalloc) {
+        plane_base = static_cast<char*>(ctx->static_scratch);
+    } else {
+        rc = ensure(ctx, &ctx->planes, &ctx->planes_cap, plane_bytes);
         if (rc) return rc;
-        unsigned long long* pw = reinterpret_cast<unsigned long long*>(ctx->planes);
+        plane_base = ctx->planes;
+    }
+    {
+        unsigned long long* pw = reinterpret_cast<unsigned long long*>(plane_base);
         p.read_lo = pw;
         p.read_hi = pw + rw;
         p.ref_lo = pw + 2 * rw;
         p.ref_hi = pw + 2 * rw + fw;
         p.planes_from_off0 = 1;
     }
+    auto too_big = [&](size_t need) {
+        return set_err(ctx, GENASM_E_SCRATCH,
+                       ("the batch needs " + std::to_string(need) +
+                        " bytes of device scratch; the no-allocation call has " +
+                        std::to_string((size_t)GENASM_NOALLOC_SCRATCH_BYTES))
+                           .c_str());
+    };
+    if (noalloc && plane_bytes > (size_t)GENASM_NOALLOC_SCRATCH_BYTES) return too_big(plane_bytes);
 
-    if (ctx->profiling) {
+    if (profiling) {
         const size_t words = (size_t)n_pairs * kStatCount;
         rc = ensure(ctx, &ctx->stats, &ctx->stats_cap, words * 8);
         if (rc) return rc;
@@ -389,19 +454,23 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
         ctx->have_profile = true;
     }
     auto mark = [&](int i) -> hipError_t {
-        return ctx->profiling ? hipEventRecord(ctx->ev[i], s) : hipSuccess;
+        return profiling ? hipEventRecord(ctx->ev[i], s) : hipSuccess;
+    };
+    auto planes = [&]() -> hipError_t {
+        hipError_t e = launch_planes(d_reads2b, d_read_off, total_read_bases,
+                                     const_cast<unsigned long long*>(p.read_lo),
+                                     const_cast<unsigned long long*>(p.read_hi), s);
+        if (e != hipSuccess) return e;
+        return launch_planes(d_refs2b, d_ref_off, total_ref_bases,
+                             const_cast<unsigned long long*>(p.ref_lo),
+                             const_cast<unsigned long long*>(p.ref_hi), s);
     };
     if (L.form == GENASM_FORM_UNIMPROVED) {
         p.lds_rows = 64;
         rc = ensure(ctx, &ctx->unimp, &ctx->unimp_cap, unimproved_table_words(n_pairs) * 8);
         if (rc) return rc;
         CHECK_HIP(ctx, mark(0));
-        CHECK_HIP(ctx, launch_planes(d_reads2b, d_read_off, total_read_bases,
-                                     const_cast<unsigned long long*>(p.read_lo),
-                                     const_cast<unsigned long long*>(p.read_hi), s));
-        CHECK_HIP(ctx, launch_planes(d_refs2b, d_ref_off, total_ref_bases,
-                                     const_cast<unsigned long long*>(p.ref_lo),
-                                     const_cast<unsigned long long*>(p.ref_hi), s));
+        CHECK_HIP(ctx, planes());
         CHECK_HIP(ctx, mark(1));
         CHECK_HIP(ctx, mark(2));
         CHECK_HIP(ctx, launch_unimproved(p, reinterpret_cast<unsigned long long*>(ctx->unimp), s));
@@ -411,12 +480,7 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     if (L.form == GENASM_FORM_PLAIN) {
         p.lds_rows = 64;
         CHECK_HIP(ctx, mark(0));
-        CHECK_HIP(ctx, launch_planes(d_reads2b, d_read_off, total_read_bases,
-                                     const_cast<unsigned long long*>(p.read_lo),
-                                     const_cast<unsigned long long*>(p.read_hi), s));
-        CHECK_HIP(ctx, launch_planes(d_refs2b, d_ref_off, total_ref_bases,
-                                     const_cast<unsigned long long*>(p.ref_lo),
-                                     const_cast<unsigned long long*>(p.ref_hi), s));
+        CHECK_HIP(ctx, planes());
         CHECK_HIP(ctx, mark(1));
         CHECK_HIP(ctx, mark(2));
         CHECK_HIP(ctx, launch_plain(p, s));
@@ -431,16 +495,7 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     p.tb_prefetch = L.tb_prefetch;
     p.hard_share = L.hard_share;
     p.route = 1;
-    int per_cu = L.workers_per_cu;
-    if (per_cu == 0) {
-        // as many as stay resident together (LDS and registers), so that no
-        // workgroup of the persistent grid waits for another to finish
-        per_cu = std::max(1, std::min(16, windows_blocks_per_cu(p)));
-    }
-    const int win_blocks = ctx->num_cus * per_cu;
-    ctx->prof_window_blocks = win_blocks;
     const int search_blocks = ctx->num_cus * 8;
-    const uint64_t workers = (uint64_t)win_blocks * 4;
     const int spill_rows = 64 - L.lds_rows;
     // Search chunks: at least kBatchSearchChunk columns, and large enough that
     // the batch makes about two items per search group, so that a long
@@ -452,7 +507,7 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
             std::max<uint64_t>(kBatchSearchChunk, (want + 1023) / 1024 * 1024), 1u << 30);
     }
     const uint64_t item_cap = search_item_cap(n_pairs, total_ref_bases, p.search_chunk);
-    auto carve = [&](Carver& c) {
+    auto carve = [&](Carver& c, uint64_t workers) {
         p.search = c.take<SearchOut>(n_pairs);
         p.counters = c.take<uint32_t>(kCounterCount);
         p.search_key = c.take<unsigned long long>(n_pairs);
@@ -464,20 +519,43 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
         uint32_t* order = c.take<uint32_t>(n_pairs);
         return std::make_tuple(items, hist, order);
     };
-    Carver dry{nullptr};
-    carve(dry);
-    rc = ensure(ctx, &ctx->scratch, &ctx->scratch_cap, dry.off + 256);
-    if (rc) return rc;
-    Carver real{ctx->scratch};
-    auto [items, hist, order] = carve(real);
+    // scratch bytes with `per_cu` window workgroups per CU (the static
+    // scratch holds the planes first)
+    const size_t base_off = noalloc ? align_up(plane_bytes, 256) : 0;
+    auto scratch_need = [&](int per_cu) {
+        Carver dry{nullptr};
+        dry.off = base_off;
+        carve(dry, (uint64_t)ctx->num_cus * per_cu * 4);
+        return dry.off + 256;
+    };
+    int per_cu = L.workers_per_cu;
+    if (per_cu == 0) {
+        // as many as stay resident together (LDS and registers), so that no
+        // workgroup of the persistent grid waits for another to finish; without
+        // allocation, as many of those as the static scratch holds
+        per_cu = std::max(1, std::min(16, windows_blocks_per_cu(p)));
+        while (noalloc && per_cu > 1 && scratch_need(per_cu) > (size_t)GENASM_NOALLOC_SCRATCH_BYTES)
+            --per_cu;
+    }
+    const int win_blocks = ctx->num_cus * per_cu;
+    const uint64_t workers = (uint64_t)win_blocks * 4;
+    const size_t need = scratch_need(per_cu);
+    char* base;
+    if (noalloc) {
+        if (need > (size_t)GENASM_NOALLOC_SCRATCH_BYTES) return too_big(need);
+        base = static_cast<char*>(ctx->static_scratch);
+    } else {
+        rc = ensure(ctx, &ctx->scratch, &ctx->scratch_cap, need);
+        if (rc) return rc;
+        base = ctx->scratch;
+    }
+    if (profiling) ctx->prof_window_blocks = win_blocks;
+    Carver real{base};
+    real.off = base_off;
+    auto [items, hist, order] = carve(real, workers);
 
     CHECK_HIP(ctx, mark(0));
-    CHECK_HIP(ctx, launch_planes(d_reads2b, d_read_off, total_read_bases,
-                                 const_cast<unsigned long long*>(p.read_lo),
-                                 const_cast<unsigned long long*>(p.read_hi), s));
-    CHECK_HIP(ctx, launch_planes(d_refs2b, d_ref_off, total_ref_bases,
-                                 const_cast<unsigned long long*>(p.ref_lo),
-                                 const_cast<unsigned long long*>(p.ref_hi), s));
+    CHECK_HIP(ctx, planes());
     if (L.lpt_order) {
         CHECK_HIP(ctx, launch_lpt_order(d_read_off, n_pairs, hist, order, s));
         p.order = order;
@@ -516,6 +594,31 @@ int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint
     CHECK_HIP(ctx, launch_windows(p, win_blocks, s));
     CHECK_HIP(ctx, mark(3));
     return GENASM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int genasm_batch_align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
+                           const uint8_t* d_refs2b, const uint64_t* d_ref_off, uint64_t n_pairs,
+                           uint64_t total_read_bases, uint64_t total_ref_bases,
+                           int32_t k, int32_t W, int32_t O,
+                           genasm_result* d_out, uint32_t* d_cigar, uint64_t cigar_cap,
+                           const genasm_launch* launch, void* stream) {
+    return align_dev(ctx, d_reads2b, d_read_off, d_refs2b, d_ref_off, n_pairs, total_read_bases,
+                     total_ref_bases, k, W, O, d_out, d_cigar, cigar_cap, launch, stream, false);
+}
+
+int genasm_batch_align_dev_noalloc(genasm_ctx* ctx, const uint8_t* d_reads2b,
+                                   const uint64_t* d_read_off, const uint8_t* d_refs2b,
+                                   const uint64_t* d_ref_off, uint64_t n_pairs,
+                                   uint64_t total_read_bases, uint64_t total_ref_bases,
+                                   int32_t k, int32_t W, int32_t O,
+                                   genasm_result* d_out, uint32_t* d_cigar, uint64_t cigar_cap,
+                                   const genasm_launch* launch, void* stream) {
+    return align_dev(ctx, d_reads2b, d_read_off, d_refs2b, d_ref_off, n_pairs, total_read_bases,
+                     total_ref_bases, k, W, O, d_out, d_cigar, cigar_cap, launch, stream, true);
 }
 
 int genasm_autotune_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_off,
