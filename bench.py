@@ -64,94 +64,182 @@ def rle(ops: str) -> str:
     return "".join(out)
 
 
+def provenance(gen, dev):
+    """Source revision, device architecture and workload seeds of the run."""
+    import torch
+    try:
+        with open(os.path.join(ROOT, "paper_2203_15561_amd", "BUILD_INFO.json")) as f:
+            info = json.load(f)
+    except (OSError, ValueError):
+        info = {}
+    props = torch.cuda.get_device_properties(dev)
+    return {"git": info.get("git"), "git_dirty": info.get("git_dirty"), "device": props.name,
+            "arch": getattr(props, "gcnArchName", None), "compute_units": props.multi_processor_count,
+            "seeds": {name: w[0] for name, w in gen.WORKLOADS.items()}}
+
+
 def serving_leg(ga, gen, ctx, args):
-    """Serving form on the request mix: a saturated run (every request queued
-    at once) gives the sustainable rate; open-loop runs with Poisson arrivals
-    at a sweep of rates below it give latency percentiles, measured from each
-    request's scheduled arrival to its completion."""
-    def requests(n, start):
-        ps = gen.make("serving", n, start=start)
-        asc = [(ga.capi._ascii(ps.read(i)), ga.capi._ascii(ps.ref(i))) for i in range(n)]
-        return ps, asc
+    """Serving form on the request mix (70% 150 bp at 1%, 30% 1-30 kb at 10%).
 
-    def drain(srv, n, got, deadline_s=300.0):
-        t_end = time.time() + deadline_s
-        t_log = time.time() + 10
-        while len(got) < n:
-            if time.time() > t_end:
-                raise RuntimeError(f"serving: {n - len(got)} requests did not complete")
-            for c in srv.poll(timeout_ms=20):
-                got[c["tag"]] = c
-            if time.time() > t_log:
-                log(f"serving: {len(got)} of {n} requests completed")
-                t_log = time.time() + 10
+    The same requests are first aligned as one batch through the device form
+    in the plain and the batched launch: that gives the cells of the mix (the
+    library's work counters) and the two launches' GCUPS. A saturated run then
+    queues every request at once through the server (pre-packed bases,
+    genasm_submit_batch; completions through genasm_poll_batch) and checks
+    every completion against the batched form's result, CIGAR included.
+    Open-loop runs with Poisson arrivals at a sweep of rates up to the
+    saturated rate give latency percentiles, from each request's scheduled
+    arrival to the time its CIGAR reached host memory."""
+    import torch
+    t0 = time.time()
+    pool = gen.make("serving", args.serving_requests)
+    n = pool.n_pairs
+    r2, f2 = ga.pack(pool.reads), ga.pack(pool.refs)
+    roff, foff = pool.read_off.astype(np.uint64), pool.ref_off.astype(np.uint64)
+    short = np.diff(pool.read_off) <= 1000
+    log(f"serving: {n} requests generated in {time.time() - t0:.1f} s")
+    out = {"mix": gen.DESCRIPTIONS["serving"], "requests": n, "k": pool.k, "W": pool.W, "O": pool.O}
 
-    def open_loop(srv, rate, start):
-        n_open = max(200, int(rate * args.serving_seconds))
-        ps2, asc2 = requests(n_open, start)
-        rng = np.random.default_rng(2203 + start)
-        gaps = rng.exponential(1.0 / rate, n_open)
-        got = {}
-        t_start = ga.now_ns() + 1_000_000
-        sched = t_start + np.cumsum(gaps * 1e9).astype(np.int64)
-        i = 0
-        while i < n_open:
-            now = ga.now_ns()
-            while i < n_open and sched[i] <= now:
-                while srv.submit(asc2[i][0], asc2[i][1], i) == ga.capi.E_BUSY:
-                    time.sleep(0.0005)
-                i += 1
-            for c in srv.poll(timeout_ms=0):
-                got[c["tag"]] = c
-            if i < n_open:
-                wait = (sched[i] - ga.now_ns()) / 1e9
-                if wait > 0.0002:
-                    time.sleep(min(wait, 0.002))
-        drain(srv, n_open, got)
-        assert all(c["flags"] == 0 for c in got.values())
-        lat = np.array([(got[t]["done_ns"] - sched[t]) / 1e6 for t in range(n_open)])
-        short = np.array([len(ps2.read(t)) <= 1000 for t in range(n_open)])
-        t_last = max(c["done_ns"] for c in got.values())
-        pct = lambda a, q: float(np.percentile(a, q)) if len(a) else None
-        return {"arrival_rate_per_s": rate, "requests": n_open,
-                "completed_per_s": n_open / ((t_last - t_start) / 1e9),
-                "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": float(lat.mean()),
-                "short_p50_ms": pct(lat[short], 50), "short_p99_ms": pct(lat[short], 99),
-                "long_p50_ms": pct(lat[~short], 50), "long_p99_ms": pct(lat[~short], 99)}
+    # the mix as one batch: cells, plain and batched launches
+    dev = torch.device("cuda:0")
+    d_r2, d_f2 = torch.from_numpy(r2).to(dev), torch.from_numpy(f2).to(dev)
+    d_ro = torch.from_numpy(roff.astype(np.int64)).to(dev)
+    d_fo = torch.from_numpy(foff.astype(np.int64)).to(dev)
+    best, _, b_out, b_cig = ctx.autotune_dev(d_r2, d_ro, d_f2, d_fo, pool.k, pool.W, pool.O)
+    ctx.profile(True)
+    ctx.align_dev(d_r2, d_ro, d_f2, d_fo, pool.k, pool.W, pool.O, launch=best, out=b_out, cigar=b_cig)
+    pr = ctx.profile_read()
+    ctx.profile(False)
+    cells = pr["window_cells"] + pr["search_cells"]
+    ref_res = b_out.cpu().numpy().view(ga.RESULT_DTYPE).reshape(-1)[:n].copy()
+    ref_el = b_cig.cpu().numpy().view(np.uint32)
+    for form, L in (("batched_launch", best), ("plain_launch", ga.make_launch(ga.FORM_PLAIN))):
+        ctx.align_dev(d_r2, d_ro, d_f2, d_fo, pool.k, pool.W, pool.O, launch=L, out=b_out, cigar=b_cig)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(2):
+            ctx.align_dev(d_r2, d_ro, d_f2, d_fo, pool.k, pool.W, pool.O, launch=L, out=b_out,
+                          cigar=b_cig)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 2
+        out[form] = {"ms": ms, "requests_per_s": n / (ms / 1e3), "gcups": cells / (ms / 1e3) / 1e9}
+        log(f"serving mix as one batch, {form}: {ms:.2f} ms ({out[form]['gcups']:.0f} GCUPS)")
+    out["cells"] = int(cells)
+    del d_r2, d_f2, d_ro, d_fo, b_out, b_cig
 
-    ps, asc = requests(args.serving_requests, 0)
-    out = {"mix": gen.DESCRIPTIONS["serving"], "k": ps.k, "W": ps.W, "O": ps.O}
-    with ga.Server(ctx, ps.k, ps.W, ps.O) as srv:
-        # warm-up: a few requests through the graph
-        for i in range(64):
-            assert srv.submit(asc[i][0], asc[i][1], i) == 0
-        drain(srv, 64, {})
+    def submit_range(srv, lo, hi, tags):
+        rc, acc = srv.submit_batch(r2, roff[lo:hi + 1], f2, foff[lo:hi + 1], tags[lo:hi])
+        assert rc in (0, ga.capi.E_BUSY), rc
+        return acc
+
+    def collect(srv, infos, runs, timeout_ms):
+        info, el = srv.poll_arrays(timeout_ms=timeout_ms)
+        if len(info):
+            infos.append(info)
+            runs.append(el)
+        return len(info)
+
+    with ga.Server(ctx, pool.k, pool.W, pool.O, cigar_runs=1, max_pending=n + 1) as srv:
+        tags = np.arange(n, dtype=np.uint64)
+        # warm-up: the first 2,000 requests
+        w = min(2000, n)
+        submit_range(srv, 0, w, tags)
+        got = 0
+        while got < w:
+            got += len(srv.poll_arrays(timeout_ms=20)[0])
+        # saturated: every request queued at once
         st0 = srv.stats()
-        got = {}
-        t0 = ga.now_ns()
-        for i, (r, f) in enumerate(asc):
-            while srv.submit(r, f, i) == ga.capi.E_BUSY:
-                for c in srv.poll(timeout_ms=1):
-                    got[c["tag"]] = c
-        drain(srv, len(asc), got)
-        t1 = max(c["done_ns"] for c in got.values())
+        infos, runs = [], []
+        t_start = ga.now_ns()
+        i = 0
+        while i < n:
+            i += submit_range(srv, i, min(n, i + 8192), tags)
+            collect(srv, infos, runs, 0)
+        done = sum(len(x) for x in infos)
+        t_log = time.time() + 10
+        while done < n:
+            done += collect(srv, infos, runs, 20)
+            if time.time() > t_log:
+                log(f"serving: {done} of {n} requests completed")
+                t_log = time.time() + 10
         st1 = srv.stats()
-        assert all(c["flags"] == 0 for c in got.values())
-        sat = len(asc) / ((t1 - t0) / 1e9)
+        info = np.concatenate(infos)
+        t_end = int(info["done_ns"].max())
+        secs = (t_end - t_start) / 1e9
         iters = st1["iterations"] - st0["iterations"]
-        out["saturated"] = {"requests": len(asc), "requests_per_s": sat, "seconds": (t1 - t0) / 1e9,
-                            "iterations": iters,
-                            "device_ms_per_iteration": (st1["device_ms"] - st0["device_ms"]) / max(iters, 1)}
-        log(f"serving saturated: {sat:.0f} req/s over {len(asc)} requests, {iters} iterations")
+        # every completion equals the batched form's result, CIGAR included
+        order = np.argsort(info["tag"])
+        info = info[order]
+        assert (info["tag"] == tags).all()
+        res = info["result"]
+        assert (res["flags"] == 0).all()
+        for f in ("edit_distance", "ref_begin", "ref_end", "n_windows", "cigar_len"):
+            assert (res[f] == ref_res[f]).all(), f
+        el = np.concatenate(runs)
+        # completion elements were appended in arrival order; rebuild per-tag offsets
+        starts = np.concatenate(([0], np.cumsum([len(x) for x in runs])))[:-1]
+        base = np.concatenate([np.full(len(x), s0, np.int64) for x, s0 in zip(infos, starts)])[order]
+        off = base + res["cigar_off"].astype(np.int64)
+        ln = res["cigar_len"].astype(np.int64)
+        idx = np.repeat(off - np.concatenate(([0], np.cumsum(ln)))[:-1], ln) + np.arange(ln.sum())
+        ref_idx = np.repeat(ref_res["cigar_off"].astype(np.int64) - np.concatenate(([0], np.cumsum(ln)))[:-1],
+                            ln) + np.arange(ln.sum())
+        assert np.array_equal(el[idx], ref_el[ref_idx]), "serving CIGARs differ from the batched form"
+        sat = n / secs
+        out["saturated"] = {
+            "requests": n, "seconds": secs, "requests_per_s": sat, "gcups": cells / secs / 1e9,
+            "iterations": iters, "device_ms": st1["device_ms"] - st0["device_ms"],
+            "device_busy": (st1["device_ms"] - st0["device_ms"]) / 1e3 / secs,
+            "over_plain_launch": (cells / secs / 1e9) / out["plain_launch"]["gcups"],
+            "over_batched_launch": (cells / secs / 1e9) / out["batched_launch"]["gcups"],
+            "checked": "every completion equals the batched device form (result fields and CIGAR)"}
+        log(f"serving saturated: {sat:.0f} req/s ({out['saturated']['gcups']:.0f} GCUPS) over {n} "
+            f"requests, {iters} iterations; plain launch {out['plain_launch']['gcups']:.0f} GCUPS")
 
+        # open loop: Poisson arrivals at each rate, submitted at their scheduled times
         rates = [float(x) for x in args.serving_rates.split(",") if x.strip()]
-        rates = sorted({r for r in rates if r < sat} | {args.serving_load * sat})
+        rates = sorted({r for r in rates if r < 0.95 * sat} | {0.5 * sat, 0.8 * sat})
         out["open_loop"] = []
         for k_rate, rate in enumerate(rates):
-            out["open_loop"].append(open_loop(srv, rate, args.serving_requests + 100_000 * k_rate))
-            o = out["open_loop"][-1]
-            log(f"serving open loop at {rate:.0f} req/s: p50 {o['p50_ms']:.2f} ms, "
-                f"p99 {o['p99_ms']:.2f} ms (short p50 {o['short_p50_ms']:.2f} / p99 "
+            n_open = int(min(n, max(2000, rate * args.serving_seconds)))
+            rng = np.random.default_rng(2203 + k_rate)
+            sched_rel = np.cumsum(rng.exponential(1.0 / rate, n_open) * 1e9).astype(np.int64)
+            infos, runs = [], []
+            t_begin = ga.now_ns() + 1_000_000
+            sched = t_begin + sched_rel
+            i = 0
+            while i < n_open:
+                now = ga.now_ns()
+                j = int(np.searchsorted(sched, now, side="right"))
+                if j > i:
+                    i += submit_range(srv, i, j, tags)
+                collect(srv, infos, runs, 0)
+                if i < n_open:
+                    wait = (sched[i] - ga.now_ns()) / 1e9
+                    if wait > 0.0002:
+                        time.sleep(min(wait, 0.001))
+            done = sum(len(x) for x in infos)
+            t_end_wait = time.time() + 300
+            while done < n_open:
+                assert time.time() < t_end_wait, "open-loop requests did not complete"
+                done += collect(srv, infos, runs, 20)
+            info = np.concatenate(infos)
+            info = info[np.argsort(info["tag"])]
+            assert (info["result"]["flags"] == 0).all()
+            assert (info["result"]["edit_distance"] == ref_res["edit_distance"][:n_open]).all()
+            lat = (info["done_ns"].astype(np.int64) - sched) / 1e6
+            sh = short[:n_open]
+            pct = lambda a, q: float(np.percentile(a, q)) if len(a) else None
+            o = {"arrival_rate_per_s": rate, "requests": n_open,
+                 "completed_per_s": n_open / ((int(info["done_ns"].max()) - t_begin) / 1e9),
+                 "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": float(lat.mean()),
+                 "short_p50_ms": pct(lat[sh], 50), "short_p99_ms": pct(lat[sh], 99),
+                 "long_p50_ms": pct(lat[~sh], 50), "long_p99_ms": pct(lat[~sh], 99)}
+            out["open_loop"].append(o)
+            log(f"serving open loop at {rate:.0f} req/s: p50 {o['p50_ms']:.2f} ms, p99 "
+                f"{o['p99_ms']:.2f} ms (150 bp: p50 {o['short_p50_ms']:.2f} / p99 "
                 f"{o['short_p99_ms']:.2f} ms)")
     return out
 
@@ -173,24 +261,29 @@ def main():
     ap.add_argument("--workers-per-cu", type=int, default=0)
     ap.add_argument("--hard-row", type=int, default=0)
     ap.add_argument("--hard-lanes", type=int, default=0)
+    ap.add_argument("--hard-share", type=int, default=-1)
+    ap.add_argument("--table-bits", type=int, default=0)
+    ap.add_argument("--search-per-cu", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default launch instead of the autotuner's pick")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the timed region, run one plain device copy of this many MiB "
                          "(reference kernel for scaling HBM byte counters)")
-    ap.add_argument("--serving-requests", type=int, default=20000,
-                    help="requests of the serving mix for the saturated run")
-    ap.add_argument("--serving-load", type=float, default=0.5,
-                    help="open-loop arrival rate as a fraction of the saturated rate")
-    ap.add_argument("--serving-seconds", type=float, default=3.0,
+    ap.add_argument("--serving-requests", type=int, default=40000,
+                    help="requests of the serving mix (saturated run; the open-loop runs use "
+                         "its first requests)")
+    ap.add_argument("--serving-seconds", type=float, default=2.0,
                     help="length of each open-loop arrival schedule")
-    ap.add_argument("--serving-rates", default="1000,3000,10000",
-                    help="open-loop arrival rates (req/s) below the saturated rate, comma-separated")
+    ap.add_argument("--serving-rates", default="1000,3000,10000,30000,100000,300000,1000000",
+                    help="open-loop arrival rates (req/s), comma-separated; those above the "
+                         "saturated rate are skipped, and 50%% and 80%% of it are added")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving leg (for profiling it)")
     ap.add_argument("--no-graph", action="store_true", help="skip timing the graph-captured step")
     ap.add_argument("--no-filter", action="store_true", help="skip the pre-alignment filter leg")
     ap.add_argument("--no-other-configs", action="store_true",
-                    help="skip the batched-vs-plain legs on the 250 bp and uneven workloads")
+                    help="skip the batched-vs-plain legs on the 100 bp, 250 bp and uneven workloads")
     ap.add_argument("--filter-pairs", type=int, default=20000,
                     help="pairs of the 250 bp workload for the filter leg")
     ap.add_argument("--no-unimproved", action="store_true",
@@ -207,6 +300,12 @@ def main():
 
     import paper_2203_15561_amd as ga
     from workloads import gen
+
+    if args.serving_only:
+        ctx = ga.Context(0)
+        print(json.dumps({"serving": serving_leg(ga, gen, ctx, args)}), flush=True)
+        ctx.close()
+        return
 
     t0 = time.time()
     ps = gen.make(args.workload, args.pairs)
@@ -235,6 +334,12 @@ def main():
         kw["hard_row"] = args.hard_row
     if args.hard_lanes:
         kw["hard_lanes"] = args.hard_lanes
+    if args.hard_share >= 0:
+        kw["hard_share"] = args.hard_share
+    if args.table_bits:
+        kw["table_bits"] = args.table_bits
+    if args.search_per_cu:
+        kw["search_per_cu"] = args.search_per_cu
     batched = ga.make_launch(ga.FORM_BATCHED, **kw)
     plain = ga.make_launch(ga.FORM_PLAIN)
 
@@ -258,14 +363,18 @@ def main():
                                               out=out, cigar=cigar, reps=2, total_read_bases=nr,
                                               total_ref_bases=nf)
         tuned = {"tuner_seconds": time.time() - t0, "best_ms": tms}
-        log(f"autotune: hard_row {batched.hard_row}, hard_lanes {batched.hard_lanes}, hard_share "
-            f"{batched.hard_share}, lds_rows "
+        log(f"autotune: table_bits {batched.table_bits}, hard_row {batched.hard_row}, hard_lanes "
+            f"{batched.hard_lanes}, hard_share {batched.hard_share}, lds_rows "
             f"{batched.lds_rows}, workers_per_cu {batched.workers_per_cu}, search_lanes "
             f"{batched.search_lanes} ({tms:.2f} ms) in {tuned['tuner_seconds']:.1f} s")
 
-    # timed region: K steps, library profiling on (HIP events around each stage on
-    # the same stream), one profile read per step for the window-kernel time
-    ctx.profile(True)
+    # work counters of one step (a profiled run), then the timed region: K steps
+    # with stage times only (HIP events around each stage on the kernels' stream;
+    # the kernels run as unprofiled), one profile read per step
+    ctx.profile(1)
+    step(batched)
+    prc = ctx.profile_read()
+    ctx.profile(2)
     win_ms, search_ms, total_ms = [], [], []
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -314,6 +423,7 @@ def main():
             verified += 1
         log(f"verified {verified} pairs against the oracle")
 
+    pr = {**prc, **{k: v for k, v in pr.items() if k.endswith("_ms")}}
     cells = pr["window_cells"] + pr["search_cells"]
     int_ops_windows = 2 * pr["window_word_ops"]  # two 32-bit halves per 64-bit word op
     achieved = int_ops_windows / (np.mean(win_ms) / 1e3) / 1e12
@@ -336,6 +446,7 @@ def main():
                    "workers_per_cu": batched.workers_per_cu, "hard_row": batched.hard_row,
                    "hard_share": batched.hard_share,
                    "hard_lanes": batched.hard_lanes, "search_lanes": batched.search_lanes,
+                   "table_bits": batched.table_bits, "search_per_cu": batched.search_per_cu,
                    "autotuned": tuned is not None},
         "autotune": tuned,
         "gcups": cells / (ms_step / 1e3) / 1e9,
@@ -347,6 +458,7 @@ def main():
                      "ops_per_launch": int_ops_windows},
         "work": {k: int(v) for k, v in pr.items() if not k.endswith("_ms")},
         "verified_pairs": verified,
+        "provenance": provenance(gen, dev),
     }
 
     traffic = measured_traffic(args.workload) if ps.n_pairs == 20000 else None
@@ -482,7 +594,7 @@ def main():
     if not args.no_other_configs:
         # the other batch workloads: batched (autotuned) against the plain launch
         line["other_configs"] = {}
-        for wname in ("short250", "uneven"):
+        for wname in ("short100", "short250", "uneven"):
             ops = gen.make(wname)
             o_r2 = torch.from_numpy(ga.pack(ops.reads)).to(dev)
             o_f2 = torch.from_numpy(ga.pack(ops.refs)).to(dev)
@@ -512,6 +624,39 @@ def main():
                 res_o[form] = {"ms": oms, "alignments_per_s": ops.n_pairs / (oms / 1e3),
                                "gcups": o_cells / (oms / 1e3) / 1e9}
                 res_o[form + "_scores"] = o_out.cpu().numpy().view(ga.RESULT_DTYPE)["edit_distance"].copy()
+            # the batched form captured once in a HIP graph (a context of its own
+            # keeps the captured scratch) and replayed
+            gctx = ga.Context(0)
+            gs = torch.cuda.Stream()
+            gs.wait_stream(torch.cuda.current_stream())
+            nr_o = int(ops.read_off[-1] - ops.read_off[0])
+            nf_o = int(ops.ref_off[-1] - ops.ref_off[0])
+
+            def ocall():
+                gctx.align_dev(o_r2, o_ro, o_f2, o_fo, ops.k, ops.W, ops.O, launch=o_best, out=o_out,
+                               cigar=o_cig, total_read_bases=nr_o, total_ref_bases=nf_o)
+
+            with torch.cuda.stream(gs):
+                ocall()
+            torch.cuda.synchronize()
+            og = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(og, stream=gs):
+                ocall()
+            og.replay()
+            torch.cuda.synchronize()
+            o0, o1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            o0.record()
+            for _ in range(args.steps):
+                og.replay()
+            o1.record()
+            torch.cuda.synchronize()
+            gms = o0.elapsed_time(o1) / args.steps
+            res_g = o_out.cpu().numpy().view(ga.RESULT_DTYPE)["edit_distance"].copy()
+            assert (res_g == res_o["plain_scores"]).all()
+            res_o["batched_graph"] = {"ms": gms, "alignments_per_s": ops.n_pairs / (gms / 1e3),
+                                      "gcups": o_cells / (gms / 1e3) / 1e9}
+            del og
+            gctx.close()
             assert (res_o["batched_scores"] == res_o["plain_scores"]).all()
             del res_o["batched_scores"], res_o["plain_scores"]
             res_o["pairs"] = ops.n_pairs

@@ -27,6 +27,11 @@
  * CIGAR ops are '=', 'X', 'I' (read base absent from the reference) and 'D'
  * (reference base absent from the read); runs merge across window seams.
  *
+ * Testing the error paths: with the environment variable GENASM_FAIL_ALLOC
+ * set to 1, every device allocation the library would make (a context buffer
+ * that has to grow, a server's pools) fails as if the device were full, so
+ * the calls return GENASM_E_NOMEM and leave the context usable.
+ *
  * Threading: a genasm_ctx is not thread-safe; use one per host thread.
  * No C++ exception crosses this interface. Every call returns GENASM_OK (0)
  * or a negative error code.
@@ -116,6 +121,13 @@ typedef struct {
     int32_t hard_share;      /* batched: percent (0..100) of the window workers that drain
                                 the hard queue before the easy one (the others the other way
                                 round); -1 = default (50) */
+    int32_t table_bits;      /* batched, 16-lane groups for both queues: 32 = compact groups
+                                (a window's table in LDS as 32-bit slices of its 16 rows,
+                                valid while the window solves within 16 rows; a deeper
+                                window is recomputed with 64-bit rows in device memory),
+                                64 = 64-bit rows, lds_rows of them in LDS; 0 = default (64) */
+    int32_t search_per_cu;   /* batched: start-search workgroups per compute unit (1..32);
+                                0 = default (8) */
 } genasm_launch;
 
 typedef struct genasm_ctx genasm_ctx;
@@ -359,6 +371,9 @@ typedef struct {
     uint64_t window_workgroups;/* resident workgroups of the batched window kernel (4 groups each) */
 } genasm_profile;
 
+/* on: 0 = off; 1 = stage times and the per-pair work counters; 2 = stage
+ * times only (the kernels then run exactly as unprofiled, since the counters
+ * take registers of their own; genasm_profile_read reports zero counters). */
 int genasm_profile_enable(genasm_ctx* ctx, int on);
 int genasm_profile_read(genasm_ctx* ctx, genasm_profile* out);
 /*
@@ -380,39 +395,51 @@ int genasm_profile_pairs(genasm_ctx* ctx, uint64_t* out, uint64_t max_words, uin
  *
  * A server owns an engine thread and device-resident state: a pool of packed
  * read and reference bases, a pool of CIGAR elements, and per-slot window
- * state. Each device iteration:
+ * state. Each device iteration (one captured HIP graph):
  *   1. admits waiting requests into free slots while the slot count and both
- *      pools have room (admission by device-memory budget);
- *   2. runs the start search for the newly admitted pairs and, concurrently,
- *      advances every resident pair whose search has finished by at most
- *      `window_budget` windows (the window work of all resident pairs
- *      overlaps on the device; one captured HIP graph per iteration);
- *   3. returns finished pairs to the completion queue and frees their slots.
+ *      pools have room (admission by device-memory budget), and runs their
+ *      start search;
+ *   2. advances every resident pair, the newly admitted ones included, by at
+ *      least one window and then until it ends or the iteration's window time
+ *      has passed (new pairs and pairs whose last turn was cut short go
+ *      first); the window work of all resident pairs overlaps on the device,
+ *      and the device itself keeps the lists of unfinished and finished pairs;
+ *   3. returns the finished pairs (results, then CIGAR elements) to the host,
+ *      which frees their slots and queues their completions.
  * Requests that arrive while others are on the device join at the next
- * iteration. A request's result does not depend on the other requests in
- * flight: each pair's windows run exactly as in genasm_batch_align.
- * All requests of one server use its k, W and O.
+ * iteration; while one iteration runs the engine collects the previous one's
+ * output and, with requests waiting, queues the next. A request's result does
+ * not depend on the other requests in flight: each pair's windows run exactly
+ * as in genasm_batch_align. All requests of one server use its k, W and O.
  */
 typedef struct genasm_server genasm_server;
 
 typedef struct {
     int32_t k, W, O;          /* alignment parameters of every request */
-    uint32_t max_slots;       /* pairs resident on the device at once; 0 = 8192 */
+    uint32_t max_slots;       /* pairs resident on the device at once; 0 = 32768 */
     uint64_t pool_bases;      /* device pool for resident reads and references, in bases;
-                                 0 = 2^28 */
+                                 0 = 2^29 */
     uint32_t max_pending;     /* requests waiting on the host before genasm_submit returns
                                  GENASM_E_BUSY; 0 = 65536 */
-    uint32_t window_budget;   /* windows a resident pair advances per iteration; 0 = 32 */
-    int32_t use_graph;        /* 1 = replay one captured hipGraph per iteration, 0 = launch the
-                                 kernels directly; -1 or 0-initialised config: 1 */
-    int32_t reserved[3];
+    uint32_t window_budget;   /* windows a resident pair advances per iteration at most;
+                                 0 = no limit (the window time alone ends its turn) */
+    int32_t use_graph;        /* 1 = replay captured hipGraphs, 0 = launch the kernels
+                                 directly; -1 or 0-initialised config: 1 */
+    int32_t iteration_us;     /* window time of an iteration in microseconds; 0 = 2000 while
+                                 requests wait or pairs occupy at least half of the window
+                                 groups, else 250 */
+    int32_t cigar_runs;       /* 0 = completions carry CIGAR text; 1 = run-length elements
+                                 (GENASM_CIGAR_LEN/OP), as the device form writes them */
+    int32_t reserved;
 } genasm_server_config;
 
 typedef struct {
     uint64_t tag;             /* the submitter's tag */
-    genasm_result result;     /* cigar_off = 0; cigar_len = characters of `cigar` */
-    char* cigar;              /* NUL-terminated CIGAR text, owned by the completion */
-    uint64_t submit_ns;       /* genasm_now_ns() at genasm_submit */
+    genasm_result result;     /* cigar_off = 0; cigar_len = characters of the text, or
+                                 elements with cigar_runs */
+    char* cigar;              /* NUL-terminated CIGAR text, or (cigar_runs) an array of
+                                 result.cigar_len uint32 elements; owned by the completion */
+    uint64_t submit_ns;       /* genasm_now_ns() at submission */
     uint64_t admit_ns;        /* when the request entered a device slot */
     uint64_t done_ns;         /* when its result and CIGAR reached host memory */
 } genasm_completion;
@@ -423,7 +450,8 @@ typedef struct {
     uint32_t resident;        /* requests in device slots now */
     uint32_t pending;         /* requests waiting on the host now */
     uint64_t pool_bases_used;
-    double device_ms;         /* summed wall time of the iterations' device work */
+    double device_ms;         /* summed device time of the iterations (uploads included) */
+    uint64_t cancelled;       /* requests cancelled (genasm_cancel) */
 } genasm_server_stats;
 
 /* Creates a server on `ctx` (which it then uses exclusively until destroyed).
@@ -431,29 +459,96 @@ typedef struct {
  * allocation or device failure. */
 int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg, genasm_server** out);
 
-/* Queues one request (ASCII read of m bases, reference of n bases, copied
- * before return). k, W and O must equal the server's (else GENASM_E_INVAL).
- * Returns GENASM_E_BUSY when max_pending requests already wait,
- * GENASM_E_ALPHABET for a non-ACGT byte, GENASM_E_TOOLONG when the pair can
- * never fit the pools. Thread-safe. */
+/* Queues one request (ASCII read of m bases, reference of n bases, packed and
+ * copied before return). k, W and O must equal the server's (else
+ * GENASM_E_INVAL). Returns GENASM_E_BUSY when max_pending requests already
+ * wait, GENASM_E_ALPHABET for a non-ACGT byte, GENASM_E_TOOLONG when the pair
+ * can never fit the pools. Thread-safe. */
 int genasm_submit(genasm_server* srv, const char* read, uint64_t m, const char* ref, uint64_t n,
                   int32_t k, int32_t W, int32_t O, uint64_t tag);
 
+/* Queues n requests at once from 2-bit packed host streams (layout as for
+ * genasm_batch_align_dev: base b is bits 2*(b%4).. of byte b/4; request i is
+ * reads2b bases [read_off[i], read_off[i+1]) against refs2b bases
+ * [ref_off[i], ref_off[i+1]), offsets in bases, n + 1 of each), with tags[i].
+ * The bases are copied before return. Requests are queued in order while
+ * fewer than max_pending wait: *accepted receives how many were queued
+ * (requests 0 .. *accepted-1), and the call returns GENASM_E_BUSY when that is
+ * fewer than n. GENASM_E_INVAL (nothing queued) for null pointers, decreasing
+ * offsets or k/W/O other than the server's, GENASM_E_TOOLONG (nothing queued)
+ * when some pair can never fit the pools. Thread-safe. */
+int genasm_submit_batch(genasm_server* srv, const uint8_t* reads2b, const uint64_t* read_off,
+                        const uint8_t* refs2b, const uint64_t* ref_off, uint64_t n,
+                        int32_t k, int32_t W, int32_t O, const uint64_t* tags,
+                        uint64_t* accepted);
+
 /* Moves up to `max` completions into out[], waiting up to timeout_ms for the
- * first one (0 = do not wait). Returns the number moved, or a negative error
- * (GENASM_E_DEVICE: the engine stopped on a device error). Thread-safe. */
+ * first one (0 = do not wait); text CIGARs are formatted here, in the calling
+ * thread. Returns the number moved, or a negative error (GENASM_E_DEVICE: the
+ * engine stopped on a device error). Thread-safe. */
 int genasm_poll(genasm_server* srv, genasm_completion* out, int max, int timeout_ms);
 
-/* Frees the CIGAR text of a completion. */
+/* A completion without its CIGAR, for genasm_poll_batch (64 bytes). */
+typedef struct {
+    uint64_t tag;
+    genasm_result result;     /* cigar_off/cigar_len: run-length elements in the caller's buffer */
+    uint64_t submit_ns, admit_ns, done_ns;
+} genasm_completion_info;
+
+/* Bulk form of genasm_poll for high-rate consumers: moves up to `max`
+ * completions into out[] and their CIGARs, as run-length elements
+ * (GENASM_CIGAR_LEN/OP) in either CIGAR mode, back to back into
+ * runs[0 .. runs_cap); result.cigar_off indexes runs. Stops before the first
+ * completion whose elements do not fit; *runs_used receives the elements
+ * written. Returns the number moved, GENASM_E_NOSPACE when not even the first
+ * completion fits (*runs_used then holds the elements it needs), or a
+ * negative error as genasm_poll. Thread-safe. */
+int genasm_poll_batch(genasm_server* srv, genasm_completion_info* out, int max, uint32_t* runs,
+                      uint64_t runs_cap, uint64_t* runs_used, int timeout_ms);
+
+/* Cancels the request with this tag (the first one found, if tags repeat):
+ * a request still waiting on the host is dropped; a resident one runs to its
+ * end on the device, then its slot is freed without a completion. Either way
+ * no completion for it is delivered. Returns GENASM_E_INVAL when no waiting
+ * or resident request has the tag (already completed, or never submitted).
+ * Thread-safe. */
+int genasm_cancel(genasm_server* srv, uint64_t tag);
+
+/* Frees the CIGAR of a completion. */
 void genasm_completion_release(genasm_completion* c);
 
 int genasm_server_stats_read(genasm_server* srv, genasm_server_stats* out);
 
-/* Stops the engine (requests still waiting are dropped) and frees the server. */
+/* Stops the engine (requests still waiting are dropped; iterations on the
+ * device complete first) and frees the server. */
 void genasm_server_destroy(genasm_server* srv);
 
 /* Monotonic clock used by the completion timestamps, in nanoseconds. */
 uint64_t genasm_now_ns(void);
+
+/*
+ * Measured limits of the device the context runs on (library plumbing: the
+ * denominators of the roofline the window kernel is reported against; no
+ * paper passage). Each is the rate of a microbenchmark with exactly known
+ * work, timed with HIP events on the context's stream:
+ *   dc_mix_tops  the DC recurrence's own step in registers, as the window
+ *                kernels execute it (one DPP lane shift of a 64-bit word and
+ *                six 64-bit and/or/shift operations, counted as 12 int32
+ *                operations), on independent chains at full occupancy;
+ *   int32_tops   plain 32-bit and/or/xor chains;
+ *   lds_tbps     16-byte LDS reads without bank conflicts;
+ *   hbm_tbps     a 1 GiB device-to-device copy (read + write bytes).
+ * Allocates about 2 GiB of device memory for the duration of the call.
+ */
+typedef struct {
+    double dc_mix_tops;   /* int32 lane-operations per second / 1e12 */
+    double int32_tops;
+    double lds_tbps;      /* bytes per second / 1e12 */
+    double hbm_tbps;
+    int32_t compute_units;
+    int32_t reserved;
+} genasm_peaks;
+int genasm_measure_peaks(genasm_ctx* ctx, genasm_peaks* out);
 
 /* Library version string. */
 const char* genasm_version(void);

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgenasm.so")
-SOURCES = ["kernels.hip", "runtime.hip", "server.hip"]
+SOURCES = ["kernels.hip", "runtime.hip", "server.hip", "peaks.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -47,12 +47,36 @@ def build(verbose: bool = False, extra_flags=None) -> str:
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    write_build_info()
     return LIB
+
+
+BUILD_INFO = os.path.join(HERE, "BUILD_INFO.json")
+
+
+def write_build_info() -> None:
+    """Records the source revision the library was built from (the GPU runs
+    see the tree without its git history)."""
+    import json
+    info = {"git": None, "git_dirty": None, "arch": ARCH}
+    try:
+        rev = subprocess.run(["git", "-C", ROOT, "rev-parse", "HEAD"], capture_output=True,
+                             text=True, timeout=10)
+        st = subprocess.run(["git", "-C", ROOT, "status", "--porcelain", "--untracked-files=no"],
+                            capture_output=True, text=True, timeout=10)
+        if rev.returncode == 0:
+            info["git"] = rev.stdout.strip()
+            info["git_dirty"] = bool(st.stdout.strip())
+    except (OSError, subprocess.SubprocessError):
+        pass
+    with open(BUILD_INFO, "w") as f:
+        json.dump(info, f)
 
 
 if __name__ == "__main__":

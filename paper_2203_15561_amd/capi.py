@@ -68,6 +68,8 @@ class Launch(ctypes.Structure):
         ("hard_lanes", ctypes.c_int32),
         ("tb_prefetch", ctypes.c_int32),
         ("hard_share", ctypes.c_int32),
+        ("table_bits", ctypes.c_int32),
+        ("search_per_cu", ctypes.c_int32),
     ]
 
 
@@ -107,7 +109,20 @@ class ServerConfig(ctypes.Structure):
         ("max_pending", ctypes.c_uint32),
         ("window_budget", ctypes.c_uint32),
         ("use_graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("iteration_us", ctypes.c_int32),
+        ("cigar_runs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class Peaks(ctypes.Structure):
+    _fields_ = [
+        ("dc_mix_tops", ctypes.c_double),
+        ("int32_tops", ctypes.c_double),
+        ("lds_tbps", ctypes.c_double),
+        ("hbm_tbps", ctypes.c_double),
+        ("compute_units", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -133,11 +148,15 @@ class ServerStats(ctypes.Structure):
         ("pending", ctypes.c_uint32),
         ("pool_bases_used", ctypes.c_uint64),
         ("device_ms", ctypes.c_double),
+        ("cancelled", ctypes.c_uint64),
     ]
 
 
+COMPLETION_INFO_DTYPE = np.dtype([("tag", "<u8"), ("result", RESULT_DTYPE), ("submit_ns", "<u8"),
+                                  ("admit_ns", "<u8"), ("done_ns", "<u8")])
+assert COMPLETION_INFO_DTYPE.itemsize == 64
 assert ctypes.sizeof(ServerConfig) == 48 and ctypes.sizeof(Completion) == 72
-assert ctypes.sizeof(ServerStats) == 64
+assert ctypes.sizeof(ServerStats) == 72
 
 
 # Every symbol include/genasm.h declares.
@@ -150,6 +169,7 @@ EXPORTS = [
     "genasm_now_ns", "genasm_filter", "genasm_filter_dev", "genasm_autotune_dev",
     "genasm_tune_cache_save", "genasm_tune_cache_load", "genasm_tune_cache_size",
     "genasm_profile_pairs", "genasm_unpin", "genasm_batch_align_dev_noalloc",
+    "genasm_submit_batch", "genasm_poll_batch", "genasm_measure_peaks", "genasm_cancel",
 ]
 
 _c = ctypes
@@ -187,7 +207,14 @@ _SIGS = {
                                         _c.POINTER(_c.c_void_p)]),
     "genasm_submit": (_c.c_int, [_c.c_void_p, _c.c_char_p, _c.c_uint64, _c.c_char_p, _c.c_uint64,
                                  _c.c_int32, _c.c_int32, _c.c_int32, _c.c_uint64]),
+    "genasm_submit_batch": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                       _c.c_void_p, _c.c_uint64, _c.c_int32, _c.c_int32,
+                                       _c.c_int32, _c.c_void_p, _u64p]),
+    "genasm_measure_peaks": (_c.c_int, [_c.c_void_p, _c.c_void_p]),
+    "genasm_cancel": (_c.c_int, [_c.c_void_p, _c.c_uint64]),
     "genasm_poll": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int, _c.c_int]),
+    "genasm_poll_batch": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int, _c.c_void_p, _c.c_uint64,
+                                     _u64p, _c.c_int]),
     "genasm_completion_release": (None, [_c.POINTER(Completion)]),
     "genasm_server_stats_read": (_c.c_int, [_c.c_void_p, _c.POINTER(ServerStats)]),
     "genasm_server_destroy": (None, [_c.c_void_p]),
@@ -471,7 +498,14 @@ class Context:
     def tune_cache_size(self) -> int:
         return int(lib().genasm_tune_cache_size(self._ctx))
 
-    def profile(self, on: bool = True):
+    def measure_peaks(self) -> dict:
+        """Measured device limits (genasm_measure_peaks)."""
+        pk = Peaks()
+        self._check(lib().genasm_measure_peaks(self._ctx, ctypes.byref(pk)), "genasm_measure_peaks")
+        return {f[0]: getattr(pk, f[0]) for f in Peaks._fields_ if f[0] != "reserved"}
+
+    def profile(self, on=True):
+        """on: False/0 off, True/1 stage times and work counters, 2 stage times only."""
         self._check(lib().genasm_profile_enable(self._ctx, int(on)), "genasm_profile_enable")
 
     def profile_read(self) -> dict:
@@ -514,34 +548,78 @@ class Server:
 
     def __init__(self, ctx: Context, k: int, W: int = 64, O: int = 24, max_slots: int = 0,
                  pool_bases: int = 0, max_pending: int = 0, window_budget: int = 0,
-                 use_graph: int = 1):
-        cfg = ServerConfig(k, W, O, max_slots, pool_bases, max_pending, window_budget, use_graph)
+                 use_graph: int = 1, iteration_us: int = 0, cigar_runs: int = 0):
+        cfg = ServerConfig(k, W, O, max_slots, pool_bases, max_pending, window_budget, use_graph,
+                           iteration_us, cigar_runs, 0)
         self._srv = ctypes.c_void_p()
         rc = lib().genasm_server_create(ctx._ctx, ctypes.byref(cfg), ctypes.byref(self._srv))
         if rc:
             raise GenasmError(rc, "genasm_server_create")
         self.ctx = ctx
         self.k, self.W, self.O = k, W, O
-        self._buf = (Completion * 1024)()
+        self.cigar_runs = bool(cigar_runs)
+        self._buf = (Completion * 4096)()
 
     def submit(self, read, ref, tag: int) -> int:
         """Queues one request; returns 0 or a GENASM_E_* code (E_BUSY: back-pressure)."""
         r, f = _ascii(read), _ascii(ref)
         return lib().genasm_submit(self._srv, r, len(r), f, len(f), self.k, self.W, self.O, tag)
 
-    def poll(self, max_n: int = 1024, timeout_ms: int = 0) -> list:
+    def submit_batch(self, reads2b, read_off, refs2b, ref_off, tags) -> tuple:
+        """Queues requests from 2-bit packed numpy streams with base offsets
+        (n + 1 each) and n tags; returns (rc, accepted)."""
+        reads2b = np.ascontiguousarray(reads2b, dtype=np.uint8)
+        refs2b = np.ascontiguousarray(refs2b, dtype=np.uint8)
+        read_off = np.ascontiguousarray(read_off, dtype=np.uint64)
+        ref_off = np.ascontiguousarray(ref_off, dtype=np.uint64)
+        tags = np.ascontiguousarray(tags, dtype=np.uint64)
+        acc = ctypes.c_uint64(0)
+        rc = lib().genasm_submit_batch(self._srv, reads2b.ctypes.data, read_off.ctypes.data,
+                                       refs2b.ctypes.data, ref_off.ctypes.data, len(tags), self.k,
+                                       self.W, self.O, tags.ctypes.data, ctypes.byref(acc))
+        return rc, int(acc.value)
+
+    def cancel(self, tag: int) -> int:
+        """Cancels a waiting or resident request; returns 0 or E_INVAL (no such request)."""
+        return lib().genasm_cancel(self._srv, tag)
+
+    def poll(self, max_n: int = 4096, timeout_ms: int = 0) -> list:
+        """Completions as dicts; "cigar" is the text, or (cigar_runs) a uint32
+        array of run-length elements."""
         n = lib().genasm_poll(self._srv, self._buf, min(max_n, len(self._buf)), timeout_ms)
         if n < 0:
             raise GenasmError(n, "genasm_poll")
         out = []
         for c in self._buf[:n]:
             r = c.result
+            if self.cigar_runs:
+                cig = np.ctypeslib.as_array((ctypes.c_uint32 * r.cigar_len).from_address(c.cigar)).copy() \
+                    if c.cigar and r.cigar_len else np.zeros(0, np.uint32)
+            else:
+                cig = ctypes.string_at(c.cigar).decode() if c.cigar else ""
             out.append({"tag": c.tag, "edit_distance": r.edit_distance, "ref_begin": r.ref_begin,
                         "ref_end": r.ref_end, "n_windows": r.n_windows, "flags": r.flags,
-                        "cigar": ctypes.string_at(c.cigar).decode() if c.cigar else "",
-                        "submit_ns": c.submit_ns, "admit_ns": c.admit_ns, "done_ns": c.done_ns})
+                        "cigar": cig, "submit_ns": c.submit_ns, "admit_ns": c.admit_ns,
+                        "done_ns": c.done_ns})
             lib().genasm_completion_release(ctypes.byref(c))
         return out
+
+    def poll_arrays(self, max_n: int = 65536, timeout_ms: int = 0, runs_cap: int = 1 << 24):
+        """Bulk poll: (structured array of completion infos, uint32 run
+        elements they index), both numpy."""
+        if getattr(self, "_info", None) is None or len(self._info) < max_n:
+            self._info = np.zeros(max_n, dtype=COMPLETION_INFO_DTYPE)
+        if getattr(self, "_runs", None) is None or len(self._runs) < runs_cap:
+            self._runs = np.zeros(runs_cap, dtype=np.uint32)
+        used = ctypes.c_uint64(0)
+        n = lib().genasm_poll_batch(self._srv, self._info.ctypes.data, max_n, self._runs.ctypes.data,
+                                    len(self._runs), ctypes.byref(used), timeout_ms)
+        if n == E_NOSPACE:
+            self._runs = np.zeros(max(int(used.value), 2 * len(self._runs)), dtype=np.uint32)
+            return self.poll_arrays(max_n, timeout_ms, len(self._runs))
+        if n < 0:
+            raise GenasmError(n, "genasm_poll_batch")
+        return self._info[:n].copy(), self._runs[:used.value].copy()
 
     def stats(self) -> dict:
         st = ServerStats()

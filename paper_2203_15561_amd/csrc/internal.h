@@ -35,7 +35,8 @@ struct genasm_ctx {
     // until genasm_unpin
     bool pinned = false;
     // profiling
-    bool profiling = false;
+    bool profiling = false;      // stage times (HIP events) of device-form calls
+    bool prof_counters = false;  // and the per-pair work counters
     bool have_profile = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     char* stats = nullptr;
@@ -69,6 +70,7 @@ constexpr uint32_t kStateDone = 2u;       // result written
 constexpr uint32_t kStateFailed = 4u;
 constexpr uint32_t kStateInternal = 8u;
 constexpr uint32_t kStateOverflow = 16u;
+constexpr uint32_t kStateDeep = 32u;      // compact groups: the last window needed 16 rows or more
 
 // Per-pair start-search outcome kept in device scratch.
 struct SearchOut {
@@ -122,12 +124,22 @@ struct AlignParams {
     int32_t tb_prefetch;        // tracebacks over spilled rows load the next row ahead
     int32_t hard_share;         // percent of window workers that start on the hard queue
     int32_t route;              // search: append finished pairs to the window lists
+    int32_t compact;            // window kernel: compact 16-lane groups (32-bit table slices)
     // Optional per-pair layout (serving: sequences sit anywhere in a device pool).
     const uint32_t* read_len;   // if set, pair i's read is [read_off[i], read_off[i] + read_len[i])
     const uint32_t* ref_len;
     const uint64_t* run_base;   // if set, first CIGAR element of pair i; else from the offsets
     PairState* state;           // if set, window state persists here between launches
     uint32_t window_budget;     // windows a pair may advance per launch (0 = to the end)
+    // Serving iterations (all null outside the serving form):
+    const unsigned long long* deadline;  // device wall clock (100 MHz) after which a pair
+                                         // starts no window past its first in this launch
+    uint32_t* fin_list;         // pairs that ended in this launch (their result is written)
+    uint32_t* fin_len;
+    uint32_t* next_hot;         // unfinished pairs that advanced at most one window
+    uint32_t* next_cold;        // unfinished pairs that advanced more
+    uint32_t* next_len;         // counters block of the next launch: its easy (hot) and hard
+                                // (cold) list lengths at kCounterEasyLen / kCounterHardLen
 };
 
 // Per-pair work counters written when AlignParams::stats is set.
@@ -169,6 +181,8 @@ constexpr int kGroupHeaderWords32 = 192;
 __host__ __device__ inline int window_group_words32(int lds_rows, int stride) {
     return kGroupHeaderWords32 + lds_rows * stride + 1;
 }
+// Compact window groups keep every row of a deep window in their spill area.
+constexpr int kCompactSpillRows = 64;
 // Words of the table stride, the spill of one worker and its end word.
 inline uint64_t spill_words(uint64_t workers, int spill_rows, int stride) {
     return workers * (uint64_t)spill_rows * (uint64_t)stride + 1;
@@ -192,6 +206,8 @@ uint64_t unimproved_table_words(uint64_t n_pairs);
 hipError_t launch_unimproved(const AlignParams& p, unsigned long long* table, hipStream_t s);
 hipError_t launch_search(const AlignParams& p, int group_lanes, int rows_per_lane, int blocks,
                          hipStream_t s);
+// Start-search workgroups one compute unit holds at once, 0 on error.
+int search_blocks_per_cu(int group_lanes, int rows_per_lane);
 hipError_t launch_windows(const AlignParams& p, int blocks, hipStream_t s);
 // Window workgroups one compute unit holds at once (registers and LDS), 0 on error.
 int windows_blocks_per_cu(const AlignParams& p);
@@ -210,14 +226,44 @@ constexpr uint32_t kServeSearchChunk = 1024;
 inline uint64_t search_item_cap(uint64_t n_pairs, uint64_t total_ref_bases, uint32_t chunk) {
     return chunk ? n_pairs + total_ref_bases / chunk + 1 : n_pairs + 1;
 }
-// Serving: stage-0 search list length and the easy window list length come
-// from a device parameter block (set by a copy before the launch or a replay).
-hipError_t launch_init_counters_dev(uint32_t* counters, const uint32_t* params, hipStream_t s);
-hipError_t launch_reset_states(PairState* state, const uint32_t* list, const uint32_t* params,
-                               uint32_t max_n, hipStream_t s);
-hipError_t launch_gather_runs(const genasm_result* out, const uint32_t* list, uint32_t n,
-                              const uint64_t* dst_off, const uint32_t* cigar, uint32_t* dst,
-                              hipStream_t s);
+// Serving iterations. A device parameter block (copied from the host before
+// each launch or graph replay) holds kServeParam* words.
+constexpr int kServeParamNew = 0;       // pairs admitted in this iteration
+constexpr int kServeParamTicks = 1;     // window time of the iteration, 100 MHz ticks (0 = none)
+constexpr int kServeParamWords = 4;
+// One admitted request: its slot and where its bases and CIGAR go in the pools.
+struct ServeAdmit {
+    uint64_t read_off, ref_off, run_base;
+    uint32_t slot, m, n, pad;
+};
+// Per-slot tables the admission kernel fills.
+struct ServeSlots {
+    uint64_t* read_off;
+    uint64_t* ref_off;
+    uint64_t* run_base;
+    uint32_t* read_len;
+    uint32_t* ref_len;
+    PairState* state;
+};
+// Starts an iteration: clears the search and queue counters of this
+// iteration's block `cur` (kCounterPairs = admitted pairs), the next block's
+// list lengths and the finished count, then writes the admitted slots'
+// tables, resets their window state and lists them in new_list.
+hipError_t launch_serve_begin(uint32_t* cur, uint32_t* next, uint32_t* fin_len,
+                              const uint32_t* params, const ServeAdmit* admit, ServeSlots slots,
+                              uint32_t* new_list, hipStream_t s);
+// Sets *deadline = now + the iteration's window time (or ~0 when it is 0).
+hipError_t launch_serve_stamp(const uint32_t* params, unsigned long long* deadline, hipStream_t s);
+// Ends an iteration: the finished pairs' CIGAR offsets (a prefix sum over
+// their element counts) into fin_off, their slots and results (cigar_off =
+// that offset) into the host-mapped summary (hdr[0] = count, hdr[1] = total
+// elements), then their CIGAR elements from the pool into dst (elements past
+// dst_cap are left for the host to fetch).
+hipError_t launch_serve_finish(const uint32_t* fin_list, const uint32_t* fin_len,
+                               const genasm_result* out, uint64_t* fin_off,
+                               unsigned long long* hdr, uint32_t* sum_slot,
+                               genasm_result* sum_res, const uint32_t* cigar, uint32_t* dst,
+                               uint64_t dst_cap, uint32_t max_fin, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s);
 // Longest-read-first pair order (approximate: reads are bucketed by length)
 // into order[0..n_pairs); hist is kLptBuckets words of scratch.
@@ -253,6 +299,7 @@ hipError_t launch_scatter_planes(const uint8_t* src, const uint64_t* src_off, co
 // Occupancy helpers.
 int plain_lds_bytes(int stride);
 int window_lds_bytes(int lds_rows, int stride);
+int compact_lds_bytes(int stride);
 int search_lds_bytes(int group_lanes);
 
 }  // namespace genasm

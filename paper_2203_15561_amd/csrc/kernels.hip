@@ -347,7 +347,7 @@ __device__ void dc_pass(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int
 // SoLayout): the same computation, with the operand reads and the
 // boundary-row write at per-step constant offsets and one clamp for the table
 // store.
-template <int G, bool SPILL, bool FIRST>
+template <int G, bool SPILL, bool FIRST, int U = 8>
 __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int stride,
                            int lds_rows) {
     using Lay = SoLayout<G>;
@@ -363,7 +363,6 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
     const int slot0 = nw + gl;       // table slot 1 + i at t = 0 (column i = nw - 1 - t + gl)
     const int hi_slot = Lc + 2;
     const int steps = nw + G - 1;
-    constexpr int U = 8;
     u64 qpm[U], qov[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -738,9 +737,9 @@ __device__ __forceinline__ PairState fresh_state(int s) {
 // consumed, or a window without a solution within K) the result and the last
 // CIGAR run are written and st gets kStateDone.
 template <int G>
-__device__ __forceinline__ void advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds_rows, int gl,
+__device__ __forceinline__ uint32_t advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds_rows, int gl,
                              int lane, uint64_t pair, const PairCursor& pc, int s, PairState& st,
-                             uint32_t budget) {
+                             uint32_t budget, u64 deadline) {
     const uint64_t run_base = pair_run_base(P, pair);
     const uint64_t run_limit = min(P.cigar_cap, run_base + (uint64_t)pc.m + (uint64_t)pc.n);
     uint32_t* runs = reinterpret_cast<uint32_t*>(lds + runs_off<G>());
@@ -766,6 +765,12 @@ __device__ __forceinline__ void advance_pair(const AlignParams& P, u64* lds, u64
         seq_open(fc, P.ref_lo, P.ref_hi, pc.fb - forg + st.ti);
     }
     while (st.pj < pc.m && (budget == 0 || done_here < budget)) {
+        // every pair advances at least one window per launch (so that a late
+        // start never leaves a pair without progress); no further window
+        // starts once the deadline has passed. The device clock is read by a
+        // scalar instruction: one value per wavefront, so every lane of the
+        // group takes the same branch.
+        if (deadline && done_here > 0 && wall_clock64() >= deadline) break;
         if (st.nwin >= max_windows) { failed = true; internal = true; break; }
         const int mw = min(P.W, pc.m - st.pj);
         const int nw = min(P.W, pc.n - st.ti);
@@ -903,6 +908,7 @@ __device__ __forceinline__ void advance_pair(const AlignParams& P, u64* lds, u64
         if (!stp[kStatPairStart]) stp[kStatPairStart] = wall_start;
         stp[kStatPairEnd] = wall_clock64();
     }
+    return done_here;
 }
 
 // Runs (or resumes, when window state persists in P.state) the windows of a
@@ -913,14 +919,28 @@ __device__ __forceinline__ void run_pair(const AlignParams& P, u64* lds, u64* sp
     const PairCursor pc = pair_cursor(P, pair);
     if (!P.state) {
         PairState st = fresh_state(s);
-        advance_pair<G>(P, lds, spill, lds_rows, gl, lane, pair, pc, s, st, 0u);
+        advance_pair<G>(P, lds, spill, lds_rows, gl, lane, pair, pc, s, st, 0u, 0ull);
         return;
     }
     PairState st = P.state[pair];
     if (st.flags & kStateDone) return;
     if (!(st.flags & kStateStarted)) st = fresh_state(s);
-    advance_pair<G>(P, lds, spill, lds_rows, gl, lane, pair, pc, s, st, P.window_budget);
-    if (gl == 0) P.state[pair] = st;
+    const u64 deadline = P.deadline ? *P.deadline : 0ull;
+    const uint32_t advanced =
+        advance_pair<G>(P, lds, spill, lds_rows, gl, lane, pair, pc, s, st, P.window_budget, deadline);
+    if (gl == 0) {
+        P.state[pair] = st;
+        // serving: the pair's list for the next iteration (hot: its turn was
+        // cut after one window, so it goes first next time), or the finished list
+        if (P.fin_list) {
+            if (st.flags & kStateDone)
+                P.fin_list[atomicAdd(P.fin_len, 1u)] = (uint32_t)pair;
+            else if (advanced <= 1)
+                P.next_hot[atomicAdd(P.next_len + kCounterEasyLen, 1u)] = (uint32_t)pair;
+            else
+                P.next_cold[atomicAdd(P.next_len + kCounterHardLen, 1u)] = (uint32_t)pair;
+        }
+    }
 }
 
 // Start-search counters of one pair (lane 0); `row` is the hit row or, when
@@ -1478,7 +1498,7 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t* len, bool want) {
 __global__ void k_search_finalize(AlignParams P) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t n_items = search_pairs(P);
-    bool easy = false, hard = false;
+    bool easy = false, hard = false, ended = false;
     uint64_t pair = 0;
     if (k < n_items) {
         pair = P.list_in ? P.list_in[k] : k;
@@ -1487,6 +1507,12 @@ __global__ void k_search_finalize(AlignParams P) {
             hard = row >= P.hard_row;
             easy = !hard;
         }
+        ended = row < 0;
+    }
+    if (P.fin_list) {
+        // serving: a pair that ends in its search (empty read, no hit) is finished
+        const uint32_t pf = wave_append(P.fin_len, ended);
+        if (ended) P.fin_list[pf] = (uint32_t)pair;
     }
     if (!P.route) return;
     const uint32_t pe = wave_append(P.counters + kCounterEasyLen, easy);
@@ -1565,6 +1591,409 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
             const SearchOut so = P.search[pair];
             if (so.row < 0) continue;  // ended in the search (result already written)
             run_pair<16>(P, lds, spill, P.lds_rows, gl, lane, pair, (int)so.col);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Compact window groups: 16 lanes, the table in LDS as 32-bit slices
+// ---------------------------------------------------------------------------
+//
+// The traceback of a window reads, at an edit from state (i, j, d), bits p-1
+// and p of R[d-1][i+1] and bit p-1 of R[d-1][i], with p = mw-1-j. Every edit
+// moves the diagonal i - j by at most one, so after d*-d edits |i - j| <=
+// d*-d: the bits the traceback can ever read from entry (r, c) lie within
+// d*-r positions of bit mw-1-c. When d* <= 15 that is a 32-bit window, and
+// the table can keep 32 bits per entry instead of 64.
+//
+// The pass runs in aligned form: every word shifted left by a = 64 - mw, so
+// that the first pattern base is bit 63 whatever mw is (the recurrence is
+// unchanged under the shift: the row above row 0 is all ones, the bit that
+// row 0 adds is 1 << a, the initial column is (~0 << d) << a, and PM is
+// shifted likewise; bits below a stay zero). Entry (r, c) keeps the 32 bits
+// of the aligned word from bit o(c) = max(0, 47-c) on: the traceback's bits
+// 62-j (and 63-j) then sit at 62-j-o(c) (63-j-o(c)), which with |i - j| <= 14
+// is in 0..31 (15+e at column i and 16+e, 17+e at column i+1 for columns up
+// to 47, e = i - j). Columns past 47 occur only when W-O > 47.
+//
+// Layout of a compact group (64-bit words): the step-ordered PM[T] array at
+// words 0..78 (kCompactPmt + x for x in -15..63; the traceback's run records
+// reuse it), then 16 table rows of `stride` 32-bit slots from word
+// kCompactTab (slot 0 and slot W-O+2 of a row are dummies, as in the 64-bit
+// table). A window that needs more than 16 rows (a deep window) is computed
+// again with 64-bit rows, all of them in the group's spill area in device
+// memory, using the 16-lane code of the 64-bit layout: its boundary row and
+// run records then sit in the table area, at the same offsets as there.
+constexpr int kCompactPmt = 15;
+constexpr int kCompactTab = 79;
+constexpr int kCompactRows = 16;
+constexpr int kCompactU = 4;  // DC steps per unrolled chunk (compact and deep passes)
+static_assert(kCompactSpillRows == 64, "a deep window may need every row");
+static_assert(kCompactTab == kCompactPmt + 64, "layout");
+// Words the deep (64-bit, spilled) passes use past the PM[T] array: the
+// boundary row at SoLayout<16>::brow = 94 with reads up to word 94 + nw + 13
+// + 2U, and the run records at 94..157.
+constexpr int kCompactDeepWords = OFF_BROW16 + 64 + 13 + 2 * kCompactU + 1;
+
+__host__ __device__ inline int compact_group_words(int stride) {
+    const int tab = kCompactTab + (kCompactRows * stride + 1 + 1) / 2;
+    return tab > kCompactDeepWords ? tab : kCompactDeepWords;
+}
+
+// Aligned initial word of row d: (~0 << d) << a.
+__device__ __forceinline__ u64 init_word_a(int d, int a) { return d + a >= 64 ? 0ull : (~0ull << (d + a)); }
+
+// Slice offset o(c) of the compact table (see above).
+__device__ __forceinline__ int slice_off(int c) { return max(0, 47 - c); }
+
+// Pass 0 of a window in aligned form (this lane: row gl), storing each
+// entry's 32-bit slice (slot 1 + c of row gl; steps outside columns 0..Lc
+// store into the dummies, and the leading steps whose columns all lie past
+// Lc store nothing). WIDE: stored columns may pass 47 (W-O > 47), so the
+// slice offset needs its clamp at zero.
+template <bool WIDE>
+__device__ __forceinline__ void dc_pass_c(u64* lds, int gl, int nw, int Lc, int stride, int a) {
+    uint32_t* trow = reinterpret_cast<uint32_t*>(lds + kCompactTab) + gl * stride;
+    const u64* pp = lds + kCompactPmt - gl;  // + t: PMT[t - gl]
+    u64 R = init_word_a(gl, a);
+    u64 Dp = gl == 0 ? ~0ull : init_word_a(gl - 1, a);
+    const u64 lowin = gl == 0 ? (1ull << a) : 0ull;
+    if (Lc == nw) trow[1 + nw] = (uint32_t)(R >> slice_off(nw));  // column nw: the initial word
+    const int slot0 = nw + gl;      // slot 1 + i at t = 0 (column i = nw - 1 - t + gl)
+    const int sh0 = 48 - nw - gl;   // 47 - i at t = 0
+    const int hi_slot = Lc + 2;
+    const int steps = nw + 15;
+    constexpr int U = kCompactU;
+    u64 qpm[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) qpm[u] = pp[u];
+    auto chunk = [&](int t0, auto store) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u;
+            const u64 pm_t = qpm[u];
+            const u64 up = shift_up<16>(~0ull, R, gl);
+            const u64 x = Dp & (((Dp & up) << 1) | lowin);
+            R = x & ((R << 1) | pm_t);
+            Dp = up;
+            if constexpr (decltype(store)::value) {
+                // live stores have 47 - i <= 47; the dummies store garbage
+                const int sh = WIDE ? max(0, sh0 + t) : sh0 + t;
+                trow[med3i(slot0 - t, 0, hi_slot)] = (uint32_t)(R >> (sh & 63));
+            }
+            if (u & 1) {
+                qpm[u - 1] = pp[t - 1 + U];
+                qpm[u] = pp[t + U];
+            }
+        }
+    };
+    using yes = std::integral_constant<bool, true>;
+    using no = std::integral_constant<bool, false>;
+    const int t_free = nw - Lc - 1;
+    int t0 = 0;
+    for (; t0 + U <= t_free; t0 += U) chunk(t0, no{});
+    for (; t0 < steps; t0 += U) chunk(t0, yes{});
+}
+
+// Traceback of a compact window (d* <= 15): traceback_planes with the edge
+// bits taken from the 32-bit slices.
+__device__ __forceinline__ TbOut traceback_c(const u64* lds, uint32_t* runs, RunState& rs, u64 pl,
+                                             u64 ph, u64 tl, u64 th, int mw, int nw, int dstar, int L,
+                                             int stride) {
+    const uint32_t* tab = reinterpret_cast<const uint32_t*>(lds + kCompactTab) + 1;
+    const int jmax = min(mw, L);
+    int i = 0, j = 0, d = dstar;
+    TbOut o{0, 0, 0, 0u, false};
+    for (int it = 0; it <= 2 * L; ++it) {
+        if (j >= jmax || i >= L) break;
+        const u64 mis = ((pl >> j) ^ (tl >> i)) | ((ph >> j) ^ (th >> i));
+        const int k = min(ctz64(mis), min(jmax - j, min(L - i, nw - i)));
+        {
+            const bool push = k > 0;
+            const bool changed = push && rs.cur_op != (int)GENASM_OP_MATCH;
+            rs.nr += changed ? 1 : 0;
+            rs.cur_len = changed ? (uint32_t)k : rs.cur_len + (uint32_t)k;
+            rs.cur_op = push ? (int)GENASM_OP_MATCH : rs.cur_op;
+            runs[max(rs.nr, 0)] = (rs.cur_len << 2) | (uint32_t)rs.cur_op;
+            i += k;
+            j += k;
+            if (j >= jmax || i >= L) break;
+        }
+        if (d < 1) { o.internal = true; break; }
+        const uint32_t* row = tab + (d - 1) * stride;
+        const uint32_t C = row[i];
+        const uint32_t B = row[i + 1];
+        const int kc = 62 - j - slice_off(i);      // bit p-1 of R[d-1][i]
+        const int kb = 62 - j - slice_off(i + 1);  // bit p-1 of R[d-1][i+1]; bit p is kb + 1
+        const bool intext = i < nw;
+        const bool s_ok = intext && !((B >> kb) & 1u);
+        const bool i_ok = !((C >> kc) & 1u);
+        const bool d_ok = intext && !((B >> (kb + 1)) & 1u);
+        if (!(s_ok || i_ok || d_ok)) { o.internal = true; break; }
+        const int op = s_ok ? GENASM_OP_MISMATCH : i_ok ? GENASM_OP_INS : GENASM_OP_DEL;
+        run_push(runs, rs, op, 1u, true);
+        o.reads += 2u;
+        i += op != GENASM_OP_INS;
+        j += op != GENASM_OP_DEL;
+        d -= 1;
+    }
+    o.i_end = i;
+    o.j_end = j;
+    o.edits = dstar - d;
+    return o;
+}
+
+// advance_pair for compact groups. A window first runs the compact pass
+// (unless the pair's previous window was deep); when no row below 16 solves,
+// it is computed again with 64-bit rows in the spill area (every row, in
+// passes of 16) and traced back from there. STATS: profiling counters.
+template <bool STATS>
+__device__ __forceinline__ uint32_t advance_pair_c(const AlignParams& P, u64* lds, u64* spill, int gl,
+                                                   int lane, uint64_t pair, const PairCursor& pc,
+                                                   int s, PairState& st, uint32_t budget,
+                                                   u64 deadline) {
+    constexpr int G = 16;
+    const uint64_t run_base = pair_run_base(P, pair);
+    const uint64_t run_limit = min(P.cigar_cap, run_base + (uint64_t)pc.m + (uint64_t)pc.n);
+    uint32_t* runs_c = reinterpret_cast<uint32_t*>(lds);               // PM[T] area, free after the pass
+    uint32_t* runs_d = reinterpret_cast<uint32_t*>(lds + OFF_RUNS16);  // deep windows
+    RunState rs{st.cur_op, st.cur_len, st.cur_op >= 0 ? 0 : -1};
+    bool overflow = (st.flags & kStateOverflow) != 0;
+    bool deep = (st.flags & kStateDeep) != 0;
+    bool failed = false, internal = false;
+    u64 st_wops = 0, st_cells = 0, st_table = 0, st_tb = 0, st_steps = 0;
+    u64 cyc_dc = 0, cyc_tb = 0, cyc_start = 0, wall_start = 0;
+    if constexpr (STATS) {
+        cyc_start = clock64();
+        wall_start = wall_clock64();
+    }
+    const uint32_t max_windows = (uint32_t)pc.m + (uint32_t)pc.n + 1u;
+    uint32_t done_here = 0;
+    const uint64_t rorg = P.planes_from_off0 ? (P.read_off[0] & ~63ull) : 0;
+    const uint64_t forg = P.planes_from_off0 ? (P.ref_off[0] & ~63ull) : 0;
+    SeqCursor rc, fc;
+    if (st.pj < pc.m) {
+        seq_open(rc, P.read_lo, P.read_hi, pc.rb - rorg + st.pj);
+        seq_open(fc, P.ref_lo, P.ref_hi, pc.fb - forg + st.ti);
+    }
+    while (st.pj < pc.m && (budget == 0 || done_here < budget)) {
+        // see advance_pair: at least one window per launch, none started past the deadline
+        if (deadline && done_here > 0 && wall_clock64() >= deadline) break;
+        if (st.nwin >= max_windows) { failed = true; internal = true; break; }
+        const int mw = min(P.W, pc.m - st.pj);
+        const int nw = min(P.W, pc.n - st.ti);
+        const int Lc = min(nw, P.L);
+        ++st.nwin;
+        ++done_here;
+        u64 cyc0 = 0;
+        if constexpr (STATS) cyc0 = clock64();
+        u64 pl, ph, tl, th;
+        seq_window(rc, P.read_lo, P.read_hi, pc.rb - rorg + st.pj, pl, ph);
+        seq_window(fc, P.ref_lo, P.ref_hi, pc.fb - forg + st.ti, tl, th);
+        const int Kr = nw > 0 ? min(P.K, mw - 1) : -1;
+        int dstar = -1;
+        bool compact = false;
+        if constexpr (STATS) st_cells += (u64)mw * nw;
+        if (Kr >= 0) {
+            u64 pm[4];
+            pm_from_planes(pl, ph, mw, pm);
+            if (!deep) {
+                const int a = 64 - mw;
+                const u64 pma[4] = {pm[0] << a, pm[1] << a, pm[2] << a, pm[3] << a};
+                store_pmt_so<G>(lds, gl, pma, tl, th, nw);
+                wave_sync();
+                if constexpr (STATS) st_steps += (u64)G * (nw + G - 1);
+                if (P.L > 47) dc_pass_c<true>(lds, gl, nw, Lc, P.stride, a);
+                else dc_pass_c<false>(lds, gl, nw, Lc, P.stride, a);
+                wave_sync();
+                const uint32_t s0 = reinterpret_cast<const uint32_t*>(lds + kCompactTab)[gl * P.stride + 1];
+                const bool sol = gl <= Kr && !((s0 >> 16) & 1u);  // bit 63 of the aligned word
+                const u64 bits = group_ballot(sol, G, lane);
+                if (bits) {
+                    dstar = __builtin_ctzll(bits);
+                } else if (Kr < G) {
+                    // every row that needs computing was computed: row mw solves
+                    if (mw <= P.K) dstar = mw;
+                    else { failed = true; break; }
+                }
+                compact = dstar >= 0 && dstar < G;
+            }
+            if (!compact) {
+                // deep window: every row again, 64-bit, in the spill area
+                store_pmt_so<G>(lds, gl, pm, tl, th, nw);
+                wave_sync();
+                dstar = -1;
+                for (int c = 0; c * G <= Kr; ++c) {
+                    if constexpr (STATS) st_steps += (u64)G * (nw + G - 1);
+                    if (c == 0) {
+                        dc_pass_so<G, true, true, kCompactU>(lds, spill, gl, c, nw, Lc, P.stride, 0);
+                    } else {
+                        fill_brow<G>(lds, spill, gl, c, nw, Lc, P.stride, 0);
+                        wave_sync();
+                        dc_pass_so<G, true, false, kCompactU>(lds, spill, gl, c, nw, Lc, P.stride, 0);
+                    }
+                    mem_sync();
+                    const int d = c * G + gl;
+                    const u64 r0 = load_spill(spill + (size_t)d * P.stride + 1);
+                    const bool sol = d <= Kr && !((r0 >> (mw - 1)) & 1ull);
+                    const u64 bits = group_ballot(sol, G, lane);
+                    if (bits) { dstar = c * G + __builtin_ctzll(bits); break; }
+                }
+                if (dstar < 0) {
+                    if (mw <= P.K) dstar = mw;
+                    else { failed = true; break; }
+                }
+            }
+        }
+        u64 cyc1 = 0;
+        if constexpr (STATS) cyc1 = clock64();
+        TbOut t;
+        uint32_t* runs = compact || nw == 0 ? runs_c : runs_d;
+        run_window_start(runs, rs, true);
+        if (nw == 0) {
+            const int k = min(mw, P.L);
+            run_push(runs, rs, GENASM_OP_INS, (uint32_t)k, true);
+            t = TbOut{0, k, k, 0u, false};
+        } else if (compact) {
+            t = traceback_c(lds, runs, rs, pl, ph, tl, th, mw, nw, dstar, P.L, P.stride);
+        } else {
+            t = traceback_planes<G>(lds, spill, runs, rs, true, pl, ph, tl, th, mw, nw, dstar, P.L,
+                                    P.stride, 0, gl, lane, P.tb_prefetch != 0);
+        }
+        // the next window starts deep when this one needed more than 16 rows
+        if (nw > 0) deep = dstar >= G;
+        st.score += t.edits;
+        if constexpr (STATS) {
+            st_tb += t.reads;
+            st_wops += (u64)nw * (2 + 6 * dstar);
+            st_table += (u64)(dstar + 1) * (Lc + 1);
+        }
+        if (t.internal) { failed = true; internal = true; break; }
+        wave_sync();
+        const int closed = max(rs.nr, 0);
+        overflow |= copy_runs<G>(runs, closed, P.cigar, run_base, run_limit, st.written, gl);
+        st.written += (uint32_t)closed;
+        wave_sync();
+        st.ti += t.i_end;
+        st.pj += t.j_end;
+        if constexpr (STATS) {
+            const u64 cyc2 = clock64();
+            cyc_dc += cyc1 - cyc0;
+            cyc_tb += cyc2 - cyc1;
+        }
+    }
+    st.cur_op = rs.cur_op;
+    st.cur_len = rs.cur_len;
+    st.flags = deep ? (st.flags | kStateDeep) : (st.flags & ~kStateDeep);
+    const bool finished = failed || st.pj >= pc.m;
+    if (finished && !failed && gl == 0 && rs.cur_op >= 0) {
+        const uint64_t idx = run_base + st.written;
+        if (idx < run_limit) P.cigar[idx] = (rs.cur_len << 2) | (uint32_t)rs.cur_op;
+        else overflow = true;
+    }
+    if (group_ballot(overflow, G, lane) != 0) st.flags |= kStateOverflow;
+    if (failed) st.flags |= kStateFailed;
+    if (internal) st.flags |= kStateInternal;
+    if (finished) st.flags |= kStateDone;
+    if (gl == 0 && finished) {
+        const bool ovf = (st.flags & kStateOverflow) != 0;
+        genasm_result r;
+        if (failed) {
+            r.edit_distance = -1;
+            r.ref_begin = r.ref_end = 0;
+            r.cigar_len = 0;
+        } else {
+            r.edit_distance = st.score;
+            r.ref_begin = (uint32_t)s;
+            r.ref_end = (uint32_t)st.ti;
+            r.cigar_len = ovf ? 0u : st.written + (rs.cur_op >= 0 ? 1u : 0u);
+        }
+        r.n_windows = st.nwin;
+        r.cigar_off = run_base;
+        r.flags = (ovf && !failed ? GENASM_FLAG_CIGAR_OVERFLOW : 0u) |
+                  (internal ? GENASM_FLAG_INTERNAL : 0u);
+        P.out[pair] = r;
+    }
+    if constexpr (STATS) {
+        if (gl == 0) {
+            u64* stp = P.stats + pair * kStatCount;
+            stp[kStatWindowWordOps] += st_wops;
+            stp[kStatWindowCells] += st_cells;
+            stp[kStatTableWords] += st_table;
+            stp[kStatTbReads] += st_tb;
+            stp[kStatWindowLaneSteps] += st_steps;
+            stp[kStatWindows] += done_here;
+            stp[kStatDcCycles] += cyc_dc;
+            stp[kStatTbCycles] += cyc_tb;
+            stp[kStatPairCycles] += clock64() - cyc_start;
+            if (!stp[kStatPairStart]) stp[kStatPairStart] = wall_start;
+            stp[kStatPairEnd] = wall_clock64();
+        }
+    }
+    return done_here;
+}
+
+// run_pair for compact groups; `deep_start`: the pair came from the hard
+// queue, so its first window starts deep.
+template <bool STATS>
+__device__ __forceinline__ void run_pair_c(const AlignParams& P, u64* lds, u64* spill, int gl, int lane,
+                                           uint64_t pair, int s, bool deep_start) {
+    const PairCursor pc = pair_cursor(P, pair);
+    if (!P.state) {
+        PairState st = fresh_state(s);
+        if (deep_start) st.flags |= kStateDeep;
+        advance_pair_c<STATS>(P, lds, spill, gl, lane, pair, pc, s, st, 0u, 0ull);
+        return;
+    }
+    PairState st = P.state[pair];
+    if (st.flags & kStateDone) return;
+    if (!(st.flags & kStateStarted)) st = fresh_state(s);
+    const u64 deadline = P.deadline ? *P.deadline : 0ull;
+    const uint32_t advanced =
+        advance_pair_c<STATS>(P, lds, spill, gl, lane, pair, pc, s, st, P.window_budget, deadline);
+    if (gl == 0) {
+        P.state[pair] = st;
+        if (P.fin_list) {
+            if (st.flags & kStateDone)
+                P.fin_list[atomicAdd(P.fin_len, 1u)] = (uint32_t)pair;
+            else if (advanced <= 1)
+                P.next_hot[atomicAdd(P.next_len + kCounterEasyLen, 1u)] = (uint32_t)pair;
+            else
+                P.next_cold[atomicAdd(P.next_len + kCounterHardLen, 1u)] = (uint32_t)pair;
+        }
+    }
+}
+
+// Window kernel with compact groups (four 16-lane groups per wavefront, both
+// queues; see k_windows for the queues and the hard share). Each group's
+// spill area holds 64 rows of `stride` words.
+template <bool STATS>
+__global__ __launch_bounds__(64) void k_windows_c(AlignParams P) {
+    extern __shared__ u64 smem[];
+    const int lane = threadIdx.x & 63;
+    const uint32_t n_hard = __hip_atomic_load(P.counters + kCounterHardLen, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t n_easy = __hip_atomic_load(P.counters + kCounterEasyLen, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    const bool hard_first = (uint64_t)blockIdx.x * 100u < (uint64_t)gridDim.x * (uint32_t)P.hard_share;
+    const int gl = lane & 15;
+    const int grp = lane >> 4;
+    u64* lds = smem + grp * compact_group_words(P.stride);
+    u64* spill = P.spill + ((uint64_t)blockIdx.x * 4 + grp) * (uint64_t)kCompactSpillRows * P.stride;
+    for (int phase = 0; phase < 2; ++phase) {
+        const bool hard = (phase == 0) == hard_first;
+        const uint32_t* list = hard ? P.hard_list : P.easy_list;
+        const uint32_t n = hard ? n_hard : n_easy;
+        uint32_t* head = P.counters + (hard ? kCounterHardHead : kCounterEasyHead);
+        for (uint32_t iter = 0; iter <= n; ++iter) {
+            const uint32_t item = group_pop(head, lds, gl);
+            if (item >= n) break;
+            const uint64_t pair = list[item];
+            const SearchOut so = P.search[pair];
+            if (so.row < 0) continue;  // ended in the search (result already written)
+            // serving routes every pair to the easy list; there the hard list
+            // holds pairs that already advanced, whose state carries their mode
+            run_pair_c<STATS>(P, lds, spill, gl, lane, pair, (int)so.col, hard && !P.state);
         }
     }
 }
@@ -1725,30 +2154,92 @@ __global__ void k_scatter_bytes(const uint8_t* src, const uint64_t* src_off, uin
     for (uint32_t e = threadIdx.x; e < len[k]; e += blockDim.x) b[e] = a[e];
 }
 
-// Serving form: zeroes the window state of newly admitted pairs
-// (list[0..params[0])), so that the window kernel starts them afresh.
-__global__ void k_reset_states(PairState* state, const uint32_t* list, const uint32_t* params) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < params[0]) state[list[i]] = PairState{0, 0, 0, 0u, 0u, -1, 0u, 0u};
+// Serving iteration start (one block of 256 threads): counters of this
+// iteration and the next, then the admitted requests' slot tables and state.
+__global__ void k_serve_begin(uint32_t* cur, uint32_t* next, uint32_t* fin_len,
+                              const uint32_t* params, const ServeAdmit* admit, ServeSlots slots,
+                              uint32_t* new_list) {
+    const uint32_t n_new = params[kServeParamNew];
+    const int t = threadIdx.x;
+    if (t < kCounterCount) {
+        // this iteration's window lists (easy = advanced no window last time,
+        // hard = advanced) were filled by the previous iteration: their
+        // lengths stay; everything else starts at zero
+        if (t != kCounterEasyLen && t != kCounterHardLen) cur[t] = t == kCounterPairs ? n_new : 0u;
+        next[t] = 0u;
+    }
+    if (t == 0) *fin_len = 0u;
+    for (uint32_t i = t; i < n_new; i += blockDim.x) {
+        const ServeAdmit a = admit[i];
+        slots.read_off[a.slot] = a.read_off;
+        slots.ref_off[a.slot] = a.ref_off;
+        slots.run_base[a.slot] = a.run_base;
+        slots.read_len[a.slot] = a.m;
+        slots.ref_len[a.slot] = a.n;
+        slots.state[a.slot] = PairState{0, 0, 0, 0u, 0u, -1, 0u, 0u};
+        new_list[i] = a.slot;
+    }
 }
 
-// Serving form: copies the CIGAR elements of the pairs list[0..n) to dst, one
-// block per listed pair, at dst_off[k] for the k-th listed pair.
-__global__ void k_gather_runs(const genasm_result* out, const uint32_t* list, uint32_t n,
-                              const uint64_t* dst_off, const uint32_t* cigar, uint32_t* dst) {
-    const uint32_t k = blockIdx.x;
-    if (k >= n) return;
-    const genasm_result r = out[list[k]];
-    for (uint32_t e = threadIdx.x; e < r.cigar_len; e += blockDim.x)
-        dst[dst_off[k] + e] = cigar[r.cigar_off + e];
+__global__ void k_serve_stamp(const uint32_t* params, u64* deadline) {
+    const uint32_t ticks = params[kServeParamTicks];
+    *deadline = ticks ? wall_clock64() + ticks : ~0ull;
 }
 
-// Serving form: params[0] = stage-0 search list length, params[1] = easy
-// window list length (written by a host copy before each launch).
-__global__ void k_init_counters_dev(uint32_t* counters, const uint32_t* params) {
-    const int i = threadIdx.x;
-    if (i < kCounterCount)
-        counters[i] = i == kCounterPairs ? params[0] : i == kCounterEasyLen ? params[1] : 0u;
+// Serving iteration end, part 1 (one block of 1024 threads): prefix sum of the
+// finished pairs' CIGAR element counts, and the summary the host reads (slot,
+// result with cigar_off = the pair's offset in the gathered elements).
+__global__ __launch_bounds__(1024) void k_serve_scan(const uint32_t* fin_list, const uint32_t* fin_len,
+                                                     const genasm_result* out, uint64_t* fin_off,
+                                                     u64* hdr, uint32_t* sum_slot,
+                                                     genasm_result* sum_res, uint32_t max_fin) {
+    __shared__ u64 part[1024];
+    const uint32_t n = min(*fin_len, max_fin);
+    const int t = threadIdx.x;
+    const uint32_t per = (n + 1023) / 1024;
+    const uint32_t lo = min(n, (uint32_t)t * per), hi = min(n, lo + per);
+    u64 sum = 0;
+    for (uint32_t k = lo; k < hi; ++k) sum += out[fin_list[k]].cigar_len;
+    part[t] = sum;
+    __syncthreads();
+    // inclusive scan of the 1024 partial sums
+    for (int d = 1; d < 1024; d <<= 1) {
+        const u64 v = t >= d ? part[t - d] : 0ull;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    u64 off = part[t] - sum;
+    for (uint32_t k = lo; k < hi; ++k) {
+        const uint32_t slot = fin_list[k];
+        genasm_result r = out[slot];
+        fin_off[k] = off;
+        sum_slot[k] = slot;
+        r.cigar_off = off;
+        sum_res[k] = r;
+        off += r.cigar_len;
+    }
+    if (t == 1023) {
+        hdr[0] = n;
+        hdr[1] = part[1023];
+    }
+    __threadfence_system();
+}
+
+// Serving iteration end, part 2: the finished pairs' CIGAR elements, pair k at
+// dst[fin_off[k]..], for the pairs that fit dst_cap.
+__global__ void k_serve_gather(const uint32_t* fin_list, const uint32_t* fin_len,
+                               const genasm_result* out, const uint64_t* fin_off,
+                               const uint32_t* cigar, uint32_t* dst, uint64_t dst_cap,
+                               uint32_t max_fin) {
+    const uint32_t n = min(*fin_len, max_fin);
+    for (uint32_t k = blockIdx.x; k < n; k += gridDim.x) {
+        const genasm_result r = out[fin_list[k]];
+        const uint64_t o = fin_off[k];
+        if (o + r.cigar_len > dst_cap) continue;
+        for (uint32_t e = threadIdx.x; e < r.cigar_len; e += blockDim.x)
+            dst[o + e] = cigar[r.cigar_off + e];
+    }
 }
 
 // Longest-first order by a counting sort over length buckets: bucket 0 holds
@@ -1858,6 +2349,17 @@ hipError_t launch_unimproved(const AlignParams& p, unsigned long long* table, hi
     return hipGetLastError();
 }
 
+int search_blocks_per_cu(int group_lanes, int rows_per_lane) {
+    int n = 0;
+    const int lds = search_lds_bytes(group_lanes);
+    hipError_t e = hipErrorInvalidValue;
+    if (group_lanes == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<64, 1>, 64, lds);
+    else if (rows_per_lane == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<16, 1>, 64, lds);
+    else if (rows_per_lane == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<16, 2>, 64, lds);
+    else if (rows_per_lane == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<16, 4>, 64, lds);
+    return e == hipSuccess ? n : 0;
+}
+
 hipError_t launch_search(const AlignParams& p, int group_lanes, int rows_per_lane, int blocks,
                          hipStream_t s) {
     const int lds = search_lds_bytes(group_lanes);
@@ -1886,15 +2388,27 @@ hipError_t launch_search_finalize(const AlignParams& p, uint32_t max_pairs, hipS
     return hipGetLastError();
 }
 
+int compact_lds_bytes(int stride) { return 4 * compact_group_words(stride) * 8; }
+
 int windows_blocks_per_cu(const AlignParams& p) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_windows, 64,
-                                                     window_lds_bytes(p.lds_rows, p.stride)) != hipSuccess)
-        return 0;
-    return n;
+    hipError_t e;
+    if (p.compact)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_windows_c<false>, 64,
+                                                         compact_lds_bytes(p.stride));
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_windows, 64,
+                                                         window_lds_bytes(p.lds_rows, p.stride));
+    return e == hipSuccess ? n : 0;
 }
 
 hipError_t launch_windows(const AlignParams& p, int blocks, hipStream_t s) {
+    if (p.compact) {
+        const int lds = compact_lds_bytes(p.stride);
+        if (p.stats) hipLaunchKernelGGL(k_windows_c<true>, dim3(blocks), dim3(64), lds, s, p);
+        else hipLaunchKernelGGL(k_windows_c<false>, dim3(blocks), dim3(64), lds, s, p);
+        return hipGetLastError();
+    }
     const int lds = window_lds_bytes(p.lds_rows, p.stride);
     hipLaunchKernelGGL(k_windows, dim3(blocks), dim3(64), lds, s, p);
     return hipGetLastError();
@@ -1920,23 +2434,30 @@ hipError_t launch_init_counters(uint32_t* counters, uint32_t stage0_len, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_init_counters_dev(uint32_t* counters, const uint32_t* params, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_counters_dev, dim3(1), dim3(64), 0, s, counters, params);
+hipError_t launch_serve_begin(uint32_t* cur, uint32_t* next, uint32_t* fin_len,
+                              const uint32_t* params, const ServeAdmit* admit, ServeSlots slots,
+                              uint32_t* new_list, hipStream_t s) {
+    hipLaunchKernelGGL(k_serve_begin, dim3(1), dim3(256), 0, s, cur, next, fin_len, params, admit,
+                       slots, new_list);
     return hipGetLastError();
 }
 
-hipError_t launch_reset_states(PairState* state, const uint32_t* list, const uint32_t* params,
-                               uint32_t max_n, hipStream_t s) {
-    if (max_n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reset_states, dim3((max_n + 255) / 256), dim3(256), 0, s, state, list, params);
+hipError_t launch_serve_stamp(const uint32_t* params, unsigned long long* deadline, hipStream_t s) {
+    hipLaunchKernelGGL(k_serve_stamp, dim3(1), dim3(1), 0, s, params, deadline);
     return hipGetLastError();
 }
 
-hipError_t launch_gather_runs(const genasm_result* out, const uint32_t* list, uint32_t n,
-                              const uint64_t* dst_off, const uint32_t* cigar, uint32_t* dst,
-                              hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_runs, dim3(n), dim3(64), 0, s, out, list, n, dst_off, cigar, dst);
+hipError_t launch_serve_finish(const uint32_t* fin_list, const uint32_t* fin_len,
+                               const genasm_result* out, uint64_t* fin_off,
+                               unsigned long long* hdr, uint32_t* sum_slot,
+                               genasm_result* sum_res, const uint32_t* cigar, uint32_t* dst,
+                               uint64_t dst_cap, uint32_t max_fin, hipStream_t s) {
+    hipLaunchKernelGGL(k_serve_scan, dim3(1), dim3(1024), 0, s, fin_list, fin_len, out, fin_off,
+                       hdr, sum_slot, sum_res, max_fin);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_serve_gather, dim3(1024), dim3(256), 0, s, fin_list, fin_len, out, fin_off,
+                       cigar, dst, dst_cap, max_fin);
     return hipGetLastError();
 }
 

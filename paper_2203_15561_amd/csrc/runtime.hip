@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -14,6 +15,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "trace.h"
 
 using namespace genasm;
 
@@ -85,7 +87,10 @@ int ensure(genasm_ctx* ctx, char** buf, size_t* cap, size_t need) {
         *cap = 0;
     }
     size_t want = align_up(std::max(need, (size_t)1 << 20), (size_t)1 << 20);
-    hipError_t e = hipMalloc((void**)buf, want);
+    // failure injection for tests of the error path: GENASM_FAIL_ALLOC=1 makes
+    // every growth of a context buffer fail as if the device were full
+    const char* fail = std::getenv("GENASM_FAIL_ALLOC");
+    hipError_t e = fail && fail[0] == '1' ? hipErrorOutOfMemory : hipMalloc((void**)buf, want);
     if (e != hipSuccess) {
         *buf = nullptr;
         (void)hipGetLastError();
@@ -158,6 +163,10 @@ int resolve_launch(const genasm_launch* in, genasm_launch* out) {
     if (out->tb_prefetch != 0 && out->tb_prefetch != 1) return GENASM_E_INVAL;
     if (in->hard_share >= 0) out->hard_share = in->hard_share;
     if (out->hard_share > 100) return GENASM_E_INVAL;
+    if (in->table_bits) out->table_bits = in->table_bits;
+    if (out->table_bits != 32 && out->table_bits != 64) return GENASM_E_INVAL;
+    if (in->search_per_cu) out->search_per_cu = in->search_per_cu;
+    if (out->search_per_cu < 1 || out->search_per_cu > 32) return GENASM_E_INVAL;
     if (out->hard_lanes != 16 && out->hard_lanes != 32 && out->hard_lanes != 64)
         return GENASM_E_INVAL;
     if (out->group_lanes != 16 && out->group_lanes != 64) return GENASM_E_INVAL;
@@ -210,6 +219,8 @@ int genasm_default_launch(int32_t form, genasm_launch* out) {
     out->hard_lanes = 16;
     out->tb_prefetch = 0;
     out->hard_share = 50;
+    out->table_bits = 64;
+    out->search_per_cu = 8;
     return GENASM_OK;
 }
 
@@ -369,6 +380,7 @@ int align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_
               uint64_t total_read_bases, uint64_t total_ref_bases, int32_t k, int32_t W, int32_t O,
               genasm_result* d_out, uint32_t* d_cigar, uint64_t cigar_cap,
               const genasm_launch* launch, void* stream, bool noalloc) {
+    RoctxRange range(noalloc ? "genasm_batch_align_dev_noalloc" : "genasm_batch_align_dev");
     if (!ctx) return GENASM_E_INVAL;
     if (!valid_wko(k, W, O)) return set_err(ctx, GENASM_E_INVAL, "W must be in [2,64], O in [0,W-1], k >= 0");
     if (n_pairs == 0) return GENASM_OK;
@@ -399,6 +411,7 @@ int align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_
         if (cs != hipStreamCaptureStatusNone) ctx->pinned = true;
     }
     const bool profiling = ctx->profiling && !noalloc;
+    const bool counters = profiling && ctx->prof_counters;
 
     AlignParams p{};
     p.reads = d_reads2b;
@@ -444,12 +457,14 @@ int align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_
     if (noalloc && plane_bytes > (size_t)GENASM_NOALLOC_SCRATCH_BYTES) return too_big(plane_bytes);
 
     if (profiling) {
-        const size_t words = (size_t)n_pairs * kStatCount;
-        rc = ensure(ctx, &ctx->stats, &ctx->stats_cap, words * 8);
-        if (rc) return rc;
-        p.stats = reinterpret_cast<unsigned long long*>(ctx->stats);
-        CHECK_HIP(ctx, launch_fill_u64(p.stats, words, 0ull, s));
-        ctx->prof_pairs = n_pairs;
+        if (counters) {
+            const size_t words = (size_t)n_pairs * kStatCount;
+            rc = ensure(ctx, &ctx->stats, &ctx->stats_cap, words * 8);
+            if (rc) return rc;
+            p.stats = reinterpret_cast<unsigned long long*>(ctx->stats);
+            CHECK_HIP(ctx, launch_fill_u64(p.stats, words, 0ull, s));
+        }
+        ctx->prof_pairs = counters ? n_pairs : 0;
         ctx->prof_form = L.form;
         ctx->have_profile = true;
     }
@@ -495,13 +510,18 @@ int align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_
     p.tb_prefetch = L.tb_prefetch;
     p.hard_share = L.hard_share;
     p.route = 1;
-    const int search_blocks = ctx->num_cus * 8;
-    const int spill_rows = 64 - L.lds_rows;
+    // compact groups (32-bit table slices) when both queues run 16-lane groups
+    p.compact = L.table_bits == 32 && L.hard_lanes == 16 && L.group_lanes == 16;
+    const int SG = L.search_lanes;
+    // more resident search workgroups than 8 per CU make smaller chunks (each
+    // rescanning m1 + 64 columns past its end) and measured slower
+    const int search_blocks = ctx->num_cus * L.search_per_cu;
+    const int spill_rows = p.compact ? kCompactSpillRows : 64 - L.lds_rows;
     // Search chunks: at least kBatchSearchChunk columns, and large enough that
     // the batch makes about two items per search group, so that a long
     // reference splits only when the groups would otherwise sit idle.
     {
-        const uint64_t groups = (uint64_t)search_blocks * 4;
+        const uint64_t groups = (uint64_t)search_blocks * (64 / SG);
         const uint64_t want = (total_ref_bases + 2 * groups - 1) / (2 * groups);
         p.search_chunk = (uint32_t)std::min<uint64_t>(
             std::max<uint64_t>(kBatchSearchChunk, (want + 1023) / 1024 * 1024), 1u << 30);
@@ -564,7 +584,6 @@ int align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_
     // reads first when ordered), stage 0 with 16 rows, stages 1-2 with 32 and 64
     // rows for the items that found no hit, then each pair's outcome and queue.
     CHECK_HIP(ctx, mark(1));
-    const int SG = L.search_lanes;
     p.list_in = p.order;
     CHECK_HIP(ctx, launch_init_counters(p.counters, (uint32_t)n_pairs, s));
     p.items_out = items;
@@ -635,7 +654,8 @@ int genasm_autotune_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_
     // wavefront; 64: one) and its start-row threshold, table rows kept in LDS
     // per 16-lane group (the rest spill), and resident workers per CU.
     std::vector<genasm_launch> cands;
-    auto add = [&](int hard_row, int hard_lanes, int lds_rows, int workers, int search_lanes) {
+    auto add = [&](int hard_row, int hard_lanes, int lds_rows, int workers, int search_lanes,
+                   int table_bits) {
         genasm_launch c;
         genasm_default_launch(GENASM_FORM_BATCHED, &c);
         c.hard_row = hard_row;
@@ -643,15 +663,25 @@ int genasm_autotune_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_
         c.lds_rows = lds_rows;
         c.workers_per_cu = workers;
         c.search_lanes = search_lanes;
+        c.table_bits = table_bits;
         cands.push_back(c);
     };
-    for (int hr : {12, 16, 24, 65}) add(hr, 16, 16, 0, 16);
-    add(16, 64, 16, 0, 16);
-    for (int hr : {12, 16, 24}) add(hr, 32, 16, 0, 16);
-    add(-1, 64, 16, 0, 16);    // every pair one per wavefront
-    add(16, 16, 32, 0, 16);
-    add(16, 16, 16, 4, 16);
-    add(16, 16, 16, 0, 64);
+    // compact groups: the hard-queue threshold, resident workers, search lanes
+    for (int hr : {12, 16, 24, 65}) add(hr, 16, 16, 0, 16, 32);
+    add(16, 16, 16, 8, 16, 32);
+    add(16, 16, 16, 0, 64, 32);
+    for (int spc : {4, 16}) {
+        genasm_launch c;
+        genasm_default_launch(GENASM_FORM_BATCHED, &c);
+        c.search_per_cu = spc;
+        cands.push_back(c);
+    }
+    // 64-bit tables: LDS rows, lanes per hard pair and their threshold
+    add(16, 16, 16, 0, 16, 64);
+    add(16, 16, 32, 0, 16, 64);
+    add(16, 64, 16, 0, 16, 64);
+    for (int hr : {12, 16, 24}) add(hr, 32, 16, 0, 16, 64);
+    add(-1, 64, 16, 0, 16, 64);  // every pair one per wavefront
     {
         genasm_launch c;
         genasm_default_launch(GENASM_FORM_BATCHED, &c);
@@ -705,12 +735,13 @@ int genasm_tune_cache_save(genasm_ctx* ctx, const char* path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return set_err(ctx, GENASM_E_INVAL, "cannot open tune cache file for writing");
     std::fprintf(f, "# key form group_lanes search_lanes lds_rows workers_per_cu lpt_order hard_row "
-                    "hard_lanes tb_prefetch hard_share ms\n");
+                    "hard_lanes tb_prefetch hard_share table_bits search_per_cu ms\n");
     for (const auto& kv : ctx->tune) {
         const genasm_launch& L = kv.second.launch;
-        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %.4f\n", kv.first.c_str(), L.form,
+        std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d %.4f\n", kv.first.c_str(), L.form,
                      L.group_lanes, L.search_lanes, L.lds_rows, L.workers_per_cu, L.lpt_order,
-                     L.hard_row, L.hard_lanes, L.tb_prefetch, L.hard_share, kv.second.ms);
+                     L.hard_row, L.hard_lanes, L.tb_prefetch, L.hard_share, L.table_bits,
+                     L.search_per_cu, kv.second.ms);
     }
     const bool ok = std::fclose(f) == 0;
     return ok ? GENASM_OK : set_err(ctx, GENASM_E_INVAL, "writing the tune cache failed");
@@ -727,12 +758,13 @@ int genasm_tune_cache_load(genasm_ctx* ctx, const char* path) {
         char key[256];
         genasm_launch L{};
         float ms = 0.f;
-        const int got = std::sscanf(line, "%255s %d %d %d %d %d %d %d %d %d %d %f", key, &L.form,
-                                    &L.group_lanes, &L.search_lanes, &L.lds_rows,
+        const int got = std::sscanf(line, "%255s %d %d %d %d %d %d %d %d %d %d %d %d %f", key,
+                                    &L.form, &L.group_lanes, &L.search_lanes, &L.lds_rows,
                                     &L.workers_per_cu, &L.lpt_order, &L.hard_row, &L.hard_lanes,
-                                    &L.tb_prefetch, &L.hard_share, &ms);
+                                    &L.tb_prefetch, &L.hard_share, &L.table_bits,
+                                    &L.search_per_cu, &ms);
         genasm_launch chk;
-        if (got != 12 || resolve_launch(&L, &chk) != GENASM_OK) { rc = GENASM_E_INVAL; break; }
+        if (got != 14 || resolve_launch(&L, &chk) != GENASM_OK) { rc = GENASM_E_INVAL; break; }
         ctx->tune[key] = genasm_ctx::Tuned{L, ms};
     }
     std::fclose(f);
@@ -748,7 +780,9 @@ int genasm_profile_enable(genasm_ctx* ctx, int on) {
         for (hipEvent_t& e : ctx->ev)
             if (!e) CHECK_HIP(ctx, hipEventCreate(&e));
     }
+    if (on < 0 || on > 2) return set_err(ctx, GENASM_E_INVAL, "profiling level must be 0, 1 or 2");
     ctx->profiling = on != 0;
+    ctx->prof_counters = on == 1;
     return GENASM_OK;
 }
 
@@ -888,6 +922,7 @@ int genasm_batch_align(genasm_ctx* ctx, const char* reads, const uint64_t* read_
                        const char* refs, const uint64_t* ref_off, uint64_t n_pairs,
                        int32_t k, int32_t W, int32_t O, genasm_result* out, char* cigar_buf,
                        uint64_t cigar_cap, uint64_t* cigar_needed, const genasm_launch* launch) {
+    RoctxRange range("genasm_batch_align");
     if (!ctx) return GENASM_E_INVAL;
     if (!valid_wko(k, W, O)) return set_err(ctx, GENASM_E_INVAL, "W must be in [2,64], O in [0,W-1], k >= 0");
     if (!read_off || !ref_off || (!out && n_pairs) || !cigar_needed || (!cigar_buf && cigar_cap))

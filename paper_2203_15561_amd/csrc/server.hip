@@ -1,18 +1,29 @@
 // Serving form of the GenASM library: continuous batching of single-pair
 // requests with device-resident sequences and per-pair window state.
 //
-// The engine thread runs device iterations. Each iteration admits waiting
-// requests into free slots (bounded by the slot count, the base pool and the
-// CIGAR pool), uploads their packed bases with one copy and one scatter
-// kernel, then replays one captured graph:
+// An engine thread runs device iterations on one stream. An iteration admits
+// waiting requests into free slots (bounded by the slot count, the base pool
+// and the CIGAR pool), uploads their packed bases (one copy, two scatter
+// kernels), then runs one captured graph:
 //
-//   init counters -> reset state of new slots -> { search stages on the new
-//   slots } || { window kernel over the resident, already-searched slots,
-//   each advancing at most window_budget windows }
+//   begin (counters; slot tables and fresh state of the admitted pairs)
+//   -> start search of the admitted pairs -> window kernel -> finish
 //
-// and finally returns the pairs that finished to the completion queue. A pair
-// admitted in iteration t is searched in t and starts its windows in t+1, so a
-// long start search never delays the window work of the pairs in flight.
+// The window kernel takes the resident pairs from two device lists: the pairs
+// admitted now and those whose previous turn was cut after one window first,
+// then the others. Every pair advances at least one window, and more until it
+// ends or the iteration's window time has passed; the kernel itself puts each
+// pair on the
+// next iteration's lists or on the finished list, so the host never copies or
+// scans per-slot state. The finish kernels write the finished pairs' slots and
+// results into host-mapped memory and gather their CIGAR elements into one
+// device buffer, which the host copies on a second stream.
+//
+// Two iterations can be in flight: while the device runs iteration t, the
+// engine collects the output of t-1 and, when requests wait or the device is
+// saturated, queues t+1 behind t. Buffers that the host writes or reads while
+// an iteration runs exist twice, once per iteration parity, and so do the two
+// captured graphs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,9 +38,11 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
+#include "trace.h"
 
 using namespace genasm;
 
@@ -41,49 +54,65 @@ uint64_t steady_ns() {
         .count();
 }
 
-// First-fit allocator of [0, cap) in abstract units.
+// Best-fit allocator of [0, cap) in abstract units: free ranges indexed by
+// start (for merging neighbours) and by length (for the smallest range that
+// fits), so that every operation is logarithmic in the number of free ranges.
 class RangeAlloc {
   public:
     void reset(uint64_t cap) {
-        free_.clear();
-        if (cap) free_[0] = cap;
+        by_start_.clear();
+        by_len_.clear();
+        if (cap) insert(0, cap);
         used_ = 0;
     }
     bool alloc(uint64_t len, uint64_t* start) {
         if (len == 0) { *start = 0; return true; }
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= len) {
-                *start = it->first;
-                const uint64_t rest = it->second - len, s2 = it->first + len;
-                free_.erase(it);
-                if (rest) free_[s2] = rest;
-                used_ += len;
-                return true;
-            }
-        }
-        return false;
+        auto it = by_len_.lower_bound(len);
+        if (it == by_len_.end()) return false;
+        const uint64_t s0 = it->second, have = it->first;
+        erase(s0, have);
+        if (have > len) insert(s0 + len, have - len);
+        *start = s0;
+        used_ += len;
+        return true;
     }
     void release(uint64_t start, uint64_t len) {
         if (len == 0) return;
         used_ -= len;
-        auto it = free_.emplace(start, len).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
+        uint64_t s0 = start, l0 = len;
+        auto nx = by_start_.lower_bound(start);
+        if (nx != by_start_.end() && s0 + l0 == nx->first) {
+            const uint64_t ns = nx->first, nl = nx->second;
+            erase(ns, nl);
+            l0 += nl;
         }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
+        auto pv = by_start_.lower_bound(start);
+        if (pv != by_start_.begin()) {
+            --pv;
+            if (pv->first + pv->second == s0) {
+                const uint64_t ps = pv->first, pl = pv->second;
+                erase(ps, pl);
+                s0 = ps;
+                l0 += pl;
             }
         }
+        insert(s0, l0);
     }
     uint64_t used() const { return used_; }
 
   private:
-    std::map<uint64_t, uint64_t> free_;
+    void insert(uint64_t s0, uint64_t len) {
+        by_start_[s0] = len;
+        by_len_.emplace(len, s0);
+    }
+    void erase(uint64_t s0, uint64_t len) {
+        by_start_.erase(s0);
+        auto r = by_len_.equal_range(len);
+        for (auto it = r.first; it != r.second; ++it)
+            if (it->second == s0) { by_len_.erase(it); break; }
+    }
+    std::map<uint64_t, uint64_t> by_start_;
+    std::multimap<uint64_t, uint64_t> by_len_;
     uint64_t used_ = 0;
 };
 
@@ -91,48 +120,75 @@ constexpr uint64_t kBaseUnit = 64;  // pool allocations in bases: whole bit-plan
 
 uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+// A queued request: the read's packed bytes, then the reference's.
 struct Request {
-    std::vector<uint8_t> read2b, ref2b;
+    std::vector<uint8_t> bytes;
     uint32_t m = 0, n = 0;
     uint64_t tag = 0, submit_ns = 0;
 };
 
 struct Slot {
-    bool busy = false;
     uint64_t tag = 0, submit_ns = 0, admit_ns = 0;
     uint64_t rstart = 0, rlen = 0, fstart = 0, flen = 0;  // pool ranges (bases)
     uint64_t cstart = 0, clen = 0;                        // CIGAR pool range (elements)
 };
 
 template <class T>
-T* host_alloc(size_t n) {
+T* host_alloc(size_t n, unsigned flags = hipHostMallocDefault) {
     void* p = nullptr;
-    if (hipHostMalloc(&p, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault) != hipSuccess)
-        return nullptr;
+    if (hipHostMalloc(&p, std::max<size_t>(n, 1) * sizeof(T), flags) != hipSuccess) return nullptr;
     return static_cast<T*>(p);
 }
 
 template <class T>
 T* dev_alloc(size_t n) {
+    // failure injection for tests of the error path (see runtime.hip)
+    const char* fail = std::getenv("GENASM_FAIL_ALLOC");
+    if (fail && fail[0] == '1') return nullptr;
     void* p = nullptr;
     if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
     return static_cast<T*>(p);
 }
+
+// Buffers of one iteration parity.
+struct IterBufs {
+    // upload staging (pinned host) and its device copy
+    uint8_t *h_upload = nullptr, *d_upload = nullptr;
+    uint64_t *h_up_src = nullptr, *h_up_dst = nullptr, *h_up_word = nullptr;
+    uint64_t *d_up_src = nullptr, *d_up_dst = nullptr, *d_up_word = nullptr;
+    uint32_t *h_up_len = nullptr, *h_up_bases = nullptr, *d_up_len = nullptr, *d_up_bases = nullptr;
+    ServeAdmit *h_admit = nullptr, *d_admit = nullptr;
+    uint32_t *h_params = nullptr, *d_params = nullptr;
+    // window lists read by this parity's iterations (hot: advanced no window
+    // last time, or admitted now; cold: the rest) and its counters block
+    uint32_t *d_hot = nullptr, *d_cold = nullptr, *d_cnt = nullptr;
+    // finished-pair summary, written by the device into host-mapped memory
+    unsigned long long* h_hdr = nullptr;
+    uint32_t* h_slot = nullptr;
+    genasm_result* h_res = nullptr;
+    unsigned long long* dh_hdr = nullptr;
+    uint32_t* dh_slot = nullptr;
+    genasm_result* dh_res = nullptr;
+    // gathered CIGAR elements of the finished pairs
+    uint32_t *d_gather = nullptr, *h_gather = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev_start = nullptr, ev_done = nullptr;
+    uint32_t n_new = 0;
+};
 
 }  // namespace
 
 struct genasm_server {
     genasm_ctx* ctx = nullptr;
     genasm_server_config cfg{};
-    AlignParams P{};      // window kernel parameters (fixed pointers)
-    AlignParams S{};      // search parameters
+    AlignParams base{};   // fields common to every iteration's kernels
     int search_blocks = 0, win_blocks = 0;
-    hipStream_t s = nullptr, s2 = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    uint32_t groups = 0;  // 16-lane window groups of the persistent grid
+    hipStream_t s = nullptr, s_copy = nullptr;
+    uint64_t gather_cap = 0;  // elements per gather buffer
 
-    // device
+    // device state shared by both parities
     uint8_t* d_pool = nullptr;                 // 2-bit packed bases (start search)
     unsigned long long *d_plo = nullptr, *d_phi = nullptr;  // the same bases as bit planes (windows)
     uint32_t* d_cigar = nullptr;
@@ -141,42 +197,30 @@ struct genasm_server {
     genasm_result* d_out = nullptr;
     PairState* d_state = nullptr;
     SearchOut* d_search = nullptr;
-    uint32_t *d_counters = nullptr, *d_new = nullptr, *d_active = nullptr, *d_params = nullptr;
-    uint64_t* d_items = nullptr;          // two start-search item lists
-    unsigned long long* d_key = nullptr;  // per-slot search key
+    uint32_t* d_new = nullptr;               // slots admitted in the running iteration
+    uint32_t *d_fin = nullptr, *d_fin_len = nullptr;
+    uint64_t* d_fin_off = nullptr;
+    uint64_t* d_items = nullptr;             // two start-search item lists
+    unsigned long long* d_key = nullptr;     // per-slot search key
+    unsigned long long* d_deadline = nullptr;
     uint64_t item_cap = 0;
     unsigned long long* d_spill = nullptr;
-    uint8_t* d_upload = nullptr;
-    uint64_t *d_up_src = nullptr, *d_up_dst = nullptr, *d_up_word = nullptr;
-    uint32_t *d_up_len = nullptr, *d_up_bases = nullptr;
-    uint32_t* d_gather_list = nullptr;
-    uint64_t* d_gather_off = nullptr;
-    uint32_t* d_gather = nullptr;
-    uint64_t upload_cap = 0, gather_cap = 0;
+    uint64_t upload_cap = 0;
+    IterBufs it[2];
 
-    // pinned host mirrors
-    uint64_t *h_read_off = nullptr, *h_ref_off = nullptr, *h_run_base = nullptr;
-    uint32_t *h_read_len = nullptr, *h_ref_len = nullptr;
-    uint32_t *h_new = nullptr, *h_active = nullptr, *h_params = nullptr;
-    uint8_t* h_upload = nullptr;
-    uint64_t *h_up_src = nullptr, *h_up_dst = nullptr, *h_up_word = nullptr;
-    uint32_t *h_up_len = nullptr, *h_up_bases = nullptr;
-    PairState* h_state = nullptr;
-    genasm_result* h_out = nullptr;
-    SearchOut* h_search = nullptr;
-    uint32_t* h_gather_list = nullptr;
-    uint64_t* h_gather_off = nullptr;
-    uint32_t* h_gather = nullptr;
+    // engine-thread state
+    std::vector<Slot> slots;
+    std::vector<uint32_t> free_slots;
+    uint32_t resident = 0;
+    RangeAlloc pool, cigpool;
 
-    // host state
+    // shared state (mu)
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request> pending;
     std::deque<genasm_completion> done;
-    std::vector<Slot> slots;
-    std::vector<uint32_t> free_slots;
-    std::vector<uint32_t> searched;  // resident, start search finished
-    RangeAlloc pool, cigpool;
+    std::unordered_multimap<uint64_t, uint32_t> tag_slot;  // resident requests by tag
+    std::vector<uint8_t> slot_cancelled;                    // resident request cancelled
     std::thread engine;
     bool stop = false;
     int error = GENASM_OK;
@@ -200,36 +244,55 @@ int srv_fail(genasm_server* srv, const char* what, hipError_t e) {
         if (e_ != hipSuccess) return srv_fail(srv, #expr, e_);      \
     } while (0)
 
-// The device work of one iteration: forked into the search chain (stream s)
-// and the window kernel (stream s2). Used for graph capture and direct launch.
-hipError_t enqueue_iteration(genasm_server* srv) {
+// The device work of one iteration of parity q (graph capture or direct launch).
+hipError_t enqueue_iteration(genasm_server* srv, int q) {
     hipError_t e;
-    const uint32_t n_slots = srv->cfg.max_slots;
-    if ((e = launch_init_counters_dev(srv->d_counters, srv->d_params, srv->s))) return e;
-    if ((e = launch_reset_states(srv->d_state, srv->d_new, srv->d_params, n_slots, srv->s))) return e;
-    if ((e = hipEventRecord(srv->ev_fork, srv->s))) return e;
-    if ((e = hipStreamWaitEvent(srv->s2, srv->ev_fork, 0))) return e;
-    if ((e = launch_windows(srv->P, srv->win_blocks, srv->s2))) return e;
-    if ((e = hipEventRecord(srv->ev_join, srv->s2))) return e;
-    AlignParams S = srv->S;
-    const uint64_t cap = srv->item_cap;
+    IterBufs& b = srv->it[q];
+    IterBufs& nb = srv->it[1 - q];
+    const uint32_t NS = srv->cfg.max_slots;
+    hipStream_t s = srv->s;
+    ServeSlots slots{srv->d_read_off, srv->d_ref_off, srv->d_run_base,
+                     srv->d_read_len, srv->d_ref_len, srv->d_state};
+    if ((e = launch_serve_begin(b.d_cnt, nb.d_cnt, srv->d_fin_len, b.d_params, b.d_admit, slots,
+                                srv->d_new, s)))
+        return e;
+    // start search of the admitted pairs; those with a hit join this
+    // iteration's hot list, those that end here the finished list
+    AlignParams S = srv->base;
+    S.counters = b.d_cnt;
+    S.easy_list = b.d_hot;
+    S.hard_list = b.d_cold;
     S.list_in = srv->d_new;
     S.items_out = srv->d_items;
-    if ((e = launch_search_items(S, n_slots, srv->s))) return e;
+    if ((e = launch_search_items(S, NS, s))) return e;
+    const uint64_t cap = srv->item_cap;
     S.list_slot = 0;
     S.items_in = srv->d_items;
     S.items_out = srv->d_items + cap;
-    if ((e = launch_search(S, 16, 1, srv->search_blocks, srv->s))) return e;
+    if ((e = launch_search(S, 16, 1, srv->search_blocks, s))) return e;
     S.items_in = srv->d_items + cap;
     S.items_out = srv->d_items;
     S.list_slot = 1;
-    if ((e = launch_search(S, 16, 2, srv->search_blocks, srv->s))) return e;
+    if ((e = launch_search(S, 16, 2, srv->search_blocks, s))) return e;
     S.items_in = srv->d_items;
     S.items_out = srv->d_items + cap;
     S.list_slot = 2;
-    if ((e = launch_search(S, 16, 4, srv->search_blocks, srv->s))) return e;
-    if ((e = launch_search_finalize(S, n_slots, srv->s))) return e;
-    return hipStreamWaitEvent(srv->s, srv->ev_join, 0);
+    if ((e = launch_search(S, 16, 4, srv->search_blocks, s))) return e;
+    if ((e = launch_search_finalize(S, NS, s))) return e;
+    // windows until the iteration's deadline
+    if ((e = launch_serve_stamp(b.d_params, srv->d_deadline, s))) return e;
+    AlignParams P = srv->base;
+    P.counters = b.d_cnt;
+    P.easy_list = b.d_hot;
+    P.hard_list = b.d_cold;
+    P.deadline = srv->d_deadline;
+    P.next_hot = nb.d_hot;
+    P.next_cold = nb.d_cold;
+    P.next_len = nb.d_cnt;
+    if ((e = launch_windows(P, srv->win_blocks, s))) return e;
+    return launch_serve_finish(srv->d_fin, srv->d_fin_len, srv->d_out, srv->d_fin_off, b.dh_hdr,
+                               b.dh_slot, b.dh_res, srv->d_cigar, b.d_gather, srv->gather_cap, NS,
+                               s);
 }
 
 void engine_main(genasm_server* srv);
@@ -246,11 +309,12 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     *out = nullptr;
     genasm_server_config cfg = *cfg_in;
     if (cfg.W < 2 || cfg.W > 64 || cfg.O < 0 || cfg.O >= cfg.W || cfg.k < 0) return GENASM_E_INVAL;
-    if (cfg.max_slots == 0) cfg.max_slots = 8192;
-    if (cfg.pool_bases == 0) cfg.pool_bases = 1ull << 28;
+    if (cfg.max_slots == 0) cfg.max_slots = 32768;
+    if (cfg.pool_bases == 0) cfg.pool_bases = 1ull << 29;
     if (cfg.max_pending == 0) cfg.max_pending = 65536;
-    if (cfg.window_budget == 0) cfg.window_budget = 32;
     if (cfg.use_graph < 0 || cfg.use_graph > 1) cfg.use_graph = 1;
+    if (cfg.iteration_us < 0 || cfg.iteration_us > 1000000) return GENASM_E_INVAL;
+    if (cfg.cigar_runs < 0 || cfg.cigar_runs > 1) return GENASM_E_INVAL;
     if (cfg.max_slots > (1u << 24) || cfg.pool_bases > (1ull << 40)) return GENASM_E_INVAL;
     genasm_server* srv = new (std::nothrow) genasm_server();
     if (!srv) return GENASM_E_NOMEM;
@@ -261,15 +325,19 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     const uint64_t pool_bytes = cfg.pool_bases / 4;
     const int L = cfg.W - cfg.O, stride = L + 2;
     const int lds_rows = 16;
-    // window workgroups per CU: one fewer than fit, leaving room for the start
-    // search of newly admitted pairs, which runs beside the window kernel
+    // window workgroups per CU: as many as stay resident together (the search
+    // runs before the window kernel, not beside it)
     AlignParams occ{};
     occ.lds_rows = lds_rows;
     occ.stride = stride;
-    const int per_cu = std::max(1, std::min(16, windows_blocks_per_cu(occ)) - 1);
+    occ.compact = 1;
+    const int per_cu = std::max(1, std::min(16, windows_blocks_per_cu(occ)));
     srv->win_blocks = ctx->num_cus * per_cu;
+    srv->groups = (uint32_t)srv->win_blocks * 4;
     srv->search_blocks = ctx->num_cus * 8;
     const uint64_t workers = (uint64_t)srv->win_blocks * 4;
+    srv->upload_cap = 1ull << 24;
+    srv->gather_cap = std::min<uint64_t>(cfg.pool_bases, 1ull << 23);
 
     bool ok = true;
     auto D = [&](auto*& p, size_t n) {
@@ -282,8 +350,14 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
         p = host_alloc<T>(n);
         ok = ok && p;
     };
-    srv->upload_cap = 1ull << 24;
-    srv->gather_cap = 1ull << 22;
+    // host memory the device writes: mapped, and its device address
+    auto M = [&](auto*& h, auto*& d, size_t n) {
+        using T = std::remove_reference_t<decltype(*h)>;
+        h = host_alloc<T>(n, hipHostMallocMapped | hipHostMallocCoherent);
+        void* dp = nullptr;
+        ok = ok && h && hipHostGetDevicePointer(&dp, h, 0) == hipSuccess;
+        d = static_cast<T*>(dp);
+    };
     D(srv->d_pool, pool_bytes + 16);
     D(srv->d_plo, plane_words(cfg.pool_bases));
     D(srv->d_phi, plane_words(cfg.pool_bases));
@@ -291,41 +365,39 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     D(srv->d_read_off, NS); D(srv->d_ref_off, NS); D(srv->d_run_base, NS);
     D(srv->d_read_len, NS); D(srv->d_ref_len, NS);
     D(srv->d_out, NS); D(srv->d_state, NS); D(srv->d_search, NS);
+    D(srv->d_new, NS); D(srv->d_fin, NS); D(srv->d_fin_len, 4); D(srv->d_fin_off, NS);
     srv->item_cap = search_item_cap(NS, cfg.pool_bases, kServeSearchChunk);
-    D(srv->d_counters, kCounterCount); D(srv->d_items, 2 * srv->item_cap); D(srv->d_key, NS);
-    D(srv->d_new, NS); D(srv->d_active, NS); D(srv->d_params, 4);
-    D(srv->d_spill, spill_words(workers, 64 - lds_rows, stride));
-    D(srv->d_upload, srv->upload_cap);
-    D(srv->d_up_src, 2 * (size_t)NS); D(srv->d_up_dst, 2 * (size_t)NS); D(srv->d_up_len, 2 * (size_t)NS);
-    D(srv->d_up_word, 2 * (size_t)NS); D(srv->d_up_bases, 2 * (size_t)NS);
-    D(srv->d_gather_list, NS); D(srv->d_gather_off, NS); D(srv->d_gather, srv->gather_cap);
-    H(srv->h_read_off, NS); H(srv->h_ref_off, NS); H(srv->h_run_base, NS);
-    H(srv->h_read_len, NS); H(srv->h_ref_len, NS);
-    H(srv->h_new, NS); H(srv->h_active, NS); H(srv->h_params, 4);
-    H(srv->h_upload, srv->upload_cap);
-    H(srv->h_up_src, 2 * (size_t)NS); H(srv->h_up_dst, 2 * (size_t)NS); H(srv->h_up_len, 2 * (size_t)NS);
-    H(srv->h_up_word, 2 * (size_t)NS); H(srv->h_up_bases, 2 * (size_t)NS);
-    H(srv->h_state, NS); H(srv->h_out, NS); H(srv->h_search, NS);
-    H(srv->h_gather_list, NS); H(srv->h_gather_off, NS); H(srv->h_gather, srv->gather_cap);
+    D(srv->d_items, 2 * srv->item_cap); D(srv->d_key, NS); D(srv->d_deadline, 1);
+    D(srv->d_spill, spill_words(workers, kCompactSpillRows, stride));
+    for (IterBufs& b : srv->it) {
+        H(b.h_upload, srv->upload_cap); D(b.d_upload, srv->upload_cap);
+        H(b.h_up_src, 2 * (size_t)NS); H(b.h_up_dst, 2 * (size_t)NS); H(b.h_up_word, 2 * (size_t)NS);
+        H(b.h_up_len, 2 * (size_t)NS); H(b.h_up_bases, 2 * (size_t)NS);
+        D(b.d_up_src, 2 * (size_t)NS); D(b.d_up_dst, 2 * (size_t)NS); D(b.d_up_word, 2 * (size_t)NS);
+        D(b.d_up_len, 2 * (size_t)NS); D(b.d_up_bases, 2 * (size_t)NS);
+        H(b.h_admit, NS); D(b.d_admit, NS);
+        H(b.h_params, kServeParamWords); D(b.d_params, kServeParamWords);
+        D(b.d_hot, NS); D(b.d_cold, NS); D(b.d_cnt, kCounterCount);
+        M(b.h_hdr, b.dh_hdr, 2); M(b.h_slot, b.dh_slot, NS); M(b.h_res, b.dh_res, NS);
+        D(b.d_gather, srv->gather_cap); H(b.h_gather, srv->gather_cap);
+        ok = ok && hipEventCreate(&b.ev_start) == hipSuccess;
+        ok = ok && hipEventCreate(&b.ev_done) == hipSuccess;
+    }
     ok = ok && hipStreamCreateWithFlags(&srv->s, hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipStreamCreateWithFlags(&srv->s2, hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&srv->ev_fork, hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&srv->ev_join, hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipEventCreate(&srv->ev_t0) == hipSuccess;
-    ok = ok && hipEventCreate(&srv->ev_t1) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&srv->s_copy, hipStreamNonBlocking) == hipSuccess;
+    if (ok) {
+        // both counters blocks start empty (no resident pairs)
+        for (IterBufs& b : srv->it)
+            ok = ok && hipMemsetAsync(b.d_cnt, 0, kCounterCount * sizeof(uint32_t), srv->s) == hipSuccess;
+        ok = ok && hipStreamSynchronize(srv->s) == hipSuccess;
+    }
     if (!ok) {
         (void)hipGetLastError();
         genasm_server_destroy(srv);
         return GENASM_E_NOMEM;
     }
-    std::memset(srv->h_params, 0, 4 * sizeof(uint32_t));
-    std::memset(srv->h_read_len, 0, NS * sizeof(uint32_t));
-    std::memset(srv->h_ref_len, 0, NS * sizeof(uint32_t));
-    std::memset(srv->h_read_off, 0, NS * sizeof(uint64_t));
-    std::memset(srv->h_ref_off, 0, NS * sizeof(uint64_t));
-    std::memset(srv->h_run_base, 0, NS * sizeof(uint64_t));
 
-    AlignParams p{};
+    AlignParams& p = srv->base;
     p.reads = srv->d_pool;
     p.refs = srv->d_pool;
     p.read_lo = srv->d_plo;
@@ -347,53 +419,92 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     p.cigar = srv->d_cigar;
     p.cigar_cap = cfg.pool_bases;
     p.search = srv->d_search;
-    p.counters = srv->d_counters;
     p.spill = srv->d_spill;
     p.lds_rows = lds_rows;
-    p.hard_row = 65;
+    p.compact = 1;       // compact 16-lane window groups
+    p.hard_row = 65;     // the search routes every pair with a hit to the hot list
     p.hard_lanes = 16;
-    p.hard_share = 100;
-    p.route = 0;
+    p.hard_share = 0;    // every worker drains the hot list before the cold one
+    p.route = 1;
     p.state = srv->d_state;
     p.window_budget = cfg.window_budget;
     p.search_key = srv->d_key;
     p.search_chunk = kServeSearchChunk;
-    p.easy_list = srv->d_active;
-    p.hard_list = srv->d_active;  // never used: the hard queue is empty
-    srv->S = p;
-    srv->P = p;
+    p.fin_list = srv->d_fin;
+    p.fin_len = srv->d_fin_len;
 
     if (cfg.use_graph) {
-        hipError_t e = hipStreamBeginCapture(srv->s, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            hipError_t e2 = enqueue_iteration(srv);
-            e = hipStreamEndCapture(srv->s, &srv->graph);
-            if (e2 != hipSuccess) e = e2;
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&srv->graph_exec, srv->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            genasm_server_destroy(srv);
-            return GENASM_E_DEVICE;
+        for (int q = 0; q < 2; ++q) {
+            IterBufs& b = srv->it[q];
+            hipError_t e = hipStreamBeginCapture(srv->s, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t e2 = enqueue_iteration(srv, q);
+                e = hipStreamEndCapture(srv->s, &b.graph);
+                if (e2 != hipSuccess) e = e2;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                genasm_server_destroy(srv);
+                return GENASM_E_DEVICE;
+            }
         }
     }
     srv->pool.reset(cfg.pool_bases);
     srv->cigpool.reset(cfg.pool_bases);
     srv->slots.resize(NS);
+    srv->slot_cancelled.assign(NS, 0);
     for (uint32_t i = NS; i-- > 0;) srv->free_slots.push_back(i);
     srv->engine = std::thread(engine_main, srv);
     *out = srv;
     return GENASM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Checks one request's sizes against the server's pools.
+int check_request(const genasm_server* srv, uint64_t m, uint64_t n) {
+    const uint64_t need = round_up(m, kBaseUnit) + round_up(n, kBaseUnit);
+    if (m > 0x7fffffffull || n > 0x7fffffffull || need > srv->cfg.pool_bases ||
+        (m + 3) / 4 + (n + 3) / 4 > srv->upload_cap || m + n + 1 > srv->cfg.pool_bases)
+        return GENASM_E_TOOLONG;
+    return GENASM_OK;
+}
+
+// Copies `nb` 2-bit bases starting at base `b0` of a packed stream to dst,
+// starting at bit 0 of dst[0].
+void copy_bases(uint8_t* dst, const uint8_t* src, uint64_t b0, uint64_t nb) {
+    const uint64_t bytes = (nb + 3) / 4;
+    const uint8_t* s = src + b0 / 4;
+    const unsigned sh = (unsigned)(b0 % 4) * 2;
+    if (sh == 0) {
+        std::memcpy(dst, s, bytes);
+    } else {
+        // the last byte's high part may read one byte past the range's end;
+        // take it only when the range extends into that byte
+        const uint64_t last = (b0 + nb + 3) / 4 - b0 / 4;  // source bytes the bases touch
+        for (uint64_t j = 0; j < bytes; ++j) {
+            const unsigned lo = s[j] >> sh;
+            const unsigned hi = j + 1 < last ? (unsigned)s[j + 1] << (8 - sh) : 0u;
+            dst[j] = (uint8_t)(lo | hi);
+        }
+    }
+    // bases past nb in the last byte are zero
+    if (nb % 4) dst[bytes - 1] &= (uint8_t)((1u << (2 * (nb % 4))) - 1);
+}
+
+}  // namespace
+
+extern "C" {
+
 int genasm_submit(genasm_server* srv, const char* read, uint64_t m, const char* ref, uint64_t n,
                   int32_t k, int32_t W, int32_t O, uint64_t tag) {
     if (!srv || (!read && m) || (!ref && n)) return GENASM_E_INVAL;
     if (k != srv->cfg.k || W != srv->cfg.W || O != srv->cfg.O) return GENASM_E_INVAL;
-    const uint64_t need = round_up(m, kBaseUnit) + round_up(n, kBaseUnit);
-    if (m > 0x7fffffffull || n > 0x7fffffffull || need > srv->cfg.pool_bases ||
-        need / 4 > srv->upload_cap || m + n + 1 > srv->cfg.pool_bases)
-        return GENASM_E_TOOLONG;
+    int rc = check_request(srv, m, n);
+    if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         if (srv->error) return srv->error;
@@ -403,10 +514,10 @@ int genasm_submit(genasm_server* srv, const char* read, uint64_t m, const char* 
         }
     }
     Request r;
-    r.read2b.resize((m + 3) / 4);
-    r.ref2b.resize((n + 3) / 4);
-    if (genasm_pack(read, m, r.read2b.data(), nullptr) != GENASM_OK ||
-        genasm_pack(ref, n, r.ref2b.data(), nullptr) != GENASM_OK)
+    const uint64_t rb = (m + 3) / 4;
+    r.bytes.resize(rb + (n + 3) / 4);
+    if (genasm_pack(read, m, r.bytes.data(), nullptr) != GENASM_OK ||
+        genasm_pack(ref, n, r.bytes.data() + rb, nullptr) != GENASM_OK)
         return GENASM_E_ALPHABET;
     r.m = (uint32_t)m;
     r.n = (uint32_t)n;
@@ -423,19 +534,136 @@ int genasm_submit(genasm_server* srv, const char* read, uint64_t m, const char* 
     return GENASM_OK;
 }
 
+int genasm_submit_batch(genasm_server* srv, const uint8_t* reads2b, const uint64_t* read_off,
+                        const uint8_t* refs2b, const uint64_t* ref_off, uint64_t n_req,
+                        int32_t k, int32_t W, int32_t O, const uint64_t* tags,
+                        uint64_t* accepted) {
+    if (!srv || !accepted) return GENASM_E_INVAL;
+    *accepted = 0;
+    if (n_req == 0) return GENASM_OK;
+    if (!read_off || !ref_off || !tags) return GENASM_E_INVAL;
+    if (k != srv->cfg.k || W != srv->cfg.W || O != srv->cfg.O) return GENASM_E_INVAL;
+    for (uint64_t i = 0; i < n_req; ++i) {
+        if (read_off[i + 1] < read_off[i] || ref_off[i + 1] < ref_off[i]) return GENASM_E_INVAL;
+        int rc = check_request(srv, read_off[i + 1] - read_off[i], ref_off[i + 1] - ref_off[i]);
+        if (rc) return rc;
+    }
+    if ((!reads2b && read_off[n_req] > read_off[0]) || (!refs2b && ref_off[n_req] > ref_off[0]))
+        return GENASM_E_INVAL;
+    uint64_t room;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->error) return srv->error;
+        room = srv->cfg.max_pending - std::min<uint64_t>(srv->pending.size(), srv->cfg.max_pending);
+    }
+    const uint64_t take = std::min(room, n_req);
+    std::vector<Request> reqs(take);
+    const uint64_t now = steady_ns();
+    for (uint64_t i = 0; i < take; ++i) {
+        Request& r = reqs[i];
+        const uint64_t m = read_off[i + 1] - read_off[i], n = ref_off[i + 1] - ref_off[i];
+        const uint64_t rb = (m + 3) / 4;
+        r.bytes.resize(rb + (n + 3) / 4);
+        if (m) copy_bases(r.bytes.data(), reads2b, read_off[i], m);
+        if (n) copy_bases(r.bytes.data() + rb, refs2b, ref_off[i], n);
+        r.m = (uint32_t)m;
+        r.n = (uint32_t)n;
+        r.tag = tags[i];
+        r.submit_ns = now;
+    }
+    std::lock_guard<std::mutex> lk(srv->mu);
+    for (Request& r : reqs) srv->pending.push_back(std::move(r));
+    srv->st.submitted += take;
+    *accepted = take;
+    if (take < n_req) srv->st.refused += n_req - take;
+    srv->cv_work.notify_one();
+    return take < n_req ? GENASM_E_BUSY : GENASM_OK;
+}
+
 int genasm_poll(genasm_server* srv, genasm_completion* out, int max, int timeout_ms) {
     if (!srv || (!out && max > 0) || max < 0) return GENASM_E_INVAL;
-    std::unique_lock<std::mutex> lk(srv->mu);
-    if (srv->done.empty() && timeout_ms > 0 && !srv->error)
-        srv->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
-                              [&] { return !srv->done.empty() || srv->error; });
     int k = 0;
-    while (k < max && !srv->done.empty()) {
-        out[k++] = srv->done.front();
-        srv->done.pop_front();
+    {
+        std::unique_lock<std::mutex> lk(srv->mu);
+        if (srv->done.empty() && timeout_ms > 0 && !srv->error)
+            srv->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
+                                  [&] { return !srv->done.empty() || srv->error; });
+        while (k < max && !srv->done.empty()) {
+            out[k++] = srv->done.front();
+            srv->done.pop_front();
+        }
+        if (k == 0 && srv->error) return srv->error;
     }
-    if (k == 0 && srv->error) return srv->error;
+    if (!srv->cfg.cigar_runs) {
+        // text CIGARs, formatted here in the caller's thread
+        static const char kOp[4] = {'=', 'X', 'I', 'D'};
+        for (int i = 0; i < k; ++i) {
+            genasm_completion& c = out[i];
+            const uint32_t* el = reinterpret_cast<const uint32_t*>(c.cigar);
+            const uint32_t ne = c.result.cigar_len;
+            char* text = static_cast<char*>(std::malloc((size_t)ne * 11 + 1));
+            char* w = text;
+            if (text) {
+                for (uint32_t e = 0; e < ne; ++e) {
+                    char tmp[12];
+                    int d = 0;
+                    uint32_t len = GENASM_CIGAR_LEN(el[e]);
+                    do { tmp[d++] = (char)('0' + len % 10); len /= 10; } while (len);
+                    while (d) *w++ = tmp[--d];
+                    *w++ = kOp[GENASM_CIGAR_OP(el[e])];
+                }
+                *w = '\0';
+            }
+            std::free(c.cigar);
+            c.cigar = text;
+            c.result.cigar_len = text ? (uint32_t)(w - text) : 0u;
+        }
+    }
     return k;
+}
+
+int genasm_poll_batch(genasm_server* srv, genasm_completion_info* out, int max, uint32_t* runs,
+                      uint64_t runs_cap, uint64_t* runs_used, int timeout_ms) {
+    if (!srv || !runs_used || max < 0 || (!out && max > 0) || (!runs && runs_cap)) return GENASM_E_INVAL;
+    *runs_used = 0;
+    std::vector<genasm_completion> got;
+    {
+        std::unique_lock<std::mutex> lk(srv->mu);
+        if (srv->done.empty() && timeout_ms > 0 && !srv->error)
+            srv->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
+                                  [&] { return !srv->done.empty() || srv->error; });
+        uint64_t used = 0;
+        while ((int)got.size() < max && !srv->done.empty()) {
+            const genasm_completion& c = srv->done.front();
+            if (used + c.result.cigar_len > runs_cap) {
+                if (got.empty()) {
+                    *runs_used = c.result.cigar_len;
+                    return GENASM_E_NOSPACE;
+                }
+                break;
+            }
+            used += c.result.cigar_len;
+            got.push_back(c);
+            srv->done.pop_front();
+        }
+        if (got.empty() && srv->error) return srv->error;
+    }
+    uint64_t used = 0;
+    for (size_t i = 0; i < got.size(); ++i) {
+        genasm_completion& c = got[i];
+        genasm_completion_info& o = out[i];
+        o.tag = c.tag;
+        o.result = c.result;
+        o.result.cigar_off = used;
+        o.submit_ns = c.submit_ns;
+        o.admit_ns = c.admit_ns;
+        o.done_ns = c.done_ns;
+        if (c.result.cigar_len) std::memcpy(runs + used, c.cigar, (size_t)c.result.cigar_len * 4);
+        used += c.result.cigar_len;
+        std::free(c.cigar);
+    }
+    *runs_used = used;
+    return (int)got.size();
 }
 
 void genasm_completion_release(genasm_completion* c) {
@@ -445,12 +673,32 @@ void genasm_completion_release(genasm_completion* c) {
     }
 }
 
+int genasm_cancel(genasm_server* srv, uint64_t tag) {
+    if (!srv) return GENASM_E_INVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    for (auto it = srv->pending.begin(); it != srv->pending.end(); ++it) {
+        if (it->tag == tag) {
+            srv->pending.erase(it);
+            srv->st.cancelled++;
+            return GENASM_OK;
+        }
+    }
+    auto r = srv->tag_slot.equal_range(tag);
+    for (auto it = r.first; it != r.second; ++it) {
+        if (!srv->slot_cancelled[it->second]) {
+            srv->slot_cancelled[it->second] = 1;
+            srv->st.cancelled++;
+            return GENASM_OK;
+        }
+    }
+    return GENASM_E_INVAL;
+}
+
 int genasm_server_stats_read(genasm_server* srv, genasm_server_stats* out) {
     if (!srv || !out) return GENASM_E_INVAL;
     std::lock_guard<std::mutex> lk(srv->mu);
     *out = srv->st;
     out->pending = (uint32_t)srv->pending.size();
-    out->pool_bases_used = srv->pool.used();
     return GENASM_OK;
 }
 
@@ -464,27 +712,34 @@ void genasm_server_destroy(genasm_server* srv) {
     if (srv->engine.joinable()) srv->engine.join();
     (void)hipSetDevice(srv->ctx->device);
     if (srv->s) (void)hipStreamSynchronize(srv->s);
-    if (srv->s2) (void)hipStreamSynchronize(srv->s2);
+    if (srv->s_copy) (void)hipStreamSynchronize(srv->s_copy);
     for (auto& c : srv->done) genasm_completion_release(&c);
-    if (srv->graph_exec) (void)hipGraphExecDestroy(srv->graph_exec);
-    if (srv->graph) (void)hipGraphDestroy(srv->graph);
-    void* dev[] = {srv->d_pool, srv->d_plo, srv->d_phi, srv->d_up_word, srv->d_up_bases, srv->d_cigar, srv->d_read_off, srv->d_ref_off, srv->d_run_base,
-                   srv->d_read_len, srv->d_ref_len, srv->d_out, srv->d_state, srv->d_search,
-                   srv->d_counters, srv->d_items, srv->d_key, srv->d_new, srv->d_active, srv->d_params,
-                   srv->d_spill, srv->d_upload, srv->d_up_src, srv->d_up_dst, srv->d_up_len,
-                   srv->d_gather_list, srv->d_gather_off, srv->d_gather};
+    std::vector<void*> dev = {srv->d_pool, srv->d_plo, srv->d_phi, srv->d_cigar, srv->d_read_off,
+                              srv->d_ref_off, srv->d_run_base, srv->d_read_len, srv->d_ref_len,
+                              srv->d_out, srv->d_state, srv->d_search, srv->d_new, srv->d_fin,
+                              srv->d_fin_len, srv->d_fin_off, srv->d_items, srv->d_key,
+                              srv->d_deadline, srv->d_spill};
+    std::vector<void*> host;
+    for (IterBufs& b : srv->it) {
+        if (b.exec) (void)hipGraphExecDestroy(b.exec);
+        if (b.graph) (void)hipGraphDestroy(b.graph);
+        for (void* p : {(void*)b.d_upload, (void*)b.d_up_src, (void*)b.d_up_dst, (void*)b.d_up_word,
+                        (void*)b.d_up_len, (void*)b.d_up_bases, (void*)b.d_admit, (void*)b.d_params,
+                        (void*)b.d_hot, (void*)b.d_cold, (void*)b.d_cnt, (void*)b.d_gather})
+            dev.push_back(p);
+        for (void* p : {(void*)b.h_upload, (void*)b.h_up_src, (void*)b.h_up_dst, (void*)b.h_up_word,
+                        (void*)b.h_up_len, (void*)b.h_up_bases, (void*)b.h_admit, (void*)b.h_params,
+                        (void*)b.h_hdr, (void*)b.h_slot, (void*)b.h_res, (void*)b.h_gather})
+            host.push_back(p);
+        for (hipEvent_t e : {b.ev_start, b.ev_done})
+            if (e) (void)hipEventDestroy(e);
+    }
     for (void* p : dev)
         if (p) (void)hipFree(p);
-    void* host[] = {srv->h_up_word, srv->h_up_bases, srv->h_read_off, srv->h_ref_off, srv->h_run_base, srv->h_read_len,
-                    srv->h_ref_len, srv->h_new, srv->h_active, srv->h_params, srv->h_upload,
-                    srv->h_up_src, srv->h_up_dst, srv->h_up_len, srv->h_state, srv->h_out,
-                    srv->h_search, srv->h_gather_list, srv->h_gather_off, srv->h_gather};
     for (void* p : host)
         if (p) (void)hipHostFree(p);
-    for (hipEvent_t e : {srv->ev_fork, srv->ev_join, srv->ev_t0, srv->ev_t1})
-        if (e) (void)hipEventDestroy(e);
     if (srv->s) (void)hipStreamDestroy(srv->s);
-    if (srv->s2) (void)hipStreamDestroy(srv->s2);
+    if (srv->s_copy) (void)hipStreamDestroy(srv->s_copy);
     delete srv;
 }
 
@@ -492,19 +747,29 @@ void genasm_server_destroy(genasm_server* srv) {
 
 namespace {
 
-// One iteration; returns GENASM_OK or a device error (the engine then stops).
-int iterate(genasm_server* srv, std::vector<uint32_t>& fresh) {
-    const uint32_t NS = srv->cfg.max_slots;
-    // 1. admission (FIFO) while a slot and room in both pools are free
+// Requests wait on the host, or at least half of the window groups hold a pair.
+bool saturated(genasm_server* srv) {
+    size_t pend;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        pend = srv->pending.size();
+    }
+    return pend > 0 || 2 * (uint64_t)srv->resident >= srv->groups;
+}
+
+// Admits waiting requests and queues iteration parity q on the device.
+int launch_iteration(genasm_server* srv, int q) {
+    RoctxRange range("genasm_serve_launch");
+    IterBufs& b = srv->it[q];
     std::vector<Request> admitted;
+    std::vector<uint32_t> admitted_slots;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         uint64_t upload = 0;
         while (!srv->pending.empty() && !srv->free_slots.empty()) {
             Request& r = srv->pending.front();
-            const uint64_t bytes = r.read2b.size() + r.ref2b.size();
-            if (!admitted.empty() && upload + bytes > srv->upload_cap) break;
-            if (bytes > srv->upload_cap) break;  // cannot upload (pool check made at submit)
+            const uint64_t bytes = r.bytes.size();
+            if (upload + bytes > srv->upload_cap) break;
             uint64_t rs, fs, cs;
             const uint64_t rl = round_up(r.m, kBaseUnit), fl = round_up(r.n, kBaseUnit);
             const uint64_t cl = (uint64_t)r.m + r.n + 1;
@@ -518,166 +783,164 @@ int iterate(genasm_server* srv, std::vector<uint32_t>& fresh) {
             const uint32_t slot = srv->free_slots.back();
             srv->free_slots.pop_back();
             Slot& sl = srv->slots[slot];
-            sl.busy = true;
             sl.tag = r.tag;
             sl.submit_ns = r.submit_ns;
             sl.admit_ns = steady_ns();
             sl.rstart = rs; sl.rlen = rl; sl.fstart = fs; sl.flen = fl; sl.cstart = cs; sl.clen = cl;
-            srv->h_read_off[slot] = rs;
-            srv->h_read_len[slot] = r.m;
-            srv->h_ref_off[slot] = fs;
-            srv->h_ref_len[slot] = r.n;
-            srv->h_run_base[slot] = cs;
-            fresh.push_back(slot);
+            srv->tag_slot.emplace(r.tag, slot);
+            srv->slot_cancelled[slot] = 0;
+            admitted_slots.push_back(slot);
             upload += bytes;
             admitted.push_back(std::move(r));
             srv->pending.pop_front();
         }
         srv->st.admitted += admitted.size();
+        srv->st.pool_bases_used = srv->pool.used();
     }
-    // 2. upload the admitted pairs' bases (one copy, one scatter) and the slot tables
+    // upload staging: packed bases and the scatter ranges, admission records
     uint64_t up = 0;
     uint32_t nr = 0;
     for (size_t a = 0; a < admitted.size(); ++a) {
-        const Slot& sl = srv->slots[fresh[fresh.size() - admitted.size() + a]];
+        const uint32_t slot = admitted_slots[a];
+        const Slot& sl = srv->slots[slot];
         const Request& r = admitted[a];
-        const std::vector<uint8_t>* parts[2] = {&r.read2b, &r.ref2b};
+        const uint64_t rb = (r.m + 3) / 4;
+        const uint64_t part_off[2] = {0, rb};
+        const uint64_t part_len[2] = {rb, r.bytes.size() - rb};
         const uint64_t dst[2] = {sl.rstart, sl.fstart};
         const uint32_t nb[2] = {r.m, r.n};
-        for (int q = 0; q < 2; ++q) {
-            if (parts[q]->empty()) continue;
-            std::memcpy(srv->h_upload + up, parts[q]->data(), parts[q]->size());
-            srv->h_up_src[nr] = up;
-            srv->h_up_dst[nr] = dst[q] / 4;
-            srv->h_up_len[nr] = (uint32_t)parts[q]->size();
-            srv->h_up_word[nr] = dst[q] / 64;
-            srv->h_up_bases[nr] = nb[q];
-            up += parts[q]->size();
+        for (int p = 0; p < 2; ++p) {
+            if (part_len[p] == 0) continue;
+            std::memcpy(b.h_upload + up, r.bytes.data() + part_off[p], part_len[p]);
+            b.h_up_src[nr] = up;
+            b.h_up_dst[nr] = dst[p] / 4;
+            b.h_up_len[nr] = (uint32_t)part_len[p];
+            b.h_up_word[nr] = dst[p] / 64;
+            b.h_up_bases[nr] = nb[p];
+            up += part_len[p];
             ++nr;
         }
+        ServeAdmit& ad = b.h_admit[a];
+        ad.read_off = sl.rstart;
+        ad.ref_off = sl.fstart;
+        ad.run_base = sl.cstart;
+        ad.slot = slot;
+        ad.m = r.m;
+        ad.n = r.n;
+        ad.pad = 0;
     }
-    const uint32_t n_new = (uint32_t)fresh.size();
-    const uint32_t n_act = (uint32_t)srv->searched.size();
-    std::copy(fresh.begin(), fresh.end(), srv->h_new);
-    std::copy(srv->searched.begin(), srv->searched.end(), srv->h_active);
-    srv->h_params[0] = n_new;
-    srv->h_params[1] = n_act;
+    const uint32_t n_new = (uint32_t)admitted.size();
+    srv->resident += n_new;
+    b.n_new = n_new;
+    // window time: short while the device has room (latency), long while
+    // requests wait or most window groups hold a pair (throughput)
+    uint32_t us = (uint32_t)srv->cfg.iteration_us;
+    if (us == 0) us = saturated(srv) ? 2000u : 250u;
+    b.h_params[kServeParamNew] = n_new;
+    b.h_params[kServeParamTicks] = us * 100u;  // the device wall clock runs at 100 MHz
     hipStream_t s = srv->s;
-    SRV_HIP(srv, hipEventRecord(srv->ev_t0, s));
+    SRV_HIP(srv, hipEventRecord(b.ev_start, s));
     if (nr) {
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_upload, srv->h_upload, up, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_up_src, srv->h_up_src, nr * 8, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_up_dst, srv->h_up_dst, nr * 8, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_up_len, srv->h_up_len, nr * 4, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_up_word, srv->h_up_word, nr * 8, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_up_bases, srv->h_up_bases, nr * 4, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, launch_scatter_bytes(srv->d_upload, srv->d_up_src, srv->d_pool, srv->d_up_dst,
-                                          srv->d_up_len, nr, s));
-        SRV_HIP(srv, launch_scatter_planes(srv->d_upload, srv->d_up_src, srv->d_up_bases,
-                                           srv->d_plo, srv->d_phi, srv->d_up_word, nr, s));
+        SRV_HIP(srv, hipMemcpyAsync(b.d_upload, b.h_upload, up, hipMemcpyHostToDevice, s));
+        SRV_HIP(srv, hipMemcpyAsync(b.d_up_src, b.h_up_src, nr * 8, hipMemcpyHostToDevice, s));
+        SRV_HIP(srv, hipMemcpyAsync(b.d_up_dst, b.h_up_dst, nr * 8, hipMemcpyHostToDevice, s));
+        SRV_HIP(srv, hipMemcpyAsync(b.d_up_len, b.h_up_len, nr * 4, hipMemcpyHostToDevice, s));
+        SRV_HIP(srv, hipMemcpyAsync(b.d_up_word, b.h_up_word, nr * 8, hipMemcpyHostToDevice, s));
+        SRV_HIP(srv, hipMemcpyAsync(b.d_up_bases, b.h_up_bases, nr * 4, hipMemcpyHostToDevice, s));
+        SRV_HIP(srv, launch_scatter_bytes(b.d_upload, b.d_up_src, srv->d_pool, b.d_up_dst, b.d_up_len,
+                                          nr, s));
+        SRV_HIP(srv, launch_scatter_planes(b.d_upload, b.d_up_src, b.d_up_bases, srv->d_plo,
+                                           srv->d_phi, b.d_up_word, nr, s));
     }
-    if (n_new) {
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_read_off, srv->h_read_off, NS * 8, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_ref_off, srv->h_ref_off, NS * 8, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_run_base, srv->h_run_base, NS * 8, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_read_len, srv->h_read_len, NS * 4, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_ref_len, srv->h_ref_len, NS * 4, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_new, srv->h_new, n_new * 4, hipMemcpyHostToDevice, s));
-    }
-    if (n_act)
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_active, srv->h_active, n_act * 4, hipMemcpyHostToDevice, s));
-    SRV_HIP(srv, hipMemcpyAsync(srv->d_params, srv->h_params, 2 * 4, hipMemcpyHostToDevice, s));
-    // 3. the device work of the iteration
-    if (srv->graph_exec) SRV_HIP(srv, hipGraphLaunch(srv->graph_exec, s));
-    else SRV_HIP(srv, enqueue_iteration(srv));
-    SRV_HIP(srv, hipEventRecord(srv->ev_t1, s));
-    // 4. which pairs finished: states of the searched pairs, search results of the new ones
-    SRV_HIP(srv, hipMemcpyAsync(srv->h_state, srv->d_state, NS * sizeof(PairState),
-                                hipMemcpyDeviceToHost, s));
-    SRV_HIP(srv, hipMemcpyAsync(srv->h_out, srv->d_out, NS * sizeof(genasm_result),
-                                hipMemcpyDeviceToHost, s));
-    SRV_HIP(srv, hipStreamSynchronize(s));
+    if (n_new)
+        SRV_HIP(srv, hipMemcpyAsync(b.d_admit, b.h_admit, n_new * sizeof(ServeAdmit),
+                                    hipMemcpyHostToDevice, s));
+    SRV_HIP(srv, hipMemcpyAsync(b.d_params, b.h_params, kServeParamWords * 4, hipMemcpyHostToDevice, s));
+    if (b.exec) SRV_HIP(srv, hipGraphLaunch(b.exec, s));
+    else SRV_HIP(srv, enqueue_iteration(srv, q));
+    SRV_HIP(srv, hipEventRecord(b.ev_done, s));
+    return GENASM_OK;
+}
+
+// Waits for iteration parity q and hands its finished pairs to the
+// completion queue.
+int finish_iteration(genasm_server* srv, int q) {
+    RoctxRange range("genasm_serve_finish");
+    IterBufs& b = srv->it[q];
+    SRV_HIP(srv, hipEventSynchronize(b.ev_done));
     float ms = 0.f;
-    SRV_HIP(srv, hipEventElapsedTime(&ms, srv->ev_t0, srv->ev_t1));
-    std::vector<uint32_t> finished;
-    std::vector<uint32_t> still;
-    still.reserve(n_act + n_new);
-    for (uint32_t i = 0; i < n_act; ++i) {
-        const uint32_t slot = srv->h_active[i];
-        (srv->h_state[slot].flags & kStateDone ? finished : still).push_back(slot);
+    SRV_HIP(srv, hipEventElapsedTime(&ms, b.ev_start, b.ev_done));
+    const uint32_t n_fin = (uint32_t)b.h_hdr[0];
+    const uint64_t total = b.h_hdr[1];
+    // the gathered elements that fit the buffer, in one copy; a pair past it
+    // is copied from the CIGAR pool by itself
+    uint64_t fit = 0;
+    std::vector<uint32_t> over;
+    for (uint32_t k = 0; k < n_fin; ++k) {
+        const genasm_result& r = b.h_res[k];
+        if (r.cigar_off + r.cigar_len <= srv->gather_cap) fit = std::max(fit, r.cigar_off + r.cigar_len);
+        else over.push_back(k);
     }
-    for (uint32_t slot : fresh) {
-        // a pair that ended in its start search (empty read, no hit) is done now
-        (srv->h_state[slot].flags & kStateDone ? finished : still).push_back(slot);
+    (void)total;
+    if (fit)
+        SRV_HIP(srv, hipMemcpyAsync(b.h_gather, b.d_gather, fit * 4, hipMemcpyDeviceToHost, srv->s_copy));
+    std::vector<std::vector<uint32_t>> over_el(over.size());
+    for (size_t j = 0; j < over.size(); ++j) {
+        const uint32_t k = over[j];
+        const Slot& sl = srv->slots[b.h_slot[k]];
+        over_el[j].resize(b.h_res[k].cigar_len);
+        SRV_HIP(srv, hipMemcpyAsync(over_el[j].data(), srv->d_cigar + sl.cstart,
+                                    over_el[j].size() * 4, hipMemcpyDeviceToHost, srv->s_copy));
     }
-    srv->searched.swap(still);
-    fresh.clear();
-    // 5. CIGARs of the finished pairs: one gather kernel, one copy
-    uint64_t total = 0;
-    uint32_t ng = 0;
-    for (uint32_t slot : finished) {
-        srv->h_gather_list[ng] = slot;
-        srv->h_gather_off[ng] = total;
-        total += srv->h_out[slot].cigar_len;
-        ++ng;
-    }
-    if (total > srv->gather_cap) {
-        // grow the gather buffers
-        SRV_HIP(srv, hipFree(srv->d_gather));
-        SRV_HIP(srv, hipHostFree(srv->h_gather));
-        srv->gather_cap = round_up(total, 1 << 20);
-        srv->d_gather = dev_alloc<uint32_t>(srv->gather_cap);
-        srv->h_gather = host_alloc<uint32_t>(srv->gather_cap);
-        if (!srv->d_gather || !srv->h_gather) return srv_fail(srv, "gather buffer", hipErrorOutOfMemory);
-    }
-    if (total) {
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_gather_list, srv->h_gather_list, ng * 4, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(srv->d_gather_off, srv->h_gather_off, ng * 8, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, launch_gather_runs(srv->d_out, srv->d_gather_list, ng, srv->d_gather_off,
-                                        srv->d_cigar, srv->d_gather, s));
-        SRV_HIP(srv, hipMemcpyAsync(srv->h_gather, srv->d_gather, total * 4, hipMemcpyDeviceToHost, s));
-        SRV_HIP(srv, hipStreamSynchronize(s));
-    }
-    // 6. completions
-    static const char kOp[4] = {'=', 'X', 'I', 'D'};
-    std::vector<genasm_completion> comps(ng);
-    for (uint32_t g = 0; g < ng; ++g) {
-        const uint32_t slot = srv->h_gather_list[g];
-        genasm_result r = srv->h_out[slot];
-        std::string text;
-        for (uint32_t e = 0; e < r.cigar_len; ++e) {
-            const uint32_t el = srv->h_gather[srv->h_gather_off[g] + e];
-            text += std::to_string(GENASM_CIGAR_LEN(el));
-            text += kOp[GENASM_CIGAR_OP(el)];
-        }
-        genasm_completion& c = comps[g];
-        c.tag = srv->slots[slot].tag;
-        r.cigar_off = 0;
-        r.cigar_len = (uint32_t)text.size();
-        c.result = r;
-        c.cigar = static_cast<char*>(std::malloc(text.size() + 1));
-        if (c.cigar) std::memcpy(c.cigar, text.c_str(), text.size() + 1);
-        c.submit_ns = srv->slots[slot].submit_ns;
-        c.admit_ns = srv->slots[slot].admit_ns;
-    }
+    SRV_HIP(srv, hipStreamSynchronize(srv->s_copy));
+    std::vector<genasm_completion> comps(n_fin);
+    size_t oj = 0;
     const uint64_t now = steady_ns();
-    std::lock_guard<std::mutex> lk(srv->mu);
-    for (uint32_t g = 0; g < ng; ++g) {
-        const uint32_t slot = srv->h_gather_list[g];
-        Slot& sl = srv->slots[slot];
+    for (uint32_t k = 0; k < n_fin; ++k) {
+        const uint32_t slot = b.h_slot[k];
+        const Slot& sl = srv->slots[slot];
+        genasm_result r = b.h_res[k];
+        const uint32_t* src = (oj < over.size() && over[oj] == k) ? over_el[oj++].data()
+                                                                  : b.h_gather + r.cigar_off;
+        genasm_completion& c = comps[k];
+        c.tag = sl.tag;
+        c.cigar = static_cast<char*>(std::malloc(std::max<size_t>(r.cigar_len, 1) * 4));
+        if (c.cigar && r.cigar_len) std::memcpy(c.cigar, src, (size_t)r.cigar_len * 4);
+        if (!c.cigar) r.cigar_len = 0;
+        r.cigar_off = 0;
+        c.result = r;
+        c.submit_ns = sl.submit_ns;
+        c.admit_ns = sl.admit_ns;
+        c.done_ns = now;
         srv->pool.release(sl.rstart, sl.rlen);
         srv->pool.release(sl.fstart, sl.flen);
         srv->cigpool.release(sl.cstart, sl.clen);
-        sl.busy = false;
         srv->free_slots.push_back(slot);
-        comps[g].done_ns = now;
-        srv->done.push_back(comps[g]);
     }
-    srv->st.completed += ng;
+    srv->resident -= std::min(srv->resident, n_fin);
+    std::lock_guard<std::mutex> lk(srv->mu);
+    uint64_t delivered = 0;
+    for (uint32_t k = 0; k < n_fin; ++k) {
+        const uint32_t slot = b.h_slot[k];
+        genasm_completion& c = comps[k];
+        auto r = srv->tag_slot.equal_range(c.tag);
+        for (auto it = r.first; it != r.second; ++it)
+            if (it->second == slot) { srv->tag_slot.erase(it); break; }
+        if (srv->slot_cancelled[slot]) {
+            // cancelled while resident: no completion
+            srv->slot_cancelled[slot] = 0;
+            genasm_completion_release(&c);
+            continue;
+        }
+        srv->done.push_back(c);
+        ++delivered;
+    }
+    srv->st.completed += delivered;
     srv->st.iterations++;
     srv->st.device_ms += ms;
-    srv->st.resident = (uint32_t)srv->searched.size();
-    if (ng) srv->cv_done.notify_all();
+    srv->st.resident = srv->resident;
+    srv->st.pool_bases_used = srv->pool.used();
+    if (delivered) srv->cv_done.notify_all();
     return GENASM_OK;
 }
 
@@ -686,17 +949,42 @@ void engine_main(genasm_server* srv) {
         srv_fail(srv, "hipSetDevice", hipErrorInvalidDevice);
         return;
     }
-    std::vector<uint32_t> fresh;
+    std::deque<int> inflight;  // parities of the queued iterations, oldest first
+    uint64_t t = 0;
     for (;;) {
+        bool stop;
+        size_t pend;
         {
-            std::unique_lock<std::mutex> lk(srv->mu);
-            if (srv->stop) return;
-            if (srv->pending.empty() && srv->searched.empty()) {
-                srv->cv_work.wait_for(lk, std::chrono::milliseconds(5));
-                continue;
-            }
+            std::lock_guard<std::mutex> lk(srv->mu);
+            stop = srv->stop;
+            pend = srv->pending.size();
         }
-        if (iterate(srv, fresh) != GENASM_OK) return;
+        if (stop && inflight.empty()) return;
+        const bool can_admit = pend > 0 && !srv->free_slots.empty();
+        bool launch = false;
+        if (!stop && inflight.size() < 2 && (can_admit || srv->resident > 0)) {
+            // a second iteration is queued behind the running one when requests
+            // wait or most window groups are busy (the device then never waits
+            // for the host); otherwise the running one is awaited, so that
+            // requests arriving meanwhile join the next iteration
+            launch = inflight.empty() || pend > 0 || 2 * (uint64_t)srv->resident >= srv->groups;
+        }
+        if (launch) {
+            const int q = (int)(t & 1);
+            if (launch_iteration(srv, q) != GENASM_OK) return;
+            inflight.push_back(q);
+            ++t;
+            continue;
+        }
+        if (!inflight.empty()) {
+            const int q = inflight.front();
+            inflight.pop_front();
+            if (finish_iteration(srv, q) != GENASM_OK) return;
+            continue;
+        }
+        std::unique_lock<std::mutex> lk(srv->mu);
+        srv->cv_work.wait_for(lk, std::chrono::milliseconds(5),
+                              [&] { return srv->stop || !srv->pending.empty(); });
     }
 }
 

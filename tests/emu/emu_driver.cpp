@@ -5,7 +5,9 @@
 //   emu_driver IN OUT
 // IN : int64 form (0 plain, 1 batched, 2 serving loop, 3 unimproved, 4 filter), group_lanes, search_lanes,
 //      lds_rows, k, W, O, n_pairs, read_bytes, ref_bytes, hard_row, window_budget,
-//      slots, admit_per_iteration, hard_lanes, search_chunk, tb_prefetch, hard_share; then
+//      slots, admit_per_iteration, hard_lanes, search_chunk, tb_prefetch, hard_share,
+//      serving window time in emulated clock reads (0 = none), compact window groups (0/1);
+//      then
 //      the packed read bytes, the packed reference bytes, read_off[n+1], ref_off[n+1] (uint64).
 // OUT: n genasm_result records, then (read bases + ref bases) CIGAR elements;
 //      for the filter, n int32 distances then n uint32 starts.
@@ -26,7 +28,7 @@ int main(int argc, char** argv) {
     if (argc != 3) { fprintf(stderr, "usage: emu_driver IN OUT\n"); return 2; }
     FILE* f = fopen(argv[1], "rb");
     if (!f) { perror("open IN"); return 2; }
-    int64_t h[18];
+    int64_t h[20];
     if (!read_all(f, h, sizeof h)) return 2;
     const int form = (int)h[0], G = (int)h[1], SG = (int)h[2], lds_rows = (int)h[3];
     const int k = (int)h[4], W = (int)h[5], O = (int)h[6];
@@ -37,6 +39,8 @@ int main(int argc, char** argv) {
     const uint32_t chunk = (uint32_t)h[15];
     const int tb_prefetch = (int)h[16];
     const int hard_share = (int)h[17];
+    const uint32_t ticks = (uint32_t)h[18];
+    const int compact = (int)h[19];
     std::vector<uint8_t> reads(nrb + 8), refs(nfb + 8);
     std::vector<uint64_t> roff(n + 1), foff(n + 1);
     if (!read_all(f, reads.data(), nrb) || !read_all(f, refs.data(), nfb) ||
@@ -99,25 +103,37 @@ int main(int argc, char** argv) {
     }
     if (form == 2) {
         // Serving loop, device side: slots are reused; each iteration admits
-        // up to per_iter pairs into free slots, resets their state, advances the
-        // searched slots by at most `budget` windows and searches the new ones.
+        // up to per_iter pairs into free slots (begin kernel), searches them,
+        // then runs the window kernel over the two device lists until the
+        // iteration's deadline (`ticks` reads of the emulated clock; 0 = none)
+        // or `budget` windows per pair; the kernels move every pair to the
+        // next iteration's lists or to the finished list.
         const int blocks = 2;
         const uint64_t workers = (uint64_t)blocks * 4;
         const int spill_rows = 64 - lds_rows;
         std::vector<SearchOut> search(n_slots, SearchOut{kSearchPending, 0});
-        std::vector<uint32_t> counters(kCounterCount, 0);
+        std::vector<uint32_t> cnt[2] = {std::vector<uint32_t>(kCounterCount, 0),
+                                        std::vector<uint32_t>(kCounterCount, 0)};
+        std::vector<uint32_t> hot[2] = {std::vector<uint32_t>(n_slots + 1), std::vector<uint32_t>(n_slots + 1)};
+        std::vector<uint32_t> cold[2] = {std::vector<uint32_t>(n_slots + 1), std::vector<uint32_t>(n_slots + 1)};
+        std::vector<uint32_t> params[2] = {std::vector<uint32_t>(kServeParamWords, 0),
+                                           std::vector<uint32_t>(kServeParamWords, 0)};
         const uint64_t icap = search_item_cap(n_slots, foff[n], chunk);
         std::vector<uint64_t> items(2 * icap);
         std::vector<unsigned long long> key(n_slots);
-        std::vector<uint32_t> fresh_list(n_slots + 1), active(n_slots + 1), params(4, 0);
-        std::vector<unsigned long long> spill(spill_words(workers, spill_rows, p.stride));
+        std::vector<uint32_t> new_list(n_slots + 1), fin(n_slots + 1), fin_len(1, 0);
+        std::vector<ServeAdmit> admit(n_slots + 1);
+        std::vector<unsigned long long> spill(spill_words(workers, kCompactSpillRows, p.stride));
+        std::vector<unsigned long long> deadline(1, 0);
         std::vector<uint64_t> s_roff(n_slots), s_foff(n_slots), s_base(n_slots);
         std::vector<uint32_t> s_rlen(n_slots), s_flen(n_slots);
         std::vector<PairState> state(n_slots);
         std::vector<genasm_result> s_out(n_slots);
         std::vector<int64_t> owner(n_slots, -1);
-        std::vector<uint32_t> free_slots, searched;
+        std::vector<uint32_t> free_slots;
         for (uint32_t q = n_slots; q-- > 0;) free_slots.push_back(q);
+        ServeSlots slots{s_roff.data(), s_foff.data(), s_base.data(), s_rlen.data(), s_flen.data(),
+                         state.data()};
         p.read_off = s_roff.data();
         p.ref_off = s_foff.data();
         p.read_len = s_rlen.data();
@@ -126,47 +142,50 @@ int main(int argc, char** argv) {
         p.n_pairs = n_slots;
         p.out = s_out.data();
         p.search = search.data();
-        p.counters = counters.data();
-        p.spill = spill_rows > 0 ? spill.data() : nullptr;
+        p.spill = spill.data();
         p.lds_rows = lds_rows;
+        p.compact = 1;
         p.hard_row = 65;
         p.hard_lanes = 16;
-        p.hard_share = 100;
-        p.route = 0;
+        p.hard_share = 0;
+        p.route = 1;
         p.state = state.data();
         p.window_budget = budget;
-        p.easy_list = active.data();
-        p.hard_list = active.data();
         p.search_key = key.data();
         p.search_chunk = chunk;
-        uint64_t next = 0, finished_n = 0, iters = 0;
-        std::vector<uint32_t> fresh;
+        p.fin_list = fin.data();
+        p.fin_len = fin_len.data();
+        uint64_t next = 0, finished_n = 0, iters = 0, resident = 0;
         while (finished_n < n) {
             if (++iters > 100000) { fprintf(stderr, "serving loop does not finish\n"); return 3; }
-            fresh.clear();
-            while (next < n && !free_slots.empty() && fresh.size() < per_iter) {
-                const uint32_t q = free_slots.back();
+            const int q = (int)(iters & 1);
+            uint32_t n_new = 0;
+            while (next < n && !free_slots.empty() && n_new < per_iter) {
+                const uint32_t sl = free_slots.back();
                 free_slots.pop_back();
-                s_roff[q] = roff[next];
-                s_rlen[q] = (uint32_t)(roff[next + 1] - roff[next]);
-                s_foff[q] = foff[next];
-                s_flen[q] = (uint32_t)(foff[next + 1] - foff[next]);
-                s_base[q] = (roff[next] - roff[0]) + (foff[next] - foff[0]);
-                owner[q] = (int64_t)next++;
-                fresh.push_back(q);
+                ServeAdmit& a = admit[n_new++];
+                a.slot = sl;
+                a.read_off = roff[next];
+                a.m = (uint32_t)(roff[next + 1] - roff[next]);
+                a.ref_off = foff[next];
+                a.n = (uint32_t)(foff[next + 1] - foff[next]);
+                a.run_base = (roff[next] - roff[0]) + (foff[next] - foff[0]);
+                owner[sl] = (int64_t)next++;
+                ++resident;
             }
-            std::copy(fresh.begin(), fresh.end(), fresh_list.begin());
-            std::copy(searched.begin(), searched.end(), active.begin());
-            params[0] = (uint32_t)fresh.size();
-            params[1] = (uint32_t)searched.size();
-            launch_init_counters_dev(counters.data(), params.data(), nullptr);
-            launch_reset_states(state.data(), fresh_list.data(), params.data(), n_slots, nullptr);
-            emu::group_lanes = 16;
-            launch_windows(p, blocks, nullptr);
+            params[q][kServeParamNew] = n_new;
+            params[q][kServeParamTicks] = ticks;
+            emu::group_lanes = 64;
+            launch_serve_begin(cnt[q].data(), cnt[1 - q].data(), fin_len.data(), params[q].data(),
+                               admit.data(), slots, new_list.data(), nullptr);
             AlignParams S = p;
-            S.list_in = fresh_list.data();
+            S.counters = cnt[q].data();
+            S.easy_list = hot[q].data();
+            S.hard_list = cold[q].data();
+            S.list_in = new_list.data();
             S.items_out = items.data();
             launch_search_items(S, n_slots, nullptr);
+            emu::group_lanes = 16;
             S.list_slot = 0;
             S.items_in = items.data();
             S.items_out = items.data() + icap;
@@ -179,27 +198,54 @@ int main(int argc, char** argv) {
             S.items_out = items.data() + icap;
             S.list_slot = 2;
             launch_search(S, 16, 4, blocks, nullptr);
+            emu::group_lanes = 64;
             launch_search_finalize(S, n_slots, nullptr);
-            std::vector<uint32_t> still;
-            auto settle = [&](uint32_t q) {
-                if (state[q].flags & kStateDone) {
-                    out[owner[q]] = s_out[q];
-                    owner[q] = -1;
-                    free_slots.push_back(q);
-                    ++finished_n;
-                } else {
-                    still.push_back(q);
-                }
-            };
-            for (uint32_t q : searched) settle(q);
-            for (uint32_t q : fresh) {
-                if (search[q].row == kSearchPending) {
-                    fprintf(stderr, "slot %u left pending by the search\n", q);
+            for (uint32_t i = 0; i < n_new; ++i) {
+                if (search[admit[i].slot].row == kSearchPending) {
+                    fprintf(stderr, "slot %u left pending by the search\n", admit[i].slot);
                     return 3;
                 }
-                settle(q);
             }
-            searched.swap(still);
+            emu::group_lanes = 1;
+            launch_serve_stamp(params[q].data(), deadline.data(), nullptr);
+            AlignParams P = p;
+            P.counters = cnt[q].data();
+            P.easy_list = hot[q].data();
+            P.hard_list = cold[q].data();
+            P.deadline = deadline.data();
+            P.next_hot = hot[1 - q].data();
+            P.next_cold = cold[1 - q].data();
+            P.next_len = cnt[1 - q].data();
+            emu::group_lanes = 16;
+            launch_windows(P, blocks, nullptr);
+            // the finished pairs' results (their CIGARs are already in place)
+            for (uint32_t k = 0; k < fin_len[0]; ++k) {
+                const uint32_t sl = fin[k];
+                if (owner[sl] < 0 || !(state[sl].flags & kStateDone)) {
+                    fprintf(stderr, "slot %u listed as finished but not done\n", sl);
+                    return 3;
+                }
+                out[owner[sl]] = s_out[sl];
+                owner[sl] = -1;
+                free_slots.push_back(sl);
+                ++finished_n;
+                --resident;
+            }
+            // every resident pair is on exactly one of the next iteration's lists
+            const uint32_t nh = cnt[1 - q][kCounterEasyLen], nc = cnt[1 - q][kCounterHardLen];
+            if (nh + nc != resident) {
+                fprintf(stderr, "lists hold %u + %u pairs, %llu resident\n", nh, nc,
+                        (unsigned long long)resident);
+                return 3;
+            }
+            std::vector<char> seen(n_slots, 0);
+            for (uint32_t k = 0; k < nh + nc; ++k) {
+                const uint32_t sl = k < nh ? hot[1 - q][k] : cold[1 - q][k - nh];
+                if (sl >= n_slots || owner[sl] < 0 || seen[sl]++) {
+                    fprintf(stderr, "bad list entry %u\n", sl);
+                    return 3;
+                }
+            }
         }
         fprintf(stderr, "emu: serving loop finished in %llu iterations\n", (unsigned long long)iters);
     } else if (form == GENASM_FORM_PLAIN) {
@@ -214,7 +260,8 @@ int main(int argc, char** argv) {
     } else {
         const int blocks = 2;
         const uint64_t workers = (uint64_t)blocks * 4;
-        const int spill_rows = 64 - lds_rows;
+        const bool use_compact = compact && G == 16 && hard_lanes == 16;
+        const int spill_rows = use_compact ? kCompactSpillRows : 64 - lds_rows;
         std::vector<SearchOut> search(n, SearchOut{kSearchPending, 0});
         std::vector<uint32_t> counters(kCounterCount, 0), order(n);
         const uint64_t icap = search_item_cap(n, foff[n] - foff[0], chunk);
@@ -238,6 +285,7 @@ int main(int argc, char** argv) {
         p.hard_share = hard_share;
         p.route = 1;
         p.lds_rows = lds_rows;
+        p.compact = use_compact ? 1 : 0;
         p.search_key = key.data();
         p.search_chunk = chunk;
         launch_init_counters(p.counters, (uint32_t)n, nullptr);

@@ -198,7 +198,23 @@ inline unsigned long long bitreverse64(unsigned long long x) {
 }  // namespace emu
 #define __builtin_bitreverse64 emu::bitreverse64
 inline unsigned long long clock64() { return 0ull; }
-inline unsigned long long wall_clock64() { return 0ull; }
+namespace emu {
+inline std::atomic<unsigned long long> clock_reads{0};
+}  // namespace emu
+// The device clock, read by a scalar instruction on the GPU (one value per
+// wavefront): here one value per lane group, advancing by one per read.
+inline unsigned long long wall_clock64() {
+    emu::BlockState* b = emu::cur.blk;
+    const int lane = (int)emu::cur.tid;
+    const int g0 = lane / b->group_lanes * b->group_lanes;
+    emu::group_barrier();
+    if (lane == g0) b->slot[lane] = emu::clock_reads.fetch_add(1);
+    emu::group_barrier();
+    const unsigned long long v = b->slot[g0];
+    emu::group_barrier();
+    return v;
+}
+inline void __threadfence_system() { std::atomic_thread_fence(std::memory_order_seq_cst); }
 #define __builtin_amdgcn_update_dpp emu::update_dpp
 // Block-wide barriers and static shared arrays are not emulated (kernels that
 // use them, such as the ordering scan, do not run under the emulation).

@@ -39,12 +39,13 @@ FILTER = 4      # the pre-alignment filter
 
 def run(driver: str, ps, form: int, group_lanes=16, search_lanes=16, lds_rows=16, hard_row=16,
         timeout=600, window_budget=0, slots=0, admit_per_iteration=0, hard_lanes=16,
-        search_chunk=37, tb_prefetch=0, hard_share=50):
+        search_chunk=37, tb_prefetch=0, hard_share=50, ticks=0, compact=1):
     """Returns (results, list of (op char, length) runs per pair)."""
     reads2b, refs2b = pack2b(ps.reads), pack2b(ps.refs)
     hdr = np.array([form, group_lanes, search_lanes, lds_rows, ps.k, ps.W, ps.O, ps.n_pairs,
                     len(reads2b), len(refs2b), hard_row, window_budget, slots,
-                    admit_per_iteration, hard_lanes, search_chunk, tb_prefetch, hard_share],
+                    admit_per_iteration, hard_lanes, search_chunk, tb_prefetch, hard_share, ticks,
+                    compact],
                    dtype=np.int64)
     with tempfile.TemporaryDirectory() as tmp:
         fin, fout = os.path.join(tmp, "in.bin"), os.path.join(tmp, "out.bin")
@@ -68,7 +69,7 @@ def run_filter(driver: str, ps, k: int, timeout=600):
     reads2b, refs2b = pack2b(ps.reads), pack2b(ps.refs)
     # same header layout as run() (the batched-form fields are unused here)
     hdr = np.array([FILTER, 64, 64, 64, k, ps.W, ps.O, ps.n_pairs, len(reads2b), len(refs2b),
-                    65, 0, 0, 0, 16, 0, 0, 100], dtype=np.int64)
+                    65, 0, 0, 0, 16, 0, 0, 100, 0, 0], dtype=np.int64)
     with tempfile.TemporaryDirectory() as tmp:
         fin, fout = os.path.join(tmp, "in.bin"), os.path.join(tmp, "out.bin")
         with open(fin, "wb") as f:

@@ -32,17 +32,17 @@ def expected(ps):
             for i in range(ps.n_pairs)]
 
 
-def emulated(driver, ps, form, hard_row=16, hard_lanes=16, tb_prefetch=0, hard_share=50):
+def emulated(driver, ps, form, hard_row=16, hard_lanes=16, tb_prefetch=0, hard_share=50, compact=1):
     res, cig = emu.run(driver, ps, form, 16, 16, 16, hard_row=hard_row, hard_lanes=hard_lanes,
-                       tb_prefetch=tb_prefetch, hard_share=hard_share)
+                       tb_prefetch=tb_prefetch, hard_share=hard_share, compact=compact)
     assert (res["flags"] == 0).all()
     return [(int(r["edit_distance"]), c, int(r["ref_begin"]), int(r["ref_end"]), int(r["n_windows"]))
             for r, c in zip(res, cig)]
 
 
-def check(driver, ps, form, hard_row=16, hard_lanes=16, tb_prefetch=0, hard_share=50):
+def check(driver, ps, form, hard_row=16, hard_lanes=16, tb_prefetch=0, hard_share=50, compact=1):
     want, got = expected(ps), emulated(driver, ps, form, hard_row, hard_lanes, tb_prefetch,
-                                       hard_share)
+                                       hard_share, compact)
     bad = [i for i in range(ps.n_pairs) if want[i] != got[i]]
     assert not bad, (bad[:5], want[bad[0]], got[bad[0]])
 
@@ -71,11 +71,14 @@ def test_unimproved_fuzz_and_edges(driver):
         check(driver, ps, emu.UNIMPROVED)
 
 
-@pytest.mark.parametrize("hard_row,hard_lanes", [(16, 16), (0, 64), (65, 16), (4, 64), (0, 32),
-                                               (4, 32)])
-def test_fuzz_batched(driver, hard_row, hard_lanes):
+@pytest.mark.parametrize("hard_row,hard_lanes,compact", [(16, 16, 1), (4, 16, 1), (16, 16, 0),
+                                                       (0, 64, 0), (65, 16, 1), (4, 64, 0),
+                                                       (0, 32, 0), (4, 32, 0)])
+def test_fuzz_batched(driver, hard_row, hard_lanes, compact):
     # hard_row 0 with 64 (32) hard lanes sends every pair through the whole- (half-)
-    # wavefront path, whose emulation is slow: fewer and shorter pairs there
+    # wavefront path, whose emulation is slow: fewer and shorter pairs there;
+    # compact 16-lane groups keep 32-bit table slices (pairs from the hard
+    # queue start deep), compact 0 the 64-bit table
     rng = np.random.default_rng(31 + hard_row)
     n, max_len = {64: (6, 110), 32: (12, 160)}.get(hard_lanes, (30, 250))
     pairs = gen.fuzz(4242 + hard_row, 2 * n, max_len=max_len)
@@ -85,7 +88,7 @@ def test_fuzz_batched(driver, hard_row, hard_lanes):
         k = int(rng.choice([1, 5, 64]))
         sub = pairs[chunk * n:(chunk + 1) * n]
         ps = gen.from_lists("fuzz", [p[0] for p in sub], [p[1] for p in sub], k, W, O)
-        check(driver, ps, 1, hard_row, hard_lanes)
+        check(driver, ps, 1, hard_row, hard_lanes, compact=compact)
 
 
 def test_edge_cases_batched(driver):
@@ -94,11 +97,13 @@ def test_edge_cases_batched(driver):
     for k in (0, 3, 64):
         ps = gen.from_lists("edge", [c[0] for c in cases], [c[1] for c in cases], k)
         check(driver, ps, 1)
+        check(driver, ps, 1, compact=0)
 
 
-@pytest.mark.parametrize("hard_row,hard_lanes,tb_prefetch", [(16, 16, 0), (16, 64, 0), (16, 16, 1),
-                                                              (16, 32, 0), (16, 32, 1)])
-def test_long_read_prefixes_with_decoy(driver, hard_row, hard_lanes, tb_prefetch):
+@pytest.mark.parametrize("hard_row,hard_lanes,tb_prefetch,compact",
+                         [(16, 16, 0, 1), (65, 16, 0, 1), (16, 16, 1, 1), (16, 16, 0, 0),
+                          (16, 64, 0, 0), (16, 16, 1, 0), (16, 32, 0, 0), (16, 32, 1, 0)])
+def test_long_read_prefixes_with_decoy(driver, hard_row, hard_lanes, tb_prefetch, compact):
     # 1,000-base prefixes of a true pair and a decoy pair: the decoy's windows
     # need most of the 64 rows (spilled rows with 16 lanes and past row 31 with
     # 32, the whole-wavefront path with 64)
@@ -106,15 +111,17 @@ def test_long_read_prefixes_with_decoy(driver, hard_row, hard_lanes, tb_prefetch
     assert ps.decoy.tolist() == [True, False]
     cut = gen.from_lists("long-prefix", [ps.read(i)[:1000] for i in range(2)],
                          [ps.ref(i)[:1100] for i in range(2)], 64)
-    check(driver, cut, 1, hard_row, hard_lanes, tb_prefetch)
+    check(driver, cut, 1, hard_row, hard_lanes, tb_prefetch, compact=compact)
 
 
-@pytest.mark.parametrize("budget", [1, 3])
-def test_serving_loop(driver, budget):
+@pytest.mark.parametrize("budget,ticks", [(1, 0), (3, 0), (0, 5), (0, 40)])
+def test_serving_loop(driver, budget, ticks):
     # the serving form's device side: 6 slots reused by 40 requests, three
     # admitted per iteration, each resident pair advancing at most `budget`
-    # windows per iteration (open CIGAR runs carried across iterations)
-    pairs = gen.fuzz(5150 + budget, 24 if budget == 1 else 16, max_len=260)
+    # windows per iteration or until the iteration's deadline (`ticks` reads
+    # of the emulated clock) passes; open CIGAR runs carried across
+    # iterations, the kernels keeping the hot, cold and finished lists
+    pairs = gen.fuzz(5150 + budget + ticks, 24 if budget == 1 else 16, max_len=260)
     cases = [("", ""), ("", "ACGT"), ("ACGT", ""), ("T" * 65, ""), ("A" * 64, "C" * 64),
              ("G" * 130, "G" * 90)]
     reads = [p[0] for p in pairs] + [c[0] for c in cases]
@@ -123,7 +130,7 @@ def test_serving_loop(driver, budget):
         ps = gen.from_lists("serve", reads, refs, k, W, O)
         want = expected(ps)
         res, cig = emu.run(driver, ps, emu.SERVE, 16, 16, 16, window_budget=budget, slots=6,
-                           admit_per_iteration=3)
+                           admit_per_iteration=3, ticks=ticks)
         assert (res["flags"] == 0).all()
         got = [(int(r["edit_distance"]), c, int(r["ref_begin"]), int(r["ref_end"]),
                 int(r["n_windows"])) for r, c in zip(res, cig)]

@@ -3,8 +3,8 @@
 C ABI, compared with the CPU oracle pair by pair on edit distance, reference
 span, window count and every CIGAR run. The bar is bit-exact (integer work).
 
-Launches: the batched form with its default launch and with the autotuner's
-pick, the plain form, the unimproved form (long10k), a persistent grid so
+Launches: the batched form with its default launch, with compact groups and
+with the autotuner's pick, the plain form, the unimproved form (long10k), a persistent grid so
 small that every window group takes many pairs in turn (its LDS header, spill
 area and run state carried from one pair to the next), and the host-memory
 form (short250), whose CIGAR text is compared run by run."""
@@ -88,6 +88,11 @@ def test_batched_autotuned_every_pair(ctx, name):
 
 
 @pytest.mark.parametrize("name", BATCH_WORKLOADS)
+def test_compact_every_pair(ctx, name):
+    run_dev(ctx, name, ga.make_launch(ga.FORM_BATCHED, table_bits=32), label=f"{name}/compact")
+
+
+@pytest.mark.parametrize("name", BATCH_WORKLOADS)
 def test_plain_every_pair(ctx, name):
     run_dev(ctx, name, ga.make_launch(ga.FORM_PLAIN), label=f"{name}/plain")
 
@@ -97,7 +102,8 @@ def test_unimproved_long10k_every_pair(ctx):
 
 
 @pytest.mark.parametrize("variant", [dict(), dict(hard_lanes=32), dict(hard_lanes=64),
-                                     dict(hard_row=65), dict(hard_row=-1, hard_lanes=32)])
+                                     dict(hard_row=65), dict(hard_row=-1, hard_lanes=32),
+                                     dict(table_bits=32), dict(table_bits=32, hard_row=65)])
 def test_groups_take_many_pairs(ctx, variant):
     # 5,000 long pairs on one workgroup per compute unit: every 16-lane group
     # (or 32-/64-lane hard group) runs several pairs in turn

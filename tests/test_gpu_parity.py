@@ -57,6 +57,7 @@ def assert_same(ps, want, got, label=""):
 FORMS = {
     "plain": ga.make_launch(ga.FORM_PLAIN),
     "batched": None,
+    "compact": ga.make_launch(ga.FORM_BATCHED, table_bits=32),
     "unimproved": ga.make_launch(ga.FORM_UNIMPROVED),
 }
 
@@ -159,6 +160,14 @@ LAUNCH_VARIANTS = {
     "hard_share_100": dict(hard_share=100),
     "hard_share_30_g32": dict(hard_share=30, hard_lanes=32),
     "hard_share_70_g64": dict(hard_share=70, hard_lanes=64),
+    # compact 16-lane groups: 32-bit table slices, deep windows recomputed in device memory
+    "compact": dict(table_bits=32),
+    "compact_no_hard": dict(table_bits=32, hard_row=65),
+    "compact_all_hard": dict(table_bits=32, hard_row=-1),
+    "compact_prefetch": dict(table_bits=32, tb_prefetch=1),
+    "compact_one_worker": dict(table_bits=32, workers_per_cu=1),
+    "search_4_per_cu": dict(search_per_cu=4),
+    "search_16_per_cu": dict(search_per_cu=16),
 }
 
 
@@ -329,8 +338,8 @@ def test_graph_capture_replays(ctx, form):
         gctx.close()
 
 
-@pytest.mark.parametrize("form,variant", [("batched", "improved"), ("plain", "improved"),
-                                          ("unimproved", "uncompressed")])
+@pytest.mark.parametrize("form,variant", [("batched", "improved"), ("compact", "improved"),
+                                          ("plain", "improved"), ("unimproved", "uncompressed")])
 def test_work_counters_match_oracle(ctx, form, variant):
     # The device work counters (profiling) against the oracle variant with the
     # same storage scheme: DC word operations, DP cells, stored table words and,
@@ -472,3 +481,26 @@ def test_host_form_nospace_writes_nothing(ctx):
     got = [(int(x["edit_distance"]), int(x["ref_begin"]), int(x["ref_end"]), int(x["n_windows"]),
             text[int(x["cigar_off"]):int(x["cigar_off"]) + int(x["cigar_len"])].decode()) for x in out]
     assert_same(ps, expected(ps), got, "after E_NOSPACE")
+
+
+def test_injected_allocation_failure(monkeypatch):
+    # With GENASM_FAIL_ALLOC=1 every device allocation fails: a fresh context's
+    # first device-form call and a server's creation return GENASM_E_NOMEM,
+    # nothing is launched, and the same context works once the variable is gone.
+    import torch
+    ps = gen.make("short100", 50, start=70)
+    want = expected(ps)
+    fresh = ga.Context(0)
+    try:
+        monkeypatch.setenv("GENASM_FAIL_ALLOC", "1")
+        with pytest.raises(ga.GenasmError) as e:
+            on_gpu(fresh, ps)
+        assert e.value.code == ga.capi.E_NOMEM
+        with pytest.raises(ga.GenasmError) as e:
+            ga.Server(fresh, ps.k, ps.W, ps.O)
+        assert e.value.code == ga.capi.E_NOMEM
+        monkeypatch.delenv("GENASM_FAIL_ALLOC")
+        torch.cuda.synchronize()
+        assert_same(ps, want, on_gpu(fresh, ps), "after the injected failure")
+    finally:
+        fresh.close()

@@ -182,3 +182,136 @@ def test_many_requests_match_oracle(ctx):
     bad = [t for t in tags if as_tuple(got[t]) != want[t]]
     assert not bad, (len(bad), bad[:5], want[bad[0]][:4], as_tuple(got[bad[0]])[:4])
     assert st["completed"] == ps.n_pairs and st["resident"] == 0
+
+
+def _run_elements_from_completions(got, tags):
+    """Device-style results and concatenated run elements of completions in tag order."""
+    res = np.zeros(len(tags), dtype=ga.RESULT_DTYPE)
+    parts, off = [], 0
+    for j, t in enumerate(tags):
+        c = got[t]
+        for f in ("edit_distance", "ref_begin", "ref_end", "n_windows", "flags"):
+            res[f][j] = c[f]
+        el = c["cigar"]
+        res["cigar_off"][j] = off
+        res["cigar_len"][j] = len(el)
+        parts.append(el)
+        off += len(el)
+    return res, (np.concatenate(parts).astype(np.uint32) if parts else np.zeros(0, np.uint32))
+
+
+@pytest.mark.parametrize("iteration_us,unaligned", [(0, False), (30, True)])
+def test_batch_submit_runs_match_oracle(ctx, iteration_us, unaligned):
+    # 5,000 requests of the serving mix queued through genasm_submit_batch from
+    # 2-bit packed streams (with every request starting at a base offset that
+    # is not a multiple of 4 when `unaligned`), completions carrying run-length
+    # elements; with a 30 us window time the long requests run over many
+    # iterations, resuming from their device-resident state each time
+    from tests._helpers import assert_batch_matches, device_run_elements
+    ps = gen.make("serving", 5000, start=40_000)
+    ores, oops, _, _ = oracle.batch(ps)
+    reads, refs = ps.reads, ps.refs
+    roff, foff = ps.read_off.astype(np.uint64), ps.ref_off.astype(np.uint64)
+    if unaligned:
+        # one to three junk bases before every request's read and reference
+        pad = (np.arange(ps.n_pairs) % 3 + 1).astype(np.uint64)
+        def spread(seq, off):
+            parts = []
+            for i in range(ps.n_pairs):
+                parts.append(np.full(int(pad[i]), 2, np.uint8))
+                parts.append(seq[off[i]:off[i + 1]])
+            return np.concatenate(parts)
+        r_cat, f_cat = spread(reads, roff), spread(refs, foff)
+        starts_r = np.concatenate(([0], np.cumsum(pad + np.diff(roff))))[:-1] + pad
+        starts_f = np.concatenate(([0], np.cumsum(pad + np.diff(foff))))[:-1] + pad
+        sub_roff = np.stack([starts_r, starts_r + np.diff(roff)], 1)
+        sub_foff = np.stack([starts_f, starts_f + np.diff(foff)], 1)
+        assert (sub_roff[:, 0] % 4 != 0).any()
+    else:
+        r_cat, f_cat = reads, refs
+        sub_roff = np.stack([roff[:-1], roff[1:]], 1)
+        sub_foff = np.stack([foff[:-1], foff[1:]], 1)
+    r2, f2 = ga.pack(r_cat), ga.pack(f_cat)
+    tags = np.arange(ps.n_pairs, dtype=np.uint64) + 77
+    got = {}
+    with ga.Server(ctx, ps.k, ps.W, ps.O, iteration_us=iteration_us, cigar_runs=1) as srv:
+        i = 0
+        deadline = time.time() + 240
+        while i < ps.n_pairs:
+            assert time.time() < deadline, "submission did not finish"
+            j = min(ps.n_pairs, i + 700)
+            # requests i..j-1 as one run of offsets, or one request per call
+            # when junk bases separate them
+            if unaligned:
+                acc = 0
+                for q in range(i, j):
+                    rc, a = srv.submit_batch(r2, sub_roff[q], f2, sub_foff[q], tags[q:q + 1])
+                    if a == 0:
+                        break
+                    acc += a
+            else:
+                rc, acc = srv.submit_batch(r2, roff[i:j + 1], f2, foff[i:j + 1], tags[i:j])
+            assert rc in (0, ga.capi.E_BUSY), rc
+            i += acc
+            for c in srv.poll(timeout_ms=1 if acc == 0 else 0):
+                got[c["tag"]] = c
+        got.update(drain(srv, [int(t) for t in tags if int(t) not in got], timeout_s=240))
+        st = srv.stats()
+    assert st["completed"] == ps.n_pairs and st["resident"] == 0 and st["pool_bases_used"] == 0
+    if iteration_us:
+        assert st["iterations"] > 20, st
+    res, el = _run_elements_from_completions(got, [int(t) for t in tags])
+    assert_batch_matches(ps, ores, oops, res, lambda lo, hi: device_run_elements(res, el, lo, hi),
+                         f"serving batch submit (window time {iteration_us} us, unaligned {unaligned})")
+
+
+def test_batch_submit_errors(ctx):
+    ps = gen.make("serving", 4, start=3)
+    r2, f2 = ga.pack(ps.reads), ga.pack(ps.refs)
+    tags = np.arange(4, dtype=np.uint64)
+    with ga.Server(ctx, ps.k, ps.W, ps.O, pool_bases=1 << 16) as srv:
+        bad = ps.read_off.astype(np.uint64).copy()
+        bad[2], bad[3] = bad[3], bad[2]  # decreasing offsets: nothing queued
+        rc, acc = srv.submit_batch(r2, bad, f2, ps.ref_off, tags)
+        assert rc == ga.capi.E_INVAL and acc == 0
+        # k, W and O are fixed per server
+        acc_c = ctypes_u64()
+        ro, fo = ps.read_off.astype(np.uint64), ps.ref_off.astype(np.uint64)
+        assert ga.capi.lib().genasm_submit_batch(
+            srv._srv, r2.ctypes.data, ro.ctypes.data, f2.ctypes.data, fo.ctypes.data, 4, ps.k + 1,
+            ps.W, ps.O, tags.ctypes.data, acc_c) == ga.capi.E_INVAL
+        assert srv.stats()["submitted"] == 0
+
+
+def ctypes_u64():
+    import ctypes
+    return ctypes.byref(ctypes.c_uint64(0))
+
+
+def test_cancel(ctx):
+    # four slots, one window per pair per iteration, 300 requests: most wait
+    # on the host when cancelled, the first ones are resident. A request
+    # cancelled successfully never completes; every other one completes with
+    # the oracle's result, and the slots and pools drain.
+    ps = gen.make("serving", 300, start=7000)
+    want = expected(ps)
+    with ga.Server(ctx, ps.k, ps.W, ps.O, max_slots=4, window_budget=1) as srv:
+        tags = list(range(ps.n_pairs))
+        for t in tags:
+            assert srv.submit(ps.read(t), ps.ref(t), t) == 0
+        asked = [0, 1, 2, 3] + list(range(5, 300, 7))
+        rcs = {t: srv.cancel(t) for t in asked}
+        assert set(rcs.values()) <= {0, ga.capi.E_INVAL}
+        assert srv.cancel(10_000) == ga.capi.E_INVAL
+        cancelled = {t for t, rc in rcs.items() if rc == 0}
+        assert len(cancelled) >= 40
+        keep = [t for t in tags if t not in cancelled]
+        got = drain(srv, keep, timeout_s=240)
+        time.sleep(0.2)
+        assert not srv.poll(timeout_ms=50)
+        st = srv.stats()
+    assert not cancelled & set(got)
+    assert st["cancelled"] == len(cancelled) and st["completed"] == len(keep)
+    assert st["resident"] == 0 and st["pool_bases_used"] == 0
+    for t in keep:
+        assert as_tuple(got[t]) == want[t], t
