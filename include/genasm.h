@@ -425,9 +425,11 @@ typedef struct {
                                  0 = no limit (the window time alone ends its turn) */
     int32_t use_graph;        /* 1 = replay captured hipGraphs, 0 = launch the kernels
                                  directly; -1 or 0-initialised config: 1 */
-    int32_t iteration_us;     /* window time of an iteration in microseconds; 0 = 2000 while
-                                 requests wait or pairs occupy at least half of the window
-                                 groups, else 250 */
+    int32_t iteration_us;     /* window time of an iteration in microseconds (fixed);
+                                 0 = 2000, and while no request waits and pairs occupy fewer
+                                 than half of the window groups a pair's turn also ends from
+                                 250 on once a pair of the iteration has finished or a new
+                                 request has arrived */
     int32_t cigar_runs;       /* 0 = completions carry CIGAR text; 1 = run-length elements
                                  (GENASM_CIGAR_LEN/OP), as the device form writes them */
     int32_t reserved;

@@ -81,6 +81,14 @@ constexpr int32_t kSearchFailed = -1;  // no hit within K rows: the result is al
 constexpr int32_t kSearchDone = -2;    // empty read: the result is already written
 constexpr int32_t kSearchPending = -3; // not searched yet (retry list)
 
+// Turn limits of a serving iteration (device wall clock, 100 MHz), written at
+// its start. A resident pair's turn takes at least one window and starts none
+// at or past `end`; from `soon` on it also ends once a pair of the iteration
+// has finished or the host has counted more arrivals than `admitted`.
+struct TurnLimits {
+    unsigned long long end, soon, admitted;
+};
+
 struct AlignParams {
     const uint8_t* reads;       // 2-bit packed read stream
     const uint64_t* read_off;   // n_pairs + 1 base offsets
@@ -132,8 +140,8 @@ struct AlignParams {
     PairState* state;           // if set, window state persists here between launches
     uint32_t window_budget;     // windows a pair may advance per launch (0 = to the end)
     // Serving iterations (all null outside the serving form):
-    const unsigned long long* deadline;  // device wall clock (100 MHz) after which a pair
-                                         // starts no window past its first in this launch
+    const TurnLimits* turn;     // when a resident pair's turn in this launch ends
+    const unsigned long long* arrivals;  // requests the host has counted so far (device word)
     uint32_t* fin_list;         // pairs that ended in this launch (their result is written)
     uint32_t* fin_len;
     uint32_t* next_hot;         // unfinished pairs that advanced at most one window
@@ -187,7 +195,10 @@ constexpr int kCompactSpillRows = 64;
 inline uint64_t spill_words(uint64_t workers, int spill_rows, int stride) {
     return workers * (uint64_t)spill_rows * (uint64_t)stride + 1;
 }
-constexpr int kSearchGroupWords = 160;   // start search: PM, ring, broadcast slots
+// Start search group: PM and broadcast slots, then a ring of 128 text masks
+// kept twice (words kSearchRingOff + w and + 128 + w).
+constexpr int kSearchRingOff = 160;
+constexpr int kSearchGroupWords = kSearchRingOff + 256;
 
 // Kernel launchers (kernels.hip). All return hipError_t of the launch.
 hipError_t launch_plain(const AlignParams& p, hipStream_t s);
@@ -230,7 +241,9 @@ inline uint64_t search_item_cap(uint64_t n_pairs, uint64_t total_ref_bases, uint
 // each launch or graph replay) holds kServeParam* words.
 constexpr int kServeParamNew = 0;       // pairs admitted in this iteration
 constexpr int kServeParamTicks = 1;     // window time of the iteration, 100 MHz ticks (0 = none)
-constexpr int kServeParamWords = 4;
+constexpr int kServeParamSoonTicks = 2; // from then on the turn also ends on news (0 = at the end)
+constexpr int kServeParamAdmitted = 3;  // arrivals admitted so far (low word; high word at 4)
+constexpr int kServeParamWords = 8;
 // One admitted request: its slot and where its bases and CIGAR go in the pools.
 struct ServeAdmit {
     uint64_t read_off, ref_off, run_base;
@@ -252,8 +265,8 @@ struct ServeSlots {
 hipError_t launch_serve_begin(uint32_t* cur, uint32_t* next, uint32_t* fin_len,
                               const uint32_t* params, const ServeAdmit* admit, ServeSlots slots,
                               uint32_t* new_list, hipStream_t s);
-// Sets *deadline = now + the iteration's window time (or ~0 when it is 0).
-hipError_t launch_serve_stamp(const uint32_t* params, unsigned long long* deadline, hipStream_t s);
+// Writes the iteration's turn limits from the parameter block and the device clock.
+hipError_t launch_serve_stamp(const uint32_t* params, TurnLimits* turn, hipStream_t s);
 // Ends an iteration: the finished pairs' CIGAR offsets (a prefix sum over
 // their element counts) into fin_off, their slots and results (cigar_off =
 // that offset) into the host-mapped summary (hdr[0] = count, hdr[1] = total

@@ -68,15 +68,25 @@ constexpr int kDppWaveShr1 = 0x138;
 constexpr int kDppWaveRor1 = 0x13C;
 
 template <int G> struct LaneShift;
+// A rotation writes every lane, so it needs no `old` value (and no copy of the
+// source into the destination first).
+template <int CTRL>
+__device__ __forceinline__ u64 dpp64_rot(u64 src) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)src, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(src >> 32), CTRL, 0xF,
+                                                           0xF, false);
+    return ((u64)hi << 32) | lo;
+}
+
 template <> struct LaneShift<16> {
     // value of lane gl-1 within the 16-lane group; lane 0 gets `old`
     static __device__ __forceinline__ u64 up(u64 old, u64 v) { return dpp64<kDppRowShr1>(old, v); }
     // value of lane gl-1, lane 0 gets lane 15 (rotation inside the group)
-    static __device__ __forceinline__ u64 rot(u64 v) { return dpp64<kDppRowRor1>(v, v); }
+    static __device__ __forceinline__ u64 rot(u64 v) { return dpp64_rot<kDppRowRor1>(v); }
 };
 template <> struct LaneShift<64> {
     static __device__ __forceinline__ u64 up(u64 old, u64 v) { return dpp64<kDppWaveShr1>(old, v); }
-    static __device__ __forceinline__ u64 rot(u64 v) { return dpp64<kDppWaveRor1>(v, v); }
+    static __device__ __forceinline__ u64 rot(u64 v) { return dpp64_rot<kDppWaveRor1>(v); }
 };
 // Two 32-lane groups per wavefront: a shift over the whole wavefront, after
 // which lane 32 holds lane 31's value; shift_up gives it `old` instead.
@@ -152,7 +162,7 @@ constexpr int OFF_BC = 154;    // broadcast slots (4 words)
 // and the group's last row has an end word of its own.
 constexpr int OFF_TAB = 158;
 static_assert(OFF_TAB == kGroupHeaderWords, "layout");
-constexpr int OFF_RING = 4;    // start search: 128-word text-mask ring (reuses PMT + BROW)
+static_assert(OFF_BC + 4 <= kSearchRingOff, "layout");
 
 // Layout of a 16-lane window group (in step order, so that a DC step needs no
 // address arithmetic): PMT16[x] = PM[T[nw-1-x]] at word OFF_PMT16 + x for
@@ -433,39 +443,82 @@ __device__ __forceinline__ void fill_brow(u64* lds, const u64* spill, int gl, in
 // Start search: rows 0.. of the first read window against the whole reference
 // ---------------------------------------------------------------------------
 
+// Bits 0, 2, 4, .. of w into the low half and bits 1, 3, 5, .. into the high
+// half (bit 2k to bit k, bit 2k+1 to bit 32+k).
+__device__ __forceinline__ u64 split_even_odd(u64 w) {
+    auto compress = [](u64 x) -> u64 {
+        x &= 0x5555555555555555ull;
+        x = (x | (x >> 1)) & 0x3333333333333333ull;
+        x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+        x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+        x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+        return (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+    };
+    return compress(w) | (compress(w >> 1) << 32);
+}
+
+// keep ? hit : t, bitwise (keep is all ones or zero), in one v_bfi_b32.
+__device__ __forceinline__ int keep_or(int keep, int hit, int t) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    int r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(keep), "v"(hit), "s"(t));
+    return r;
+#else
+    return (keep & hit) | (~keep & t);
+#endif
+}
+
 // RS rows per lane: slot s of lane gl is row s*G + gl, lagging slot s-1 by G
 // steps; lane 0 of slot s takes lane G-1 of slot s-1 through the rotation.
 // Returns (in *row, *col) the least row <= Kr with a hit and its leftmost
 // column, or row = -1 when rows 0..min(Kr, RS*G-1) have none.
+//
+// Word form. The pattern sits in the top bits: with a = 64 - m1, bit q + a
+// stands for bit q of the usual form and bits below a stay 0 (pattern
+// positions that match every base: zero masks and initial bits, and the zero
+// that a left shift brings in keeps them zero), so the top pattern bit is bit
+// 63 for every read. Each word is kept as its even bits E and odd bits O (bit
+// 2k in E bit k, bit 2k+1 in O bit k): a left shift by one is then E' = O << 1,
+// O' = E, one 32-bit shift instead of a 64-bit one, and bit 63 is the sign of
+// O. The recurrence is unchanged bit for bit.
 template <int G, int RS>
 __device__ void search_rows(u64* lds, int gl, int lane, const uint8_t* refs, uint64_t fb, int n,
                             int m1, int Kr, int* row_out, int* col_out, int out_hi = 0x7fffffff) {
-    const u64 p0 = lds[OFF_PM + 0], p1 = lds[OFF_PM + 1], p2 = lds[OFF_PM + 2],
-              p3 = lds[OFF_PM + 3];
-    u64* ring = lds + OFF_RING;
+    static_assert(G == 16 || G == 64, "search groups of 16 or 64 lanes");
     constexpr int BPL = 64 / G;  // text bases each lane converts per 64-column block
     constexpr int O = RS * G;
-    const int top = m1 - 1;
-    // columns n..n+63 lie past the text end: the all-mismatch mask. Word 128
-    // repeats word 0, so that the entries of two consecutive steps are always
-    // adjacent words (one paired read)
+    constexpr int kRot = G == 16 ? kDppRowRor1 : kDppWaveRor1;
+    const int a = 64 - m1;
+    const u64 p0 = split_even_odd(lds[OFF_PM + 0] << a), p1 = split_even_odd(lds[OFF_PM + 1] << a),
+              p2 = split_even_odd(lds[OFF_PM + 2] << a), p3 = split_even_odd(lds[OFF_PM + 3] << a);
+    // text masks by column i at ring word (-i) & 127, and again 128 words on:
+    // the steps of a block read increasing words
+    u64* ring = lds + kSearchRingOff;
+    // columns n..n+63 lie past the text end: the all-mismatch mask
+    const u64 past = split_even_odd(~0ull << a);
 #pragma unroll
     for (int u = 0; u < BPL; ++u) {
-        const int w = (n + gl * BPL + u) & 127;
-        ring[w] = ~0ull;
-        if (w == 0) ring[128] = ~0ull;
+        const int w = (-(n + gl * BPL + u)) & 127;
+        ring[w] = past;
+        ring[w + 128] = past;
     }
 
-    u64 R[RS], Dp[RS];
-    int hit[RS];
+    uint32_t RE[RS], RO[RS], DE[RS], DO[RS];
+    int hit[RS];  // step of the last hit (leftmost column so far), -1 before any
 #pragma unroll
     for (int s = 0; s < RS; ++s) {
         const int d = s * G + gl;
-        R[s] = init_word(d);
-        Dp[s] = d == 0 ? ~0ull : init_word(d - 1);
+        const u64 r = split_even_odd(init_word(d) << a);
+        const u64 dp = d == 0 ? ~0ull : split_even_odd(init_word(d - 1) << a);
+        RE[s] = (uint32_t)r;
+        RO[s] = (uint32_t)(r >> 32);
+        DE[s] = (uint32_t)dp;
+        DO[s] = (uint32_t)(dp >> 32);
         hit[s] = -1;
     }
-    const u64 lowin = gl == 0 ? 1ull : 0ull;  // slot 0 only
+    // lane 0 of slot 0 (row 0) has no row above: all ones, and a one shifted in
+    const uint32_t top = gl == 0 ? ~0u : 0u;
+    const uint32_t lowin = gl == 0 ? 1u : 0u;
 
     auto fetch = [&](int blk) -> unsigned {
         const int c0 = n - 64 * (blk + 1) + gl * BPL;
@@ -480,52 +533,90 @@ __device__ void search_rows(u64* lds, int gl, int lane, const uint8_t* refs, uin
 
     const int steps = n + O - 1;
     const int nblk = (steps + 63) / 64;
-    u64 pm_pair[RS][2];
     unsigned cur = fetch(0);
+    // One block of 64 steps. Slot s of lane gl is at column b - tt at step tt
+    // of the block (b = n-1-t0+s*G+gl): ring word ((-b) & 127) + tt, one base
+    // address per block, constant offsets, two steps per paired read. EDGE:
+    // some lane's column lies outside [0, out_hi) at some step, so hits are
+    // range-checked.
+    auto block = [&](int t0, auto edge) {
+        const u64* rp[RS];
+#pragma unroll
+        for (int s = 0; s < RS; ++s) rp[s] = ring + ((-(n - 1 - t0 + s * G + gl)) & 127);
+        uint32_t pmE[RS][2], pmO[RS][2];
+#pragma unroll 8
+        for (int tt = 0; tt < 64; ++tt) {
+            const int t = t0 + tt;
+            uint32_t rE[RS], rO[RS];
+#pragma unroll
+            for (int s = 0; s < RS; ++s) {
+                rE[s] = (uint32_t)__builtin_amdgcn_mov_dpp((int)RE[s], kRot, 0xF, 0xF, false);
+                rO[s] = (uint32_t)__builtin_amdgcn_mov_dpp((int)RO[s], kRot, 0xF, 0xF, false);
+            }
+            if ((tt & 1) == 0) {
+#pragma unroll
+                for (int s = 0; s < RS; ++s) {
+                    const u64 c0 = rp[s][tt], c1 = rp[s][tt + 1];
+                    pmE[s][0] = (uint32_t)c0;
+                    pmO[s][0] = (uint32_t)(c0 >> 32);
+                    pmE[s][1] = (uint32_t)c1;
+                    pmO[s][1] = (uint32_t)(c1 >> 32);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < RS; ++s) {
+                // the row above at this column: the rotation, with lane 0 taking
+                // all ones (slot 0) or lane G-1 of the slot before
+                uint32_t uE, uO;
+                if (s == 0) {
+                    uE = rE[0] | top;
+                    uO = rO[0] | top;
+                } else {
+                    uE = (top & rE[s - 1]) | (~top & rE[s]);
+                    uO = (top & rO[s - 1]) | (~top & rO[s]);
+                }
+                // x = D & (((D & up) << 1) | low); R = x & ((R << 1) | PM)
+                const uint32_t eE = DE[s] & uE, eO = DO[s] & uO;
+                const uint32_t xE = DE[s] & ((eO << 1) | (s == 0 ? lowin : 0u)), xO = DO[s] & eE;
+                const uint32_t sE = (RO[s] << 1) | pmE[s][tt & 1], sO = RE[s] | pmO[s][tt & 1];
+                RE[s] = xE & sE;
+                RO[s] = xO & sO;
+                DE[s] = uE;
+                DO[s] = uO;
+                if constexpr (decltype(edge)::value) {
+                    const int i = n - 1 - t + s * G + gl;
+                    const bool h = (int)RO[s] >= 0 && i >= 0 && i < out_hi;
+                    hit[s] = h ? t : hit[s];
+                } else {
+                    hit[s] = keep_or((int)RO[s] >> 31, hit[s], t);  // all ones: no hit
+                }
+            }
+        }
+    };
+    // block b covers steps 64b..64b+63; lane gl of slot s is at column
+    // n-1-t+s*G+gl, so the block is interior when 64b+63 <= n-1 (every column
+    // >= 0) and n-1-64b+RS*G-1 < out_hi
     for (int blk = 0; blk < nblk; ++blk) {
         // fill ring entries of this block's columns, prefetch the next block's bases
         const int c0 = n - 64 * (blk + 1) + gl * BPL;
 #pragma unroll
         for (int u = 0; u < BPL; ++u) {
-            const int col = c0 + u;
+            const int w = (-(c0 + u)) & 127;
             const u64 v = pick_pm(p0, p1, p2, p3, (cur >> (2 * u)) & 3);
-            ring[col & 127] = v;
-            if ((col & 127) == 0) ring[128] = v;
+            ring[w] = v;
+            ring[w + 128] = v;
         }
         cur = fetch(blk + 1);
         wave_sync();
         const int t0 = blk * 64;
-#pragma unroll 4
-        for (int tt = 0; tt < 64; ++tt) {
-            const int t = t0 + tt;
-            u64 rot[RS];
-#pragma unroll
-            for (int s = 0; s < RS; ++s) rot[s] = LaneShift<G>::rot(R[s]);
-            // even steps read the entries of this step and the next as one pair
-            // (columns i and i-1: words (i-1)&127 + 1 and (i-1)&127)
-            if ((tt & 1) == 0) {
-#pragma unroll
-                for (int s = 0; s < RS; ++s) {
-                    const int b = (n - 2 - t + s * G + gl) & 127;
-                    pm_pair[s][0] = ring[b + 1];
-                    pm_pair[s][1] = ring[b];
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < RS; ++s) {
-                const int i = n - 1 - t + s * G + gl;
-                const u64 pm_t = pm_pair[s][tt & 1];
-                const u64 up = gl == 0 ? (s == 0 ? ~0ull : rot[s - 1]) : rot[s];
-                const u64 li = s == 0 ? lowin : 0ull;
-                const u64 x = Dp[s] & (((Dp[s] & up) << 1) | li);
-                R[s] = x & ((R[s] << 1) | pm_t);
-                Dp[s] = up;
-                const bool h = i >= 0 && i < out_hi && !((R[s] >> top) & 1ull);
-                hit[s] = h ? i : hit[s];
-            }
-        }
+        const bool interior = t0 + 63 <= n - 1 && n - 1 - t0 + O - 1 < out_hi;
+        if (interior) block(t0, std::integral_constant<bool, false>{});
+        else block(t0, std::integral_constant<bool, true>{});
         wave_sync();
     }
+    // steps of the hits to their columns
+#pragma unroll
+    for (int s = 0; s < RS; ++s) hit[s] = hit[s] >= 0 ? n - 1 - hit[s] + s * G + gl : -1;
     // least row with a hit
     int row = -1;
 #pragma unroll
@@ -731,6 +822,40 @@ __device__ __forceinline__ PairState fresh_state(int s) {
     return PairState{s, 0, 0, 0u, 0u, -1, 0u, kStateStarted};
 }
 
+// A resident pair's turn in a serving iteration (inactive elsewhere). The
+// device clock is read by a scalar instruction and the two counters are made
+// wave-uniform, so every lane of a group takes the same branch. The counters
+// are looked at no more often than every kTurnLookTicks per group: the
+// arrival count is written by a host-to-device copy while the kernel runs, so
+// it is read past the caches.
+constexpr u64 kTurnLookTicks = 2000;  // 20 us
+struct TurnClock {
+    u64 end = 0, soon = 0, admitted = 0, next_look = 0;
+    const unsigned long long* arrivals = nullptr;
+    const uint32_t* fin_len = nullptr;
+    bool active = false;
+    __device__ __forceinline__ void open(const AlignParams& P) {
+        if (!P.turn) return;
+        const TurnLimits t = *P.turn;
+        end = t.end;
+        soon = t.soon;
+        admitted = t.admitted;
+        arrivals = P.arrivals;
+        fin_len = P.fin_len;
+        active = true;
+    }
+    // Whether the turn has ended (asked before every window but the first).
+    __device__ __forceinline__ bool over() {
+        const u64 now = wall_clock64();
+        if (now >= end) return true;
+        if (now < soon || now < next_look) return false;
+        next_look = now + kTurnLookTicks;
+        const u64 a = arrivals ? __hip_atomic_load(arrivals, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0ull;
+        const uint32_t f = fin_len ? __hip_atomic_load(fin_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        return __builtin_amdgcn_readfirstlane((int)(a > admitted || f > 0u)) != 0;
+    }
+};
+
 // Advances one pair whose window state is `st` by at most `budget` windows
 // (0: to the end). All G lanes of the group call this together; lane 0 holds
 // the traceback-side fields (score, open run). When the pair ends (read
@@ -739,7 +864,7 @@ __device__ __forceinline__ PairState fresh_state(int s) {
 template <int G>
 __device__ __forceinline__ uint32_t advance_pair(const AlignParams& P, u64* lds, u64* spill, int lds_rows, int gl,
                              int lane, uint64_t pair, const PairCursor& pc, int s, PairState& st,
-                             uint32_t budget, u64 deadline) {
+                             uint32_t budget, TurnClock& turn) {
     const uint64_t run_base = pair_run_base(P, pair);
     const uint64_t run_limit = min(P.cigar_cap, run_base + (uint64_t)pc.m + (uint64_t)pc.n);
     uint32_t* runs = reinterpret_cast<uint32_t*>(lds + runs_off<G>());
@@ -767,10 +892,8 @@ __device__ __forceinline__ uint32_t advance_pair(const AlignParams& P, u64* lds,
     while (st.pj < pc.m && (budget == 0 || done_here < budget)) {
         // every pair advances at least one window per launch (so that a late
         // start never leaves a pair without progress); no further window
-        // starts once the deadline has passed. The device clock is read by a
-        // scalar instruction: one value per wavefront, so every lane of the
-        // group takes the same branch.
-        if (deadline && done_here > 0 && wall_clock64() >= deadline) break;
+        // starts once its turn has ended
+        if (turn.active && done_here > 0 && turn.over()) break;
         if (st.nwin >= max_windows) { failed = true; internal = true; break; }
         const int mw = min(P.W, pc.m - st.pj);
         const int nw = min(P.W, pc.n - st.ti);
@@ -919,15 +1042,17 @@ __device__ __forceinline__ void run_pair(const AlignParams& P, u64* lds, u64* sp
     const PairCursor pc = pair_cursor(P, pair);
     if (!P.state) {
         PairState st = fresh_state(s);
-        advance_pair<G>(P, lds, spill, lds_rows, gl, lane, pair, pc, s, st, 0u, 0ull);
+        TurnClock none;
+        advance_pair<G>(P, lds, spill, lds_rows, gl, lane, pair, pc, s, st, 0u, none);
         return;
     }
     PairState st = P.state[pair];
     if (st.flags & kStateDone) return;
     if (!(st.flags & kStateStarted)) st = fresh_state(s);
-    const u64 deadline = P.deadline ? *P.deadline : 0ull;
+    TurnClock turn;
+    turn.open(P);
     const uint32_t advanced =
-        advance_pair<G>(P, lds, spill, lds_rows, gl, lane, pair, pc, s, st, P.window_budget, deadline);
+        advance_pair<G>(P, lds, spill, lds_rows, gl, lane, pair, pc, s, st, P.window_budget, turn);
     if (gl == 0) {
         P.state[pair] = st;
         // serving: the pair's list for the next iteration (hot: its turn was
@@ -1360,8 +1485,15 @@ __global__ __launch_bounds__(64) void k_unimproved(AlignParams P, u64* table) {
 
 // Pops one item per group from a device queue; returns the same value in all
 // lanes of the group.
-__device__ __forceinline__ uint32_t group_pop(uint32_t* head, u64* lds, int gl) {
-    if (gl == 0) lds[OFF_BC + 3] = atomicAdd(head, 1u);
+// Once the list is drained a plain load of the head says so, and the group
+// returns without an atomic: thousands of groups finding an empty list would
+// otherwise serialize on the one counter (tens of microseconds per launch).
+__device__ __forceinline__ uint32_t group_pop(uint32_t* head, u64* lds, int gl, uint32_t n) {
+    if (gl == 0) {
+        uint32_t v = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v < n) v = atomicAdd(head, 1u);
+        lds[OFF_BC + 3] = v;
+    }
     wave_sync();
     const uint32_t v = (uint32_t)lds[OFF_BC + 3];
     wave_sync();
@@ -1414,7 +1546,7 @@ __global__ __launch_bounds__(64) void k_search(AlignParams P) {
     const int rows_before = P.list_slot == 0 ? 0 : (P.list_slot == 1 ? 16 : 32);
     // A group takes at most n_items items, which bounds the loop.
     for (uint32_t iter = 0; iter <= n_items; ++iter) {
-        const uint32_t item = group_pop(head, lds, gl);
+        const uint32_t item = group_pop(head, lds, gl, n_items);
         if (item >= n_items) break;
         const uint64_t it = P.items_in[item];
         const uint64_t pair = it >> 24;
@@ -1553,7 +1685,7 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
         const bool hard = (phase == 0) == hard_first;
         if (hard && P.hard_lanes == 64) {
             for (uint32_t iter = 0; iter <= n_hard; ++iter) {
-                const uint32_t item = group_pop(P.counters + kCounterHardHead, smem, lane);
+                const uint32_t item = group_pop(P.counters + kCounterHardHead, smem, lane, n_hard);
                 if (item >= n_hard) break;
                 const uint64_t pair = P.hard_list[item];
                 const SearchOut so = P.search[pair];
@@ -1572,7 +1704,7 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
             u64* spill32 = P.spill + ((uint64_t)blockIdx.x * 4 + 2 * h) *
                                          (uint64_t)(64 - P.lds_rows) * P.stride;
             for (uint32_t iter = 0; iter <= n_hard; ++iter) {
-                const uint32_t item = group_pop(P.counters + kCounterHardHead, lds32, gl32);
+                const uint32_t item = group_pop(P.counters + kCounterHardHead, lds32, gl32, n_hard);
                 if (item >= n_hard) break;
                 const uint64_t pair = P.hard_list[item];
                 const SearchOut so = P.search[pair];
@@ -1585,7 +1717,7 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
         const uint32_t n = hard ? n_hard : n_easy;
         uint32_t* head = P.counters + (hard ? kCounterHardHead : kCounterEasyHead);
         for (uint32_t iter = 0; iter <= n; ++iter) {
-            const uint32_t item = group_pop(head, lds, gl);
+            const uint32_t item = group_pop(head, lds, gl, n);
             if (item >= n) break;
             const uint64_t pair = list[item];
             const SearchOut so = P.search[pair];
@@ -1751,7 +1883,7 @@ template <bool STATS>
 __device__ __forceinline__ uint32_t advance_pair_c(const AlignParams& P, u64* lds, u64* spill, int gl,
                                                    int lane, uint64_t pair, const PairCursor& pc,
                                                    int s, PairState& st, uint32_t budget,
-                                                   u64 deadline) {
+                                                   TurnClock& turn) {
     constexpr int G = 16;
     const uint64_t run_base = pair_run_base(P, pair);
     const uint64_t run_limit = min(P.cigar_cap, run_base + (uint64_t)pc.m + (uint64_t)pc.n);
@@ -1777,8 +1909,8 @@ __device__ __forceinline__ uint32_t advance_pair_c(const AlignParams& P, u64* ld
         seq_open(fc, P.ref_lo, P.ref_hi, pc.fb - forg + st.ti);
     }
     while (st.pj < pc.m && (budget == 0 || done_here < budget)) {
-        // see advance_pair: at least one window per launch, none started past the deadline
-        if (deadline && done_here > 0 && wall_clock64() >= deadline) break;
+        // see advance_pair: at least one window per launch, none once the turn has ended
+        if (turn.active && done_here > 0 && turn.over()) break;
         if (st.nwin >= max_windows) { failed = true; internal = true; break; }
         const int mw = min(P.W, pc.m - st.pj);
         const int nw = min(P.W, pc.n - st.ti);
@@ -1942,15 +2074,17 @@ __device__ __forceinline__ void run_pair_c(const AlignParams& P, u64* lds, u64* 
     if (!P.state) {
         PairState st = fresh_state(s);
         if (deep_start) st.flags |= kStateDeep;
-        advance_pair_c<STATS>(P, lds, spill, gl, lane, pair, pc, s, st, 0u, 0ull);
+        TurnClock none;
+        advance_pair_c<STATS>(P, lds, spill, gl, lane, pair, pc, s, st, 0u, none);
         return;
     }
     PairState st = P.state[pair];
     if (st.flags & kStateDone) return;
     if (!(st.flags & kStateStarted)) st = fresh_state(s);
-    const u64 deadline = P.deadline ? *P.deadline : 0ull;
+    TurnClock turn;
+    turn.open(P);
     const uint32_t advanced =
-        advance_pair_c<STATS>(P, lds, spill, gl, lane, pair, pc, s, st, P.window_budget, deadline);
+        advance_pair_c<STATS>(P, lds, spill, gl, lane, pair, pc, s, st, P.window_budget, turn);
     if (gl == 0) {
         P.state[pair] = st;
         if (P.fin_list) {
@@ -1986,7 +2120,7 @@ __global__ __launch_bounds__(64) void k_windows_c(AlignParams P) {
         const uint32_t n = hard ? n_hard : n_easy;
         uint32_t* head = P.counters + (hard ? kCounterHardHead : kCounterEasyHead);
         for (uint32_t iter = 0; iter <= n; ++iter) {
-            const uint32_t item = group_pop(head, lds, gl);
+            const uint32_t item = group_pop(head, lds, gl, n);
             if (item >= n) break;
             const uint64_t pair = list[item];
             const SearchOut so = P.search[pair];
@@ -2181,9 +2315,14 @@ __global__ void k_serve_begin(uint32_t* cur, uint32_t* next, uint32_t* fin_len,
     }
 }
 
-__global__ void k_serve_stamp(const uint32_t* params, u64* deadline) {
-    const uint32_t ticks = params[kServeParamTicks];
-    *deadline = ticks ? wall_clock64() + ticks : ~0ull;
+__global__ void k_serve_stamp(const uint32_t* params, TurnLimits* turn) {
+    const u64 now = wall_clock64();
+    const uint32_t ticks = params[kServeParamTicks], soon = params[kServeParamSoonTicks];
+    TurnLimits t;
+    t.end = ticks ? now + ticks : ~0ull;
+    t.soon = soon && (!ticks || soon < ticks) ? now + soon : t.end;
+    t.admitted = (u64)params[kServeParamAdmitted] | ((u64)params[kServeParamAdmitted + 1] << 32);
+    *turn = t;
 }
 
 // Serving iteration end, part 1 (one block of 1024 threads): prefix sum of the
@@ -2325,7 +2464,11 @@ __global__ void k_compact(const genasm_result* out, const uint64_t* dst_off, uin
 // Launchers
 // ---------------------------------------------------------------------------
 
-int plain_lds_bytes(int stride) { return window_group_words(64, stride) * 8; }
+// The plain and unimproved kernels run the start search in their group's LDS first.
+int plain_lds_bytes(int stride) {
+    const int w = window_group_words(64, stride);
+    return (w > kSearchGroupWords ? w : kSearchGroupWords) * 8;
+}
 int window_lds_bytes(int lds_rows, int stride) {
     const int easy = 4 * window_group_words(lds_rows, stride);
     const int hard = window_group_words(64, stride);
@@ -2442,8 +2585,8 @@ hipError_t launch_serve_begin(uint32_t* cur, uint32_t* next, uint32_t* fin_len,
     return hipGetLastError();
 }
 
-hipError_t launch_serve_stamp(const uint32_t* params, unsigned long long* deadline, hipStream_t s) {
-    hipLaunchKernelGGL(k_serve_stamp, dim3(1), dim3(1), 0, s, params, deadline);
+hipError_t launch_serve_stamp(const uint32_t* params, TurnLimits* turn, hipStream_t s) {
+    hipLaunchKernelGGL(k_serve_stamp, dim3(1), dim3(1), 0, s, params, turn);
     return hipGetLastError();
 }
 

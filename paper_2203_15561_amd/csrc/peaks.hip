@@ -82,12 +82,15 @@ __global__ __launch_bounds__(256) void k_peak_lds(const unsigned* in, unsigned* 
     for (int w = t; w < kLdsWords; w += blockDim.x)
         buf[w] = make_uint4(in[0] + w, in[1] ^ w, w, ~w);
     __syncthreads();
+    // the index step comes from memory (256 at run time), so the compiler
+    // cannot see that the reads repeat and keep them in registers
+    const int inc = 256 + (int)((in[3] & 1u) << 8);
     unsigned acc = 0;
     int idx = t;
     for (int s = 0; s < kLdsSteps; ++s) {
         const uint4 v = buf[idx];
         acc ^= v.x ^ v.y ^ v.z ^ v.w;
-        idx = (idx + 256) & (kLdsWords - 1);
+        idx = (idx + inc) & (kLdsWords - 1);
     }
     out[blockIdx.x * blockDim.x + t] = acc;
 }

@@ -34,11 +34,12 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
+#include <set>
 #include <string>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
@@ -67,9 +68,9 @@ class RangeAlloc {
     }
     bool alloc(uint64_t len, uint64_t* start) {
         if (len == 0) { *start = 0; return true; }
-        auto it = by_len_.lower_bound(len);
+        auto it = by_len_.lower_bound({len, 0});
         if (it == by_len_.end()) return false;
-        const uint64_t s0 = it->second, have = it->first;
+        const uint64_t have = it->first, s0 = it->second;
         erase(s0, have);
         if (have > len) insert(s0 + len, have - len);
         *start = s0;
@@ -105,14 +106,14 @@ class RangeAlloc {
         by_start_[s0] = len;
         by_len_.emplace(len, s0);
     }
+    // (length, start) keys: many free ranges share a length (requests of one
+    // size), and each is found directly rather than by a scan of its length
     void erase(uint64_t s0, uint64_t len) {
         by_start_.erase(s0);
-        auto r = by_len_.equal_range(len);
-        for (auto it = r.first; it != r.second; ++it)
-            if (it->second == s0) { by_len_.erase(it); break; }
+        by_len_.erase({len, s0});
     }
     std::map<uint64_t, uint64_t> by_start_;
-    std::multimap<uint64_t, uint64_t> by_len_;
+    std::set<std::pair<uint64_t, uint64_t>> by_len_;
     uint64_t used_ = 0;
 };
 
@@ -120,17 +121,34 @@ constexpr uint64_t kBaseUnit = 64;  // pool allocations in bases: whole bit-plan
 
 uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
-// A queued request: the read's packed bytes, then the reference's.
+// A queued request: its read's packed bytes, then its reference's, at `off`
+// in a byte block shared by the requests of one submission call (one host
+// allocation per call rather than per request).
 struct Request {
-    std::vector<uint8_t> bytes;
+    std::shared_ptr<std::vector<uint8_t>> block;
+    uint64_t off = 0;
     uint32_t m = 0, n = 0;
     uint64_t tag = 0, submit_ns = 0;
+    uint64_t read_bytes() const { return ((uint64_t)m + 3) / 4; }
+    uint64_t bytes() const { return read_bytes() + ((uint64_t)n + 3) / 4; }
+    const uint8_t* data() const { return block->data() + off; }
+};
+
+// A finished request on its way to the caller: the CIGAR elements stay in the
+// iteration's gathered block until a poll copies or formats them (in the
+// polling thread, not the engine's).
+struct DoneRec {
+    uint64_t tag;
+    genasm_result result;  // cigar_off: element offset in `block`; cigar_len: elements
+    uint64_t submit_ns, admit_ns, done_ns;
+    std::shared_ptr<std::vector<uint32_t>> block;
 };
 
 struct Slot {
     uint64_t tag = 0, submit_ns = 0, admit_ns = 0;
-    uint64_t rstart = 0, rlen = 0, fstart = 0, flen = 0;  // pool ranges (bases)
-    uint64_t cstart = 0, clen = 0;                        // CIGAR pool range (elements)
+    uint64_t bstart = 0, blen = 0;  // base pool range (bases): the read, then the reference
+    uint64_t fstart = 0;            // where the reference starts in it
+    uint64_t cstart = 0, clen = 0;  // CIGAR pool range (elements)
 };
 
 template <class T>
@@ -202,7 +220,9 @@ struct genasm_server {
     uint64_t* d_fin_off = nullptr;
     uint64_t* d_items = nullptr;             // two start-search item lists
     unsigned long long* d_key = nullptr;     // per-slot search key
-    unsigned long long* d_deadline = nullptr;
+    TurnLimits* d_turn = nullptr;            // the running iteration's turn limits
+    unsigned long long* d_arrivals = nullptr;  // arrival count, copied from h_arrivals
+    unsigned long long* h_arrivals = nullptr;  // pinned
     uint64_t item_cap = 0;
     unsigned long long* d_spill = nullptr;
     uint64_t upload_cap = 0;
@@ -218,9 +238,11 @@ struct genasm_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request> pending;
-    std::deque<genasm_completion> done;
-    std::unordered_multimap<uint64_t, uint32_t> tag_slot;  // resident requests by tag
-    std::vector<uint8_t> slot_cancelled;                    // resident request cancelled
+    uint64_t arrivals = 0;               // requests accepted so far
+    bool signalled = false;              // arrivals copied to the device since the last admission
+    std::deque<DoneRec> done;
+    std::vector<uint64_t> slot_tag;      // resident request per slot (mu): tag,
+    std::vector<uint8_t> slot_state;     // and 0 free, 1 resident, 2 resident and cancelled
     std::thread engine;
     bool stop = false;
     int error = GENASM_OK;
@@ -280,12 +302,13 @@ hipError_t enqueue_iteration(genasm_server* srv, int q) {
     if ((e = launch_search(S, 16, 4, srv->search_blocks, s))) return e;
     if ((e = launch_search_finalize(S, NS, s))) return e;
     // windows until the iteration's deadline
-    if ((e = launch_serve_stamp(b.d_params, srv->d_deadline, s))) return e;
+    if ((e = launch_serve_stamp(b.d_params, srv->d_turn, s))) return e;
     AlignParams P = srv->base;
     P.counters = b.d_cnt;
     P.easy_list = b.d_hot;
     P.hard_list = b.d_cold;
-    P.deadline = srv->d_deadline;
+    P.turn = srv->d_turn;
+    P.arrivals = srv->d_arrivals;
     P.next_hot = nb.d_hot;
     P.next_cold = nb.d_cold;
     P.next_len = nb.d_cnt;
@@ -367,7 +390,8 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     D(srv->d_out, NS); D(srv->d_state, NS); D(srv->d_search, NS);
     D(srv->d_new, NS); D(srv->d_fin, NS); D(srv->d_fin_len, 4); D(srv->d_fin_off, NS);
     srv->item_cap = search_item_cap(NS, cfg.pool_bases, kServeSearchChunk);
-    D(srv->d_items, 2 * srv->item_cap); D(srv->d_key, NS); D(srv->d_deadline, 1);
+    D(srv->d_items, 2 * srv->item_cap); D(srv->d_key, NS); D(srv->d_turn, 1);
+    D(srv->d_arrivals, 1); H(srv->h_arrivals, 1);
     D(srv->d_spill, spill_words(workers, kCompactSpillRows, stride));
     for (IterBufs& b : srv->it) {
         H(b.h_upload, srv->upload_cap); D(b.d_upload, srv->upload_cap);
@@ -453,7 +477,8 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     srv->pool.reset(cfg.pool_bases);
     srv->cigpool.reset(cfg.pool_bases);
     srv->slots.resize(NS);
-    srv->slot_cancelled.assign(NS, 0);
+    srv->slot_tag.assign(NS, 0);
+    srv->slot_state.assign(NS, 0);
     for (uint32_t i = NS; i-- > 0;) srv->free_slots.push_back(i);
     srv->engine = std::thread(engine_main, srv);
     *out = srv;
@@ -465,6 +490,29 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
 namespace {
 
 // Checks one request's sizes against the server's pools.
+// Counts accepted requests (mu held) and, once per admission, copies the count
+// to the device, where a running iteration's turns look for news (a turn may
+// then end early and let the engine admit the new requests sooner). The copy
+// runs on the copy stream beside the running kernels; if it cannot be queued
+// the next submission tries again.
+void note_arrivals(genasm_server* srv, uint64_t n) {
+    srv->arrivals += n;
+    *srv->h_arrivals = srv->arrivals;
+    if (srv->signalled) return;
+    int dev = -1;
+    const bool switch_dev = hipGetDevice(&dev) != hipSuccess || dev != srv->ctx->device;
+    if (switch_dev && hipSetDevice(srv->ctx->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    if (hipMemcpyAsync(srv->d_arrivals, srv->h_arrivals, sizeof(unsigned long long),
+                       hipMemcpyHostToDevice, srv->s_copy) == hipSuccess)
+        srv->signalled = true;
+    else
+        (void)hipGetLastError();
+    if (switch_dev && dev >= 0) (void)hipSetDevice(dev);
+}
+
 int check_request(const genasm_server* srv, uint64_t m, uint64_t n) {
     const uint64_t need = round_up(m, kBaseUnit) + round_up(n, kBaseUnit);
     if (m > 0x7fffffffull || n > 0x7fffffffull || need > srv->cfg.pool_bases ||
@@ -482,14 +530,14 @@ void copy_bases(uint8_t* dst, const uint8_t* src, uint64_t b0, uint64_t nb) {
     if (sh == 0) {
         std::memcpy(dst, s, bytes);
     } else {
-        // the last byte's high part may read one byte past the range's end;
-        // take it only when the range extends into that byte
+        // a byte takes its high part from the next source byte, which exists
+        // for every byte but (possibly) the last: the range's last source byte
+        // is `last - 1`, and no byte past it is read
         const uint64_t last = (b0 + nb + 3) / 4 - b0 / 4;  // source bytes the bases touch
-        for (uint64_t j = 0; j < bytes; ++j) {
-            const unsigned lo = s[j] >> sh;
-            const unsigned hi = j + 1 < last ? (unsigned)s[j + 1] << (8 - sh) : 0u;
-            dst[j] = (uint8_t)(lo | hi);
-        }
+        const uint64_t body = std::min(bytes, last - 1);
+        for (uint64_t j = 0; j < body; ++j)
+            dst[j] = (uint8_t)((s[j] >> sh) | ((unsigned)s[j + 1] << (8 - sh)));
+        for (uint64_t j = body; j < bytes; ++j) dst[j] = (uint8_t)(s[j] >> sh);
     }
     // bases past nb in the last byte are zero
     if (nb % 4) dst[bytes - 1] &= (uint8_t)((1u << (2 * (nb % 4))) - 1);
@@ -515,9 +563,9 @@ int genasm_submit(genasm_server* srv, const char* read, uint64_t m, const char* 
     }
     Request r;
     const uint64_t rb = (m + 3) / 4;
-    r.bytes.resize(rb + (n + 3) / 4);
-    if (genasm_pack(read, m, r.bytes.data(), nullptr) != GENASM_OK ||
-        genasm_pack(ref, n, r.bytes.data() + rb, nullptr) != GENASM_OK)
+    r.block = std::make_shared<std::vector<uint8_t>>(rb + (n + 3) / 4);
+    if (genasm_pack(read, m, r.block->data(), nullptr) != GENASM_OK ||
+        genasm_pack(ref, n, r.block->data() + rb, nullptr) != GENASM_OK)
         return GENASM_E_ALPHABET;
     r.m = (uint32_t)m;
     r.n = (uint32_t)n;
@@ -531,6 +579,7 @@ int genasm_submit(genasm_server* srv, const char* read, uint64_t m, const char* 
     srv->pending.push_back(std::move(r));
     srv->st.submitted++;
     srv->cv_work.notify_one();
+    note_arrivals(srv, 1);
     return GENASM_OK;
 }
 
@@ -559,13 +608,20 @@ int genasm_submit_batch(genasm_server* srv, const uint8_t* reads2b, const uint64
     const uint64_t take = std::min(room, n_req);
     std::vector<Request> reqs(take);
     const uint64_t now = steady_ns();
+    uint64_t total = 0;
+    for (uint64_t i = 0; i < take; ++i)
+        total += (read_off[i + 1] - read_off[i] + 3) / 4 + (ref_off[i + 1] - ref_off[i] + 3) / 4;
+    auto block = std::make_shared<std::vector<uint8_t>>(std::max<uint64_t>(total, 1));
+    uint64_t at = 0;
     for (uint64_t i = 0; i < take; ++i) {
         Request& r = reqs[i];
         const uint64_t m = read_off[i + 1] - read_off[i], n = ref_off[i + 1] - ref_off[i];
         const uint64_t rb = (m + 3) / 4;
-        r.bytes.resize(rb + (n + 3) / 4);
-        if (m) copy_bases(r.bytes.data(), reads2b, read_off[i], m);
-        if (n) copy_bases(r.bytes.data() + rb, refs2b, ref_off[i], n);
+        r.block = block;
+        r.off = at;
+        if (m) copy_bases(block->data() + at, reads2b, read_off[i], m);
+        if (n) copy_bases(block->data() + at + rb, refs2b, ref_off[i], n);
+        at += rb + (n + 3) / 4;
         r.m = (uint32_t)m;
         r.n = (uint32_t)n;
         r.tag = tags[i];
@@ -577,44 +633,83 @@ int genasm_submit_batch(genasm_server* srv, const uint8_t* reads2b, const uint64
     *accepted = take;
     if (take < n_req) srv->st.refused += n_req - take;
     srv->cv_work.notify_one();
+    note_arrivals(srv, take);
     return take < n_req ? GENASM_E_BUSY : GENASM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Takes up to `max` finished records off the completion queue (waiting up to
+// timeout_ms for the first), and no more than fit `runs_cap` elements when
+// runs_cap is not ~0. Returns the count or a negative error; *first_need is
+// set when not even the first record fits.
+int take_done(genasm_server* srv, std::vector<DoneRec>& got, int max, uint64_t runs_cap,
+              int timeout_ms, uint64_t* first_need) {
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (srv->done.empty() && timeout_ms > 0 && !srv->error)
+        srv->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
+                              [&] { return !srv->done.empty() || srv->error; });
+    uint64_t used = 0;
+    while ((int)got.size() < max && !srv->done.empty()) {
+        const DoneRec& d = srv->done.front();
+        if (runs_cap != ~0ull && used + d.result.cigar_len > runs_cap) {
+            if (got.empty()) {
+                *first_need = d.result.cigar_len;
+                return GENASM_E_NOSPACE;
+            }
+            break;
+        }
+        used += d.result.cigar_len;
+        got.push_back(std::move(srv->done.front()));
+        srv->done.pop_front();
+    }
+    if (got.empty() && srv->error) return srv->error;
+    return (int)got.size();
+}
+
+}  // namespace
+
+extern "C" {
+
 int genasm_poll(genasm_server* srv, genasm_completion* out, int max, int timeout_ms) {
     if (!srv || (!out && max > 0) || max < 0) return GENASM_E_INVAL;
-    int k = 0;
-    {
-        std::unique_lock<std::mutex> lk(srv->mu);
-        if (srv->done.empty() && timeout_ms > 0 && !srv->error)
-            srv->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
-                                  [&] { return !srv->done.empty() || srv->error; });
-        while (k < max && !srv->done.empty()) {
-            out[k++] = srv->done.front();
-            srv->done.pop_front();
-        }
-        if (k == 0 && srv->error) return srv->error;
-    }
-    if (!srv->cfg.cigar_runs) {
-        // text CIGARs, formatted here in the caller's thread
-        static const char kOp[4] = {'=', 'X', 'I', 'D'};
-        for (int i = 0; i < k; ++i) {
-            genasm_completion& c = out[i];
-            const uint32_t* el = reinterpret_cast<const uint32_t*>(c.cigar);
-            const uint32_t ne = c.result.cigar_len;
+    std::vector<DoneRec> got;
+    uint64_t need = 0;
+    const int k = take_done(srv, got, max, ~0ull, timeout_ms, &need);
+    if (k < 0) return k;
+    // the CIGAR, as text or as elements, copied here in the caller's thread
+    static const char kOp[4] = {'=', 'X', 'I', 'D'};
+    for (int i = 0; i < k; ++i) {
+        const DoneRec& d = got[i];
+        genasm_completion& c = out[i];
+        c.tag = d.tag;
+        c.result = d.result;
+        c.result.cigar_off = 0;
+        c.submit_ns = d.submit_ns;
+        c.admit_ns = d.admit_ns;
+        c.done_ns = d.done_ns;
+        const uint32_t ne = d.result.cigar_len;
+        const uint32_t* el = ne ? d.block->data() + d.result.cigar_off : nullptr;
+        if (srv->cfg.cigar_runs) {
+            c.cigar = static_cast<char*>(std::malloc(std::max<size_t>(ne, 1) * 4));
+            if (c.cigar && ne) std::memcpy(c.cigar, el, (size_t)ne * 4);
+            if (!c.cigar) c.result.cigar_len = 0;
+        } else {
             char* text = static_cast<char*>(std::malloc((size_t)ne * 11 + 1));
             char* w = text;
             if (text) {
                 for (uint32_t e = 0; e < ne; ++e) {
                     char tmp[12];
-                    int d = 0;
+                    int dg = 0;
                     uint32_t len = GENASM_CIGAR_LEN(el[e]);
-                    do { tmp[d++] = (char)('0' + len % 10); len /= 10; } while (len);
-                    while (d) *w++ = tmp[--d];
+                    do { tmp[dg++] = (char)('0' + len % 10); len /= 10; } while (len);
+                    while (dg) *w++ = tmp[--dg];
                     *w++ = kOp[GENASM_CIGAR_OP(el[e])];
                 }
                 *w = '\0';
             }
-            std::free(c.cigar);
             c.cigar = text;
             c.result.cigar_len = text ? (uint32_t)(w - text) : 0u;
         }
@@ -626,44 +721,27 @@ int genasm_poll_batch(genasm_server* srv, genasm_completion_info* out, int max, 
                       uint64_t runs_cap, uint64_t* runs_used, int timeout_ms) {
     if (!srv || !runs_used || max < 0 || (!out && max > 0) || (!runs && runs_cap)) return GENASM_E_INVAL;
     *runs_used = 0;
-    std::vector<genasm_completion> got;
-    {
-        std::unique_lock<std::mutex> lk(srv->mu);
-        if (srv->done.empty() && timeout_ms > 0 && !srv->error)
-            srv->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
-                                  [&] { return !srv->done.empty() || srv->error; });
-        uint64_t used = 0;
-        while ((int)got.size() < max && !srv->done.empty()) {
-            const genasm_completion& c = srv->done.front();
-            if (used + c.result.cigar_len > runs_cap) {
-                if (got.empty()) {
-                    *runs_used = c.result.cigar_len;
-                    return GENASM_E_NOSPACE;
-                }
-                break;
-            }
-            used += c.result.cigar_len;
-            got.push_back(c);
-            srv->done.pop_front();
-        }
-        if (got.empty() && srv->error) return srv->error;
-    }
+    std::vector<DoneRec> got;
+    uint64_t need = 0;
+    const int k = take_done(srv, got, max, runs_cap, timeout_ms, &need);
+    if (k == GENASM_E_NOSPACE) *runs_used = need;
+    if (k < 0) return k;
     uint64_t used = 0;
-    for (size_t i = 0; i < got.size(); ++i) {
-        genasm_completion& c = got[i];
+    for (int i = 0; i < k; ++i) {
+        const DoneRec& d = got[i];
         genasm_completion_info& o = out[i];
-        o.tag = c.tag;
-        o.result = c.result;
+        o.tag = d.tag;
+        o.result = d.result;
         o.result.cigar_off = used;
-        o.submit_ns = c.submit_ns;
-        o.admit_ns = c.admit_ns;
-        o.done_ns = c.done_ns;
-        if (c.result.cigar_len) std::memcpy(runs + used, c.cigar, (size_t)c.result.cigar_len * 4);
-        used += c.result.cigar_len;
-        std::free(c.cigar);
+        o.submit_ns = d.submit_ns;
+        o.admit_ns = d.admit_ns;
+        o.done_ns = d.done_ns;
+        if (d.result.cigar_len)
+            std::memcpy(runs + used, d.block->data() + d.result.cigar_off, (size_t)d.result.cigar_len * 4);
+        used += d.result.cigar_len;
     }
     *runs_used = used;
-    return (int)got.size();
+    return k;
 }
 
 void genasm_completion_release(genasm_completion* c) {
@@ -683,10 +761,9 @@ int genasm_cancel(genasm_server* srv, uint64_t tag) {
             return GENASM_OK;
         }
     }
-    auto r = srv->tag_slot.equal_range(tag);
-    for (auto it = r.first; it != r.second; ++it) {
-        if (!srv->slot_cancelled[it->second]) {
-            srv->slot_cancelled[it->second] = 1;
+    for (size_t slot = 0; slot < srv->slot_state.size(); ++slot) {
+        if (srv->slot_state[slot] == 1 && srv->slot_tag[slot] == tag) {
+            srv->slot_state[slot] = 2;
             srv->st.cancelled++;
             return GENASM_OK;
         }
@@ -713,12 +790,11 @@ void genasm_server_destroy(genasm_server* srv) {
     (void)hipSetDevice(srv->ctx->device);
     if (srv->s) (void)hipStreamSynchronize(srv->s);
     if (srv->s_copy) (void)hipStreamSynchronize(srv->s_copy);
-    for (auto& c : srv->done) genasm_completion_release(&c);
     std::vector<void*> dev = {srv->d_pool, srv->d_plo, srv->d_phi, srv->d_cigar, srv->d_read_off,
                               srv->d_ref_off, srv->d_run_base, srv->d_read_len, srv->d_ref_len,
                               srv->d_out, srv->d_state, srv->d_search, srv->d_new, srv->d_fin,
                               srv->d_fin_len, srv->d_fin_off, srv->d_items, srv->d_key,
-                              srv->d_deadline, srv->d_spill};
+                              srv->d_turn, srv->d_arrivals, srv->d_spill};
     std::vector<void*> host;
     for (IterBufs& b : srv->it) {
         if (b.exec) (void)hipGraphExecDestroy(b.exec);
@@ -763,21 +839,22 @@ int launch_iteration(genasm_server* srv, int q) {
     IterBufs& b = srv->it[q];
     std::vector<Request> admitted;
     std::vector<uint32_t> admitted_slots;
+    uint64_t admitted_arrivals = 0;
     {
+        RoctxRange r_admit("genasm_serve_admit");
         std::lock_guard<std::mutex> lk(srv->mu);
         uint64_t upload = 0;
+        const uint64_t now = steady_ns();
         while (!srv->pending.empty() && !srv->free_slots.empty()) {
             Request& r = srv->pending.front();
-            const uint64_t bytes = r.bytes.size();
+            const uint64_t bytes = r.bytes();
             if (upload + bytes > srv->upload_cap) break;
-            uint64_t rs, fs, cs;
+            uint64_t bs, cs;
             const uint64_t rl = round_up(r.m, kBaseUnit), fl = round_up(r.n, kBaseUnit);
             const uint64_t cl = (uint64_t)r.m + r.n + 1;
-            if (!srv->pool.alloc(rl, &rs)) break;
-            if (!srv->pool.alloc(fl, &fs)) { srv->pool.release(rs, rl); break; }
+            if (!srv->pool.alloc(rl + fl, &bs)) break;
             if (!srv->cigpool.alloc(cl, &cs)) {
-                srv->pool.release(rs, rl);
-                srv->pool.release(fs, fl);
+                srv->pool.release(bs, rl + fl);
                 break;
             }
             const uint32_t slot = srv->free_slots.back();
@@ -785,10 +862,10 @@ int launch_iteration(genasm_server* srv, int q) {
             Slot& sl = srv->slots[slot];
             sl.tag = r.tag;
             sl.submit_ns = r.submit_ns;
-            sl.admit_ns = steady_ns();
-            sl.rstart = rs; sl.rlen = rl; sl.fstart = fs; sl.flen = fl; sl.cstart = cs; sl.clen = cl;
-            srv->tag_slot.emplace(r.tag, slot);
-            srv->slot_cancelled[slot] = 0;
+            sl.admit_ns = now;
+            sl.bstart = bs; sl.blen = rl + fl; sl.fstart = bs + rl; sl.cstart = cs; sl.clen = cl;
+            srv->slot_tag[slot] = r.tag;
+            srv->slot_state[slot] = 1;
             admitted_slots.push_back(slot);
             upload += bytes;
             admitted.push_back(std::move(r));
@@ -796,22 +873,27 @@ int launch_iteration(genasm_server* srv, int q) {
         }
         srv->st.admitted += admitted.size();
         srv->st.pool_bases_used = srv->pool.used();
+        // arrivals up to here are admitted (the queue is first in, first out);
+        // later ones are news to this iteration's turns
+        admitted_arrivals = srv->arrivals - srv->pending.size();
+        srv->signalled = false;
     }
     // upload staging: packed bases and the scatter ranges, admission records
     uint64_t up = 0;
     uint32_t nr = 0;
+    RoctxRange r_stage("genasm_serve_stage");
     for (size_t a = 0; a < admitted.size(); ++a) {
         const uint32_t slot = admitted_slots[a];
         const Slot& sl = srv->slots[slot];
         const Request& r = admitted[a];
-        const uint64_t rb = (r.m + 3) / 4;
+        const uint64_t rb = r.read_bytes();
         const uint64_t part_off[2] = {0, rb};
-        const uint64_t part_len[2] = {rb, r.bytes.size() - rb};
-        const uint64_t dst[2] = {sl.rstart, sl.fstart};
+        const uint64_t part_len[2] = {rb, r.bytes() - rb};
+        const uint64_t dst[2] = {sl.bstart, sl.fstart};
         const uint32_t nb[2] = {r.m, r.n};
         for (int p = 0; p < 2; ++p) {
             if (part_len[p] == 0) continue;
-            std::memcpy(b.h_upload + up, r.bytes.data() + part_off[p], part_len[p]);
+            std::memcpy(b.h_upload + up, r.data() + part_off[p], part_len[p]);
             b.h_up_src[nr] = up;
             b.h_up_dst[nr] = dst[p] / 4;
             b.h_up_len[nr] = (uint32_t)part_len[p];
@@ -821,7 +903,7 @@ int launch_iteration(genasm_server* srv, int q) {
             ++nr;
         }
         ServeAdmit& ad = b.h_admit[a];
-        ad.read_off = sl.rstart;
+        ad.read_off = sl.bstart;
         ad.ref_off = sl.fstart;
         ad.run_base = sl.cstart;
         ad.slot = slot;
@@ -832,12 +914,20 @@ int launch_iteration(genasm_server* srv, int q) {
     const uint32_t n_new = (uint32_t)admitted.size();
     srv->resident += n_new;
     b.n_new = n_new;
-    // window time: short while the device has room (latency), long while
-    // requests wait or most window groups hold a pair (throughput)
-    uint32_t us = (uint32_t)srv->cfg.iteration_us;
-    if (us == 0) us = saturated(srv) ? 2000u : 250u;
+    // window time: 2 ms; while no request waits and most window groups are
+    // free, a turn also ends from 250 us on once a pair of the iteration has
+    // finished or a request has arrived (latency), else it runs the whole
+    // window time (throughput). A configured window time is fixed.
+    uint32_t us = (uint32_t)srv->cfg.iteration_us, soon_us = 0;
+    if (us == 0) {
+        us = 2000u;
+        soon_us = saturated(srv) ? 0u : 250u;
+    }
     b.h_params[kServeParamNew] = n_new;
     b.h_params[kServeParamTicks] = us * 100u;  // the device wall clock runs at 100 MHz
+    b.h_params[kServeParamSoonTicks] = soon_us * 100u;
+    b.h_params[kServeParamAdmitted] = (uint32_t)admitted_arrivals;
+    b.h_params[kServeParamAdmitted + 1] = (uint32_t)(admitted_arrivals >> 32);
     hipStream_t s = srv->s;
     SRV_HIP(srv, hipEventRecord(b.ev_start, s));
     if (nr) {
@@ -867,72 +957,71 @@ int launch_iteration(genasm_server* srv, int q) {
 int finish_iteration(genasm_server* srv, int q) {
     RoctxRange range("genasm_serve_finish");
     IterBufs& b = srv->it[q];
-    SRV_HIP(srv, hipEventSynchronize(b.ev_done));
+    {
+        RoctxRange r_wait("genasm_serve_wait");
+        SRV_HIP(srv, hipEventSynchronize(b.ev_done));
+    }
     float ms = 0.f;
     SRV_HIP(srv, hipEventElapsedTime(&ms, b.ev_start, b.ev_done));
     const uint32_t n_fin = (uint32_t)b.h_hdr[0];
-    const uint64_t total = b.h_hdr[1];
-    // the gathered elements that fit the buffer, in one copy; a pair past it
-    // is copied from the CIGAR pool by itself
-    uint64_t fit = 0;
+    // the gathered elements that fit the buffer, in one copy, then into one
+    // block that the iteration's completions share; a pair past the buffer is
+    // copied from the CIGAR pool by itself, to the end of the block
+    uint64_t fit = 0, over_elems = 0;
     std::vector<uint32_t> over;
     for (uint32_t k = 0; k < n_fin; ++k) {
         const genasm_result& r = b.h_res[k];
-        if (r.cigar_off + r.cigar_len <= srv->gather_cap) fit = std::max(fit, r.cigar_off + r.cigar_len);
-        else over.push_back(k);
+        if (r.cigar_off + r.cigar_len <= srv->gather_cap) {
+            fit = std::max(fit, r.cigar_off + r.cigar_len);
+        } else {
+            over.push_back(k);
+            over_elems += r.cigar_len;
+        }
     }
-    (void)total;
+    auto block = std::make_shared<std::vector<uint32_t>>(std::max<uint64_t>(fit + over_elems, 1));
     if (fit)
         SRV_HIP(srv, hipMemcpyAsync(b.h_gather, b.d_gather, fit * 4, hipMemcpyDeviceToHost, srv->s_copy));
-    std::vector<std::vector<uint32_t>> over_el(over.size());
+    uint64_t at = fit;
+    std::vector<uint64_t> over_at(over.size());
     for (size_t j = 0; j < over.size(); ++j) {
         const uint32_t k = over[j];
         const Slot& sl = srv->slots[b.h_slot[k]];
-        over_el[j].resize(b.h_res[k].cigar_len);
-        SRV_HIP(srv, hipMemcpyAsync(over_el[j].data(), srv->d_cigar + sl.cstart,
-                                    over_el[j].size() * 4, hipMemcpyDeviceToHost, srv->s_copy));
+        over_at[j] = at;
+        SRV_HIP(srv, hipMemcpyAsync(block->data() + at, srv->d_cigar + sl.cstart,
+                                    (size_t)b.h_res[k].cigar_len * 4, hipMemcpyDeviceToHost,
+                                    srv->s_copy));
+        at += b.h_res[k].cigar_len;
     }
     SRV_HIP(srv, hipStreamSynchronize(srv->s_copy));
-    std::vector<genasm_completion> comps(n_fin);
+    if (fit) std::memcpy(block->data(), b.h_gather, fit * 4);
+    RoctxRange r_records("genasm_serve_records");
+    std::vector<DoneRec> recs(n_fin);
     size_t oj = 0;
     const uint64_t now = steady_ns();
     for (uint32_t k = 0; k < n_fin; ++k) {
         const uint32_t slot = b.h_slot[k];
         const Slot& sl = srv->slots[slot];
-        genasm_result r = b.h_res[k];
-        const uint32_t* src = (oj < over.size() && over[oj] == k) ? over_el[oj++].data()
-                                                                  : b.h_gather + r.cigar_off;
-        genasm_completion& c = comps[k];
-        c.tag = sl.tag;
-        c.cigar = static_cast<char*>(std::malloc(std::max<size_t>(r.cigar_len, 1) * 4));
-        if (c.cigar && r.cigar_len) std::memcpy(c.cigar, src, (size_t)r.cigar_len * 4);
-        if (!c.cigar) r.cigar_len = 0;
-        r.cigar_off = 0;
-        c.result = r;
-        c.submit_ns = sl.submit_ns;
-        c.admit_ns = sl.admit_ns;
-        c.done_ns = now;
-        srv->pool.release(sl.rstart, sl.rlen);
-        srv->pool.release(sl.fstart, sl.flen);
+        DoneRec& d = recs[k];
+        d.tag = sl.tag;
+        d.result = b.h_res[k];
+        if (oj < over.size() && over[oj] == k) d.result.cigar_off = over_at[oj++];
+        d.submit_ns = sl.submit_ns;
+        d.admit_ns = sl.admit_ns;
+        d.done_ns = now;
+        d.block = block;
+        srv->pool.release(sl.bstart, sl.blen);
         srv->cigpool.release(sl.cstart, sl.clen);
-        srv->free_slots.push_back(slot);
     }
     srv->resident -= std::min(srv->resident, n_fin);
     std::lock_guard<std::mutex> lk(srv->mu);
     uint64_t delivered = 0;
     for (uint32_t k = 0; k < n_fin; ++k) {
         const uint32_t slot = b.h_slot[k];
-        genasm_completion& c = comps[k];
-        auto r = srv->tag_slot.equal_range(c.tag);
-        for (auto it = r.first; it != r.second; ++it)
-            if (it->second == slot) { srv->tag_slot.erase(it); break; }
-        if (srv->slot_cancelled[slot]) {
-            // cancelled while resident: no completion
-            srv->slot_cancelled[slot] = 0;
-            genasm_completion_release(&c);
-            continue;
-        }
-        srv->done.push_back(c);
+        const bool cancelled = srv->slot_state[slot] == 2;
+        srv->slot_state[slot] = 0;
+        srv->free_slots.push_back(slot);
+        if (cancelled) continue;  // cancelled while resident: no completion
+        srv->done.push_back(std::move(recs[k]));
         ++delivered;
     }
     srv->st.completed += delivered;
@@ -962,13 +1051,9 @@ void engine_main(genasm_server* srv) {
         if (stop && inflight.empty()) return;
         const bool can_admit = pend > 0 && !srv->free_slots.empty();
         bool launch = false;
-        if (!stop && inflight.size() < 2 && (can_admit || srv->resident > 0)) {
-            // a second iteration is queued behind the running one when requests
-            // wait or most window groups are busy (the device then never waits
-            // for the host); otherwise the running one is awaited, so that
-            // requests arriving meanwhile join the next iteration
-            launch = inflight.empty() || pend > 0 || 2 * (uint64_t)srv->resident >= srv->groups;
-        }
+        // while work remains, a second iteration is queued behind the running
+        // one, so that the device never waits for the host between them
+        launch = !stop && inflight.size() < 2 && (can_admit || srv->resident > 0);
         if (launch) {
             const int q = (int)(t & 1);
             if (launch_iteration(srv, q) != GENASM_OK) return;

@@ -124,7 +124,8 @@ int main(int argc, char** argv) {
         std::vector<uint32_t> new_list(n_slots + 1), fin(n_slots + 1), fin_len(1, 0);
         std::vector<ServeAdmit> admit(n_slots + 1);
         std::vector<unsigned long long> spill(spill_words(workers, kCompactSpillRows, p.stride));
-        std::vector<unsigned long long> deadline(1, 0);
+        std::vector<TurnLimits> turn(1);
+        std::vector<unsigned long long> arrivals(1, 0);
         std::vector<uint64_t> s_roff(n_slots), s_foff(n_slots), s_base(n_slots);
         std::vector<uint32_t> s_rlen(n_slots), s_flen(n_slots);
         std::vector<PairState> state(n_slots);
@@ -174,7 +175,10 @@ int main(int argc, char** argv) {
                 ++resident;
             }
             params[q][kServeParamNew] = n_new;
+            // a turn may also end, from half the window time on, once a pair
+            // of the iteration has finished
             params[q][kServeParamTicks] = ticks;
+            params[q][kServeParamSoonTicks] = ticks / 2;
             emu::group_lanes = 64;
             launch_serve_begin(cnt[q].data(), cnt[1 - q].data(), fin_len.data(), params[q].data(),
                                admit.data(), slots, new_list.data(), nullptr);
@@ -207,12 +211,13 @@ int main(int argc, char** argv) {
                 }
             }
             emu::group_lanes = 1;
-            launch_serve_stamp(params[q].data(), deadline.data(), nullptr);
+            launch_serve_stamp(params[q].data(), turn.data(), nullptr);
             AlignParams P = p;
             P.counters = cnt[q].data();
             P.easy_list = hot[q].data();
             P.hard_list = cold[q].data();
-            P.deadline = deadline.data();
+            P.turn = turn.data();
+            P.arrivals = arrivals.data();
             P.next_hot = hot[1 - q].data();
             P.next_cold = cold[1 - q].data();
             P.next_len = cnt[1 - q].data();

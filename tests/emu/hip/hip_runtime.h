@@ -215,7 +215,37 @@ inline unsigned long long wall_clock64() {
     return v;
 }
 inline void __threadfence_system() { std::atomic_thread_fence(std::memory_order_seq_cst); }
+namespace emu {
+// The first lane's value to every lane: here the first lane of the group.
+inline int readfirstlane(int v) {
+    BlockState* b = cur.blk;
+    const int lane = (int)cur.tid;
+    const int g0 = lane / b->group_lanes * b->group_lanes;
+    group_barrier();
+    if (lane == g0) b->slot[lane] = (unsigned long long)(unsigned)v;
+    group_barrier();
+    const int r = (int)(unsigned)b->slot[g0];
+    group_barrier();
+    return r;
+}
+}  // namespace emu
+#define __builtin_amdgcn_readfirstlane emu::readfirstlane
 #define __builtin_amdgcn_update_dpp emu::update_dpp
+namespace emu {
+inline int mov_dpp(int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+    // lanes without a source lane would keep an undefined value; the kernels
+    // use this only for rotations, where every lane has one
+    return update_dpp((int)0xDEADDEAD, src, ctrl, row_mask, bank_mask, bound_ctrl);
+}
+}  // namespace emu
+#define __builtin_amdgcn_mov_dpp emu::mov_dpp
+namespace emu {
+// v_alignbit_b32: the low 32 bits of (hi:lo) >> (s mod 32)
+inline unsigned alignbit(unsigned hi, unsigned lo, unsigned s) {
+    return (unsigned)((((unsigned long long)hi << 32) | lo) >> (s & 31));
+}
+}  // namespace emu
+#define __builtin_amdgcn_alignbit emu::alignbit
 // Block-wide barriers and static shared arrays are not emulated (kernels that
 // use them, such as the ordering scan, do not run under the emulation).
 inline void __syncthreads() {
@@ -228,6 +258,7 @@ inline void __syncthreads() {
 #define __ballot(p) emu::ballot(p)
 #define __shfl(v, src) emu::shfl(v, src)
 #define __HIP_MEMORY_SCOPE_AGENT 0
+#define __HIP_MEMORY_SCOPE_SYSTEM 0
 #define __HIP_MEMORY_SCOPE_WAVEFRONT 0
 #define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_SEQ_CST)
 
