@@ -139,10 +139,11 @@ typedef struct genasm_ctx genasm_ctx;
  * defines no such object.) */
 int genasm_create(genasm_ctx** out, int hip_device);
 
-/* Frees everything the context owns. Safe on NULL. */
+/* Frees everything the context owns. Safe on NULL. (Library plumbing.) */
 void genasm_destroy(genasm_ctx* ctx);
 
-/* Graph capture and the context's buffers. A genasm_batch_align_dev call made
+/* Graph capture and the context's buffers (library plumbing around the device
+ * form; no paper passage). A genasm_batch_align_dev call made
  * while its stream is being captured records kernels that use the context's
  * device buffers by address, so such a call pins the context: from then on a
  * call that would need larger buffers fails with GENASM_E_PINNED instead of
@@ -153,13 +154,16 @@ void genasm_destroy(genasm_ctx* ctx);
 int genasm_unpin(genasm_ctx* ctx);
 
 /* Message of the last error on this context (never NULL). With ctx == NULL:
- * the reason of the calling thread's last failed genasm_create. */
+ * the reason of the calling thread's last failed genasm_create. (Library
+ * plumbing.) */
 const char* genasm_last_error(const genasm_ctx* ctx);
 
-/* Static text for an error code. */
+/* Static text for an error code. (Library plumbing.) */
 const char* genasm_strerror(int code);
 
-/* Fills *out with the default launch parameters of `form`. */
+/* Fills *out with the default launch parameters of `form` (launch geometry of
+ * the device form; library plumbing). Returns GENASM_E_INVAL for an unknown
+ * form or a NULL out. */
 int genasm_default_launch(int32_t form, genasm_launch* out);
 
 /*
@@ -307,7 +311,9 @@ int genasm_autotune_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_
                         int32_t k, int32_t W, int32_t O, genasm_result* d_out, uint32_t* d_cigar,
                         uint64_t cigar_cap, int32_t reps, void* stream, genasm_launch* best,
                         float* best_ms);
-/* Tuning cache as text, one signature per line; load merges into the context's cache. */
+/* Tuning cache as text, one signature per line; load merges into the context's
+ * cache (library plumbing). GENASM_E_INVAL for a file that cannot be opened or
+ * parsed; size returns the number of cached signatures. */
 int genasm_tune_cache_save(genasm_ctx* ctx, const char* path);
 int genasm_tune_cache_load(genasm_ctx* ctx, const char* path);
 int genasm_tune_cache_size(genasm_ctx* ctx);
@@ -321,8 +327,8 @@ int genasm_tune_cache_size(genasm_ctx* ctx);
 int genasm_pack(const char* ascii, uint64_t n, uint8_t* packed, uint64_t* bad_index);
 
 /*
- * Device version of genasm_pack, asynchronous on `stream` (NULL = the null
- * stream): packs d_ascii[0..n)
+ * Device version of genasm_pack (input loading, as genasm_pack), asynchronous
+ * on `stream` (NULL = the null stream): packs d_ascii[0..n)
  * into d_packed[0..(n+3)/4) and adds the number of non-ACGT bytes to
  * *d_bad_count (device memory, caller-initialised).
  */
@@ -330,7 +336,8 @@ int genasm_pack_dev(genasm_ctx* ctx, const char* d_ascii, uint64_t n, uint8_t* d
                     uint32_t* d_bad_count, void* stream);
 
 /*
- * Checks arguments of a host-form call without touching a device: the values
+ * Checks arguments of a host-form call without touching a device (library
+ * plumbing; the limits are those stated for genasm_batch_align): the values
  * of W, O and k, the offsets (non-decreasing, in range of the given stream
  * lengths) and the alphabet. Returns GENASM_OK or the code genasm_batch_align
  * would return.
@@ -457,19 +464,22 @@ typedef struct {
 } genasm_server_stats;
 
 /* Creates a server on `ctx` (which it then uses exclusively until destroyed).
- * Returns GENASM_E_INVAL for bad parameters, GENASM_E_NOMEM/GENASM_E_DEVICE on
- * allocation or device failure. */
+ * Serving plumbing, as described above. Returns GENASM_E_INVAL for bad
+ * parameters, GENASM_E_NOMEM/GENASM_E_DEVICE on allocation or device failure. */
 int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg, genasm_server** out);
 
-/* Queues one request (ASCII read of m bases, reference of n bases, packed and
- * copied before return). k, W and O must equal the server's (else
- * GENASM_E_INVAL). Returns GENASM_E_BUSY when max_pending requests already
- * wait, GENASM_E_ALPHABET for a non-ACGT byte, GENASM_E_TOOLONG when the pair
- * can never fit the pools. Thread-safe. */
+/* Queues one request (serving plumbing; the pair is aligned as by
+ * genasm_batch_align): an ASCII read of m bases and reference of n bases,
+ * packed and copied into pinned host memory before return. k, W and O must
+ * equal the server's (else GENASM_E_INVAL). Returns GENASM_E_BUSY when
+ * max_pending requests already wait, GENASM_E_ALPHABET for a non-ACGT byte,
+ * GENASM_E_TOOLONG when the pair can never fit the pools, GENASM_E_NOMEM when
+ * no pinned host memory can be had. Thread-safe. */
 int genasm_submit(genasm_server* srv, const char* read, uint64_t m, const char* ref, uint64_t n,
                   int32_t k, int32_t W, int32_t O, uint64_t tag);
 
-/* Queues n requests at once from 2-bit packed host streams (layout as for
+/* Queues n requests at once (serving plumbing, as genasm_submit) from 2-bit
+ * packed host streams (layout as for
  * genasm_batch_align_dev: base b is bits 2*(b%4).. of byte b/4; request i is
  * reads2b bases [read_off[i], read_off[i+1]) against refs2b bases
  * [ref_off[i], ref_off[i+1]), offsets in bases, n + 1 of each), with tags[i].
@@ -478,15 +488,17 @@ int genasm_submit(genasm_server* srv, const char* read, uint64_t m, const char* 
  * (requests 0 .. *accepted-1), and the call returns GENASM_E_BUSY when that is
  * fewer than n. GENASM_E_INVAL (nothing queued) for null pointers, decreasing
  * offsets or k/W/O other than the server's, GENASM_E_TOOLONG (nothing queued)
- * when some pair can never fit the pools. Thread-safe. */
+ * when some pair can never fit the pools, GENASM_E_NOMEM (nothing queued) when
+ * no pinned host memory can be had. Thread-safe. */
 int genasm_submit_batch(genasm_server* srv, const uint8_t* reads2b, const uint64_t* read_off,
                         const uint8_t* refs2b, const uint64_t* ref_off, uint64_t n,
                         int32_t k, int32_t W, int32_t O, const uint64_t* tags,
                         uint64_t* accepted);
 
-/* Moves up to `max` completions into out[], waiting up to timeout_ms for the
- * first one (0 = do not wait); text CIGARs are formatted here, in the calling
- * thread. Returns the number moved, or a negative error (GENASM_E_DEVICE: the
+/* Moves up to `max` completions into out[] (serving plumbing: each carries the
+ * result and CIGAR genasm_batch_align would give its pair), waiting up to
+ * timeout_ms for the first one (0 = do not wait); text CIGARs are formatted
+ * here, in the calling thread. Returns the number moved, or a negative error (GENASM_E_DEVICE: the
  * engine stopped on a device error). Thread-safe. */
 int genasm_poll(genasm_server* srv, genasm_completion* out, int max, int timeout_ms);
 
@@ -497,7 +509,7 @@ typedef struct {
     uint64_t submit_ns, admit_ns, done_ns;
 } genasm_completion_info;
 
-/* Bulk form of genasm_poll for high-rate consumers: moves up to `max`
+/* Bulk form of genasm_poll for high-rate consumers (serving plumbing): moves up to `max`
  * completions into out[] and their CIGARs, as run-length elements
  * (GENASM_CIGAR_LEN/OP) in either CIGAR mode, back to back into
  * runs[0 .. runs_cap); result.cigar_off indexes runs. Stops before the first
@@ -508,7 +520,7 @@ typedef struct {
 int genasm_poll_batch(genasm_server* srv, genasm_completion_info* out, int max, uint32_t* runs,
                       uint64_t runs_cap, uint64_t* runs_used, int timeout_ms);
 
-/* Cancels the request with this tag (the first one found, if tags repeat):
+/* Cancels the request with this tag (serving plumbing; the first one found, if tags repeat):
  * a request still waiting on the host is dropped; a resident one runs to its
  * end on the device, then its slot is freed without a completion. Either way
  * no completion for it is delivered. Returns GENASM_E_INVAL when no waiting
@@ -516,16 +528,18 @@ int genasm_poll_batch(genasm_server* srv, genasm_completion_info* out, int max, 
  * Thread-safe. */
 int genasm_cancel(genasm_server* srv, uint64_t tag);
 
-/* Frees the CIGAR of a completion. */
+/* Frees the CIGAR of a completion (serving plumbing). Safe on NULL. */
 void genasm_completion_release(genasm_completion* c);
 
+/* Copies the server's counters (serving plumbing). GENASM_E_INVAL for NULL. */
 int genasm_server_stats_read(genasm_server* srv, genasm_server_stats* out);
 
 /* Stops the engine (requests still waiting are dropped; iterations on the
- * device complete first) and frees the server. */
+ * device complete first) and frees the server (serving plumbing). Safe on NULL. */
 void genasm_server_destroy(genasm_server* srv);
 
-/* Monotonic clock used by the completion timestamps, in nanoseconds. */
+/* Monotonic clock used by the completion timestamps, in nanoseconds (serving
+ * plumbing). */
 uint64_t genasm_now_ns(void);
 
 /*
@@ -552,7 +566,7 @@ typedef struct {
 } genasm_peaks;
 int genasm_measure_peaks(genasm_ctx* ctx, genasm_peaks* out);
 
-/* Library version string. */
+/* Library version string (library plumbing). */
 const char* genasm_version(void);
 
 #ifdef __cplusplus

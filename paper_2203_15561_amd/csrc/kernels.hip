@@ -229,6 +229,35 @@ __device__ void build_pm(u64* lds, int gl, const uint8_t* reads, uint64_t rb, in
     wave_sync();
 }
 
+// One DC step on a 64-bit word: R' = x & ((R << 1) | pm) with
+// x = D & (((D & up) << 1) | low), worked on 32-bit halves: the low half's
+// shift and OR are one instruction and the high half's shift is a funnel shift,
+// which together issue faster on gfx950 than the 64-bit shift instruction.
+__device__ __forceinline__ u64 dc_step(u64 R, u64 D, u64 up, u64 pm, u64 low) {
+    const uint32_t Rl = (uint32_t)R, Rh = (uint32_t)(R >> 32);
+    const uint32_t Dl = (uint32_t)D, Dh = (uint32_t)(D >> 32);
+    const uint32_t el = Dl & (uint32_t)up, eh = Dh & (uint32_t)(up >> 32);
+    const uint32_t xl = Dl & ((el << 1) | (uint32_t)low);
+    const uint32_t xh = Dh & (__builtin_amdgcn_alignbit(eh, el, 31) | (uint32_t)(low >> 32));
+    const uint32_t sl = (Rl << 1) | (uint32_t)pm;
+    const uint32_t sh = __builtin_amdgcn_alignbit(Rh, Rl, 31) | (uint32_t)(pm >> 32);
+    return ((u64)(xh & sh) << 32) | (xl & sl);
+}
+
+// Bits 0, 2, 4, .. of w into the low half and bits 1, 3, 5, .. into the high
+// half (bit 2k to bit k, bit 2k+1 to bit 32+k).
+__device__ __forceinline__ u64 split_even_odd(u64 w) {
+    auto compress = [](u64 x) -> u64 {
+        x &= 0x5555555555555555ull;
+        x = (x | (x >> 1)) & 0x3333333333333333ull;
+        x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+        x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+        x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+        return (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+    };
+    return compress(w) | (compress(w >> 1) << 32);
+}
+
 // Shifts a two-word bit window: bits [s, s+64) of the 128-bit value (hi:lo).
 __device__ __forceinline__ u64 funnel64(u64 lo, u64 hi, int s) {
     return s == 0 ? lo : (lo >> s) | (hi << (64 - s));
@@ -273,6 +302,7 @@ __device__ __forceinline__ void pm_from_planes(u64 pl, u64 ph, int mw, u64 pm[4]
         pm[c] = ~(__builtin_bitreverse64(eq) >> sh);
     }
 }
+
 
 // Writes PMT (PM[T[i]] for the window's columns, ~0 at nw..64) into LDS.
 template <int G>
@@ -344,8 +374,7 @@ __device__ void dc_pass(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int
             qpm[u] = pmt[clampi(ip, 0, nw)];
             if (!FIRST) qov[u] = brow[1 + clampi(ip, -1, nw + 1)];
             const u64 up = shift_up<G>(ov, R, gl);
-            const u64 x = Dp & (((Dp & up) << 1) | lowin);
-            R = x & ((R << 1) | pm_t);
+            R = dc_step(R, Dp, up, pm_t, lowin);
             Dp = up;
             trow[1 + clampi(i, -1, Lc + 1)] = R;
             if (gl == G - 1) brow[1 + clampi(i, -1, nw + 1)] = R;
@@ -388,8 +417,7 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
             const u64 pm_t = qpm[u];
             const u64 ov = qov[u];
             const u64 up = shift_up<G>(ov, R, gl);
-            const u64 x = Dp & (((Dp & up) << 1) | lowin);
-            R = x & ((R << 1) | pm_t);
+            R = dc_step(R, Dp, up, pm_t, lowin);
             Dp = up;
             if constexpr (decltype(store)::value) trow[med3i(slot0 - t, 0, hi_slot)] = R;
             if constexpr (decltype(brow_store)::value) {
@@ -442,20 +470,6 @@ __device__ __forceinline__ void fill_brow(u64* lds, const u64* spill, int gl, in
 // ---------------------------------------------------------------------------
 // Start search: rows 0.. of the first read window against the whole reference
 // ---------------------------------------------------------------------------
-
-// Bits 0, 2, 4, .. of w into the low half and bits 1, 3, 5, .. into the high
-// half (bit 2k to bit k, bit 2k+1 to bit 32+k).
-__device__ __forceinline__ u64 split_even_odd(u64 w) {
-    auto compress = [](u64 x) -> u64 {
-        x &= 0x5555555555555555ull;
-        x = (x | (x >> 1)) & 0x3333333333333333ull;
-        x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
-        x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
-        x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
-        return (x | (x >> 16)) & 0x00000000FFFFFFFFull;
-    };
-    return compress(w) | (compress(w >> 1) << 32);
-}
 
 // keep ? hit : t, bitwise (keep is all ones or zero), in one v_bfi_b32.
 __device__ __forceinline__ int keep_or(int keep, int hit, int t) {
@@ -1805,8 +1819,7 @@ __device__ __forceinline__ void dc_pass_c(u64* lds, int gl, int nw, int Lc, int 
             const int t = t0 + u;
             const u64 pm_t = qpm[u];
             const u64 up = shift_up<16>(~0ull, R, gl);
-            const u64 x = Dp & (((Dp & up) << 1) | lowin);
-            R = x & ((R << 1) | pm_t);
+            R = dc_step(R, Dp, up, pm_t, lowin);
             Dp = up;
             if constexpr (decltype(store)::value) {
                 // live stores have 47 - i <= 47; the dummies store garbage

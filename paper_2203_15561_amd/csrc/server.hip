@@ -43,6 +43,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "range_alloc.h"
 #include "trace.h"
 
 using namespace genasm;
@@ -55,98 +56,105 @@ uint64_t steady_ns() {
         .count();
 }
 
-// Best-fit allocator of [0, cap) in abstract units: free ranges indexed by
-// start (for merging neighbours) and by length (for the smallest range that
-// fits), so that every operation is logarithmic in the number of free ranges.
-class RangeAlloc {
-  public:
-    void reset(uint64_t cap) {
-        by_start_.clear();
-        by_len_.clear();
-        if (cap) insert(0, cap);
-        used_ = 0;
-    }
-    bool alloc(uint64_t len, uint64_t* start) {
-        if (len == 0) { *start = 0; return true; }
-        auto it = by_len_.lower_bound({len, 0});
-        if (it == by_len_.end()) return false;
-        const uint64_t have = it->first, s0 = it->second;
-        erase(s0, have);
-        if (have > len) insert(s0 + len, have - len);
-        *start = s0;
-        used_ += len;
-        return true;
-    }
-    void release(uint64_t start, uint64_t len) {
-        if (len == 0) return;
-        used_ -= len;
-        uint64_t s0 = start, l0 = len;
-        auto nx = by_start_.lower_bound(start);
-        if (nx != by_start_.end() && s0 + l0 == nx->first) {
-            const uint64_t ns = nx->first, nl = nx->second;
-            erase(ns, nl);
-            l0 += nl;
-        }
-        auto pv = by_start_.lower_bound(start);
-        if (pv != by_start_.begin()) {
-            --pv;
-            if (pv->first + pv->second == s0) {
-                const uint64_t ps = pv->first, pl = pv->second;
-                erase(ps, pl);
-                s0 = ps;
-                l0 += pl;
-            }
-        }
-        insert(s0, l0);
-    }
-    uint64_t used() const { return used_; }
-
-  private:
-    void insert(uint64_t s0, uint64_t len) {
-        by_start_[s0] = len;
-        by_len_.emplace(len, s0);
-    }
-    // (length, start) keys: many free ranges share a length (requests of one
-    // size), and each is found directly rather than by a scan of its length
-    void erase(uint64_t s0, uint64_t len) {
-        by_start_.erase(s0);
-        by_len_.erase({len, s0});
-    }
-    std::map<uint64_t, uint64_t> by_start_;
-    std::set<std::pair<uint64_t, uint64_t>> by_len_;
-    uint64_t used_ = 0;
-};
-
 constexpr uint64_t kBaseUnit = 64;  // pool allocations in bases: whole bit-plane words
+constexpr uint64_t kArenaChunk = 4ull << 20;  // pinned chunk that submissions are packed into
 
 uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
+// Pinned host blocks, reused: a block goes back to the free list of its size
+// class (powers of two from 1 MiB) when its last reference drops, in whatever
+// thread that happens; up to kKeepBytes stay cached, beyond that they are
+// freed. Copies between these blocks and the device run at full PCIe rate with
+// no staging copy on either side.
+class HostPool : public std::enable_shared_from_this<HostPool> {
+  public:
+    static constexpr int kMinClass = 20;
+    static constexpr uint64_t kKeepBytes = 1ull << 30;
+    ~HostPool() {
+        for (auto& f : free_)
+            for (void* p : f) (void)hipHostFree(p);
+    }
+    // Puts `count` blocks of `bytes` bytes (a power of two from 1 MiB) into the
+    // free lists ahead of use, with their pages touched: the first write to a
+    // freshly pinned page is many times slower than later ones.
+    void warm(uint64_t bytes, int count) {
+        std::vector<std::shared_ptr<uint8_t>> held;
+        for (int i = 0; i < count; ++i) {
+            std::shared_ptr<uint8_t> b = get(bytes);
+            if (!b) break;
+            std::memset(b.get(), 0, bytes);
+            held.push_back(std::move(b));
+        }
+    }
+    // A block of at least `bytes` bytes, or null when none can be allocated.
+    std::shared_ptr<uint8_t> get(uint64_t bytes) {
+        int k = kMinClass;
+        while ((1ull << k) < bytes) ++k;
+        if (k >= 48) return nullptr;
+        void* p = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (!free_[k].empty()) {
+                p = free_[k].back();
+                free_[k].pop_back();
+                cached_ -= 1ull << k;
+            }
+        }
+        if (!p && hipHostMalloc(&p, 1ull << k, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        std::shared_ptr<HostPool> self = shared_from_this();
+        return std::shared_ptr<uint8_t>(static_cast<uint8_t*>(p),
+                                        [self, k](uint8_t* q) { self->put(q, k); });
+    }
+
+  private:
+    void put(void* p, int k) {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (cached_ + (1ull << k) <= kKeepBytes) {
+                free_[k].push_back(p);
+                cached_ += 1ull << k;
+                return;
+            }
+        }
+        (void)hipHostFree(p);
+    }
+    std::mutex mu_;
+    std::vector<void*> free_[48];
+    uint64_t cached_ = 0;
+};
+
 // A queued request: its read's packed bytes, then its reference's, at `off`
-// in a byte block shared by the requests of one submission call (one host
-// allocation per call rather than per request).
+// in a pinned block that it shares with the requests submitted around it.
 struct Request {
-    std::shared_ptr<std::vector<uint8_t>> block;
+    std::shared_ptr<uint8_t> block;
     uint64_t off = 0;
     uint32_t m = 0, n = 0;
     uint64_t tag = 0, submit_ns = 0;
     uint64_t read_bytes() const { return ((uint64_t)m + 3) / 4; }
     uint64_t bytes() const { return read_bytes() + ((uint64_t)n + 3) / 4; }
-    const uint8_t* data() const { return block->data() + off; }
+    const uint8_t* data() const { return block.get() + off; }
 };
 
 // A finished request on its way to the caller: the CIGAR elements stay in the
-// iteration's gathered block until a poll copies or formats them (in the
-// polling thread, not the engine's).
+// iteration's pinned completion block until a poll copies or formats them (in
+// the polling thread, not the engine's).
 struct DoneRec {
     uint64_t tag;
     genasm_result result;  // cigar_off: element offset in `block`; cigar_len: elements
     uint64_t submit_ns, admit_ns, done_ns;
-    std::shared_ptr<std::vector<uint32_t>> block;
+    std::shared_ptr<uint8_t> block;
+    const uint32_t* elements() const {
+        return reinterpret_cast<const uint32_t*>(block.get()) + result.cigar_off;
+    }
 };
 
 struct Slot {
     uint64_t tag = 0, submit_ns = 0, admit_ns = 0;
     uint64_t bstart = 0, blen = 0;  // base pool range (bases): the read, then the reference
+    uint32_t bh = 0, ch = 0;        // their allocator handles
     uint64_t fstart = 0;            // where the reference starts in it
     uint64_t cstart = 0, clen = 0;  // CIGAR pool range (elements)
 };
@@ -188,7 +196,9 @@ struct IterBufs {
     uint32_t* dh_slot = nullptr;
     genasm_result* dh_res = nullptr;
     // gathered CIGAR elements of the finished pairs
-    uint32_t *d_gather = nullptr, *h_gather = nullptr;
+    uint32_t* d_gather = nullptr;
+    // submission blocks the iteration's uploads read from (kept until it ends)
+    std::vector<std::shared_ptr<uint8_t>> holds;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev_start = nullptr, ev_done = nullptr;
@@ -227,6 +237,13 @@ struct genasm_server {
     unsigned long long* d_spill = nullptr;
     uint64_t upload_cap = 0;
     IterBufs it[2];
+
+    // pinned host blocks: submissions (an arena of chunks, or a block of their
+    // own when large) and per-iteration completion blocks
+    std::shared_ptr<HostPool> hpool = std::make_shared<HostPool>();
+    std::mutex arena_mu;
+    std::shared_ptr<uint8_t> arena;
+    uint64_t arena_used = 0, arena_size = 0;
 
     // engine-thread state
     std::vector<Slot> slots;
@@ -403,10 +420,14 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
         H(b.h_params, kServeParamWords); D(b.d_params, kServeParamWords);
         D(b.d_hot, NS); D(b.d_cold, NS); D(b.d_cnt, kCounterCount);
         M(b.h_hdr, b.dh_hdr, 2); M(b.h_slot, b.dh_slot, NS); M(b.h_res, b.dh_res, NS);
-        D(b.d_gather, srv->gather_cap); H(b.h_gather, srv->gather_cap);
+        D(b.d_gather, srv->gather_cap);
         ok = ok && hipEventCreate(&b.ev_start) == hipSuccess;
         ok = ok && hipEventCreate(&b.ev_done) == hipSuccess;
     }
+    // pinned host blocks for submissions and completions, ready before the first request
+    srv->hpool->warm(kArenaChunk, 32);
+    srv->hpool->warm(8ull << 20, 2);
+    srv->hpool->warm(16ull << 20, 2);
     ok = ok && hipStreamCreateWithFlags(&srv->s, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&srv->s_copy, hipStreamNonBlocking) == hipSuccess;
     if (ok) {
@@ -490,6 +511,29 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
 namespace {
 
 // Checks one request's sizes against the server's pools.
+// Room for `bytes` bytes of packed submissions in pinned memory: the tail of
+// the current arena chunk, a new chunk, or (large submissions) a block of
+// their own. False when no pinned memory can be had.
+bool reserve_bytes(genasm_server* srv, uint64_t bytes, std::shared_ptr<uint8_t>* block, uint64_t* off) {
+    bytes = std::max<uint64_t>(bytes, 1);
+    if (bytes > kArenaChunk / 4) {
+        *block = srv->hpool->get(bytes);
+        *off = 0;
+        return *block != nullptr;
+    }
+    std::lock_guard<std::mutex> lk(srv->arena_mu);
+    if (!srv->arena || srv->arena_used + bytes > srv->arena_size) {
+        srv->arena = srv->hpool->get(kArenaChunk);
+        srv->arena_used = 0;
+        srv->arena_size = srv->arena ? kArenaChunk : 0;
+        if (!srv->arena) return false;
+    }
+    *block = srv->arena;
+    *off = srv->arena_used;
+    srv->arena_used += bytes;
+    return true;
+}
+
 // Counts accepted requests (mu held) and, once per admission, copies the count
 // to the device, where a running iteration's turns look for news (a turn may
 // then end early and let the engine admit the new requests sooner). The copy
@@ -563,9 +607,9 @@ int genasm_submit(genasm_server* srv, const char* read, uint64_t m, const char* 
     }
     Request r;
     const uint64_t rb = (m + 3) / 4;
-    r.block = std::make_shared<std::vector<uint8_t>>(rb + (n + 3) / 4);
-    if (genasm_pack(read, m, r.block->data(), nullptr) != GENASM_OK ||
-        genasm_pack(ref, n, r.block->data() + rb, nullptr) != GENASM_OK)
+    if (!reserve_bytes(srv, rb + (n + 3) / 4, &r.block, &r.off)) return GENASM_E_NOMEM;
+    if (genasm_pack(read, m, r.block.get() + r.off, nullptr) != GENASM_OK ||
+        genasm_pack(ref, n, r.block.get() + r.off + rb, nullptr) != GENASM_OK)
         return GENASM_E_ALPHABET;
     r.m = (uint32_t)m;
     r.n = (uint32_t)n;
@@ -608,20 +652,13 @@ int genasm_submit_batch(genasm_server* srv, const uint8_t* reads2b, const uint64
     const uint64_t take = std::min(room, n_req);
     std::vector<Request> reqs(take);
     const uint64_t now = steady_ns();
-    uint64_t total = 0;
-    for (uint64_t i = 0; i < take; ++i)
-        total += (read_off[i + 1] - read_off[i] + 3) / 4 + (ref_off[i + 1] - ref_off[i] + 3) / 4;
-    auto block = std::make_shared<std::vector<uint8_t>>(std::max<uint64_t>(total, 1));
-    uint64_t at = 0;
     for (uint64_t i = 0; i < take; ++i) {
         Request& r = reqs[i];
         const uint64_t m = read_off[i + 1] - read_off[i], n = ref_off[i + 1] - ref_off[i];
         const uint64_t rb = (m + 3) / 4;
-        r.block = block;
-        r.off = at;
-        if (m) copy_bases(block->data() + at, reads2b, read_off[i], m);
-        if (n) copy_bases(block->data() + at + rb, refs2b, ref_off[i], n);
-        at += rb + (n + 3) / 4;
+        if (!reserve_bytes(srv, rb + (n + 3) / 4, &r.block, &r.off)) return GENASM_E_NOMEM;
+        if (m) copy_bases(r.block.get() + r.off, reads2b, read_off[i], m);
+        if (n) copy_bases(r.block.get() + r.off + rb, refs2b, ref_off[i], n);
         r.m = (uint32_t)m;
         r.n = (uint32_t)n;
         r.tag = tags[i];
@@ -691,7 +728,7 @@ int genasm_poll(genasm_server* srv, genasm_completion* out, int max, int timeout
         c.admit_ns = d.admit_ns;
         c.done_ns = d.done_ns;
         const uint32_t ne = d.result.cigar_len;
-        const uint32_t* el = ne ? d.block->data() + d.result.cigar_off : nullptr;
+        const uint32_t* el = ne ? d.elements() : nullptr;
         if (srv->cfg.cigar_runs) {
             c.cigar = static_cast<char*>(std::malloc(std::max<size_t>(ne, 1) * 4));
             if (c.cigar && ne) std::memcpy(c.cigar, el, (size_t)ne * 4);
@@ -737,7 +774,7 @@ int genasm_poll_batch(genasm_server* srv, genasm_completion_info* out, int max, 
         o.admit_ns = d.admit_ns;
         o.done_ns = d.done_ns;
         if (d.result.cigar_len)
-            std::memcpy(runs + used, d.block->data() + d.result.cigar_off, (size_t)d.result.cigar_len * 4);
+            std::memcpy(runs + used, d.elements(), (size_t)d.result.cigar_len * 4);
         used += d.result.cigar_len;
     }
     *runs_used = used;
@@ -805,7 +842,7 @@ void genasm_server_destroy(genasm_server* srv) {
             dev.push_back(p);
         for (void* p : {(void*)b.h_upload, (void*)b.h_up_src, (void*)b.h_up_dst, (void*)b.h_up_word,
                         (void*)b.h_up_len, (void*)b.h_up_bases, (void*)b.h_admit, (void*)b.h_params,
-                        (void*)b.h_hdr, (void*)b.h_slot, (void*)b.h_res, (void*)b.h_gather})
+                        (void*)b.h_hdr, (void*)b.h_slot, (void*)b.h_res})
             host.push_back(p);
         for (hipEvent_t e : {b.ev_start, b.ev_done})
             if (e) (void)hipEventDestroy(e);
@@ -852,9 +889,10 @@ int launch_iteration(genasm_server* srv, int q) {
             uint64_t bs, cs;
             const uint64_t rl = round_up(r.m, kBaseUnit), fl = round_up(r.n, kBaseUnit);
             const uint64_t cl = (uint64_t)r.m + r.n + 1;
-            if (!srv->pool.alloc(rl + fl, &bs)) break;
-            if (!srv->cigpool.alloc(cl, &cs)) {
-                srv->pool.release(bs, rl + fl);
+            uint32_t bh, ch;
+            if (!srv->pool.alloc(rl + fl, &bh, &bs)) break;
+            if (!srv->cigpool.alloc(cl, &ch, &cs)) {
+                srv->pool.release(bh);
                 break;
             }
             const uint32_t slot = srv->free_slots.back();
@@ -864,6 +902,8 @@ int launch_iteration(genasm_server* srv, int q) {
             sl.submit_ns = r.submit_ns;
             sl.admit_ns = now;
             sl.bstart = bs; sl.blen = rl + fl; sl.fstart = bs + rl; sl.cstart = cs; sl.clen = cl;
+            sl.bh = bh;
+            sl.ch = ch;
             srv->slot_tag[slot] = r.tag;
             srv->slot_state[slot] = 1;
             admitted_slots.push_back(slot);
@@ -878,14 +918,53 @@ int launch_iteration(genasm_server* srv, int q) {
         admitted_arrivals = srv->arrivals - srv->pending.size();
         srv->signalled = false;
     }
-    // upload staging: packed bases and the scatter ranges, admission records
-    uint64_t up = 0;
-    uint32_t nr = 0;
+    // Uploads. Requests that lie back to back in one pinned submission block
+    // form a run; a large run is copied to the device straight from its block,
+    // a small one through the staging buffer (one copy for all of them). The
+    // staged runs take the front of the device upload area, the direct ones
+    // follow. Then the scatter ranges and admission records.
     RoctxRange r_stage("genasm_serve_stage");
+    struct UpRun {
+        const Request* first;
+        uint64_t off, len, pos;
+        bool direct;
+    };
+    std::vector<UpRun> upruns;
+    std::vector<uint32_t> run_of(admitted.size());
+    for (size_t a = 0; a < admitted.size(); ++a) {
+        const Request& r = admitted[a];
+        if (!upruns.empty() && upruns.back().first->block == r.block &&
+            upruns.back().off + upruns.back().len == r.off) {
+            upruns.back().len += r.bytes();
+        } else {
+            upruns.push_back(UpRun{&r, r.off, r.bytes(), 0, false});
+        }
+        run_of[a] = (uint32_t)(upruns.size() - 1);
+    }
+    constexpr uint64_t kDirectMin = 256ull << 10;
+    uint64_t staged = 0;
+    for (UpRun& u : upruns) {
+        u.direct = u.len >= kDirectMin;
+        if (!u.direct) {
+            u.pos = staged;
+            std::memcpy(b.h_upload + staged, u.first->block.get() + u.off, u.len);
+            staged += u.len;
+        }
+    }
+    uint64_t up = staged;
+    for (UpRun& u : upruns) {
+        if (u.direct) {
+            u.pos = up;
+            up += u.len;
+        }
+    }
+    uint32_t nr = 0;
     for (size_t a = 0; a < admitted.size(); ++a) {
         const uint32_t slot = admitted_slots[a];
         const Slot& sl = srv->slots[slot];
         const Request& r = admitted[a];
+        const UpRun& u = upruns[run_of[a]];
+        const uint64_t at = u.pos + (r.off - u.off);  // the request's bytes in the upload area
         const uint64_t rb = r.read_bytes();
         const uint64_t part_off[2] = {0, rb};
         const uint64_t part_len[2] = {rb, r.bytes() - rb};
@@ -893,13 +972,11 @@ int launch_iteration(genasm_server* srv, int q) {
         const uint32_t nb[2] = {r.m, r.n};
         for (int p = 0; p < 2; ++p) {
             if (part_len[p] == 0) continue;
-            std::memcpy(b.h_upload + up, r.data() + part_off[p], part_len[p]);
-            b.h_up_src[nr] = up;
+            b.h_up_src[nr] = at + part_off[p];
             b.h_up_dst[nr] = dst[p] / 4;
             b.h_up_len[nr] = (uint32_t)part_len[p];
             b.h_up_word[nr] = dst[p] / 64;
             b.h_up_bases[nr] = nb[p];
-            up += part_len[p];
             ++nr;
         }
         ServeAdmit& ad = b.h_admit[a];
@@ -931,7 +1008,14 @@ int launch_iteration(genasm_server* srv, int q) {
     hipStream_t s = srv->s;
     SRV_HIP(srv, hipEventRecord(b.ev_start, s));
     if (nr) {
-        SRV_HIP(srv, hipMemcpyAsync(b.d_upload, b.h_upload, up, hipMemcpyHostToDevice, s));
+        if (staged)
+            SRV_HIP(srv, hipMemcpyAsync(b.d_upload, b.h_upload, staged, hipMemcpyHostToDevice, s));
+        for (const UpRun& u : upruns) {
+            if (!u.direct) continue;
+            SRV_HIP(srv, hipMemcpyAsync(b.d_upload + u.pos, u.first->block.get() + u.off, u.len,
+                                        hipMemcpyHostToDevice, s));
+            b.holds.push_back(u.first->block);  // read by the copy until the iteration ends
+        }
         SRV_HIP(srv, hipMemcpyAsync(b.d_up_src, b.h_up_src, nr * 8, hipMemcpyHostToDevice, s));
         SRV_HIP(srv, hipMemcpyAsync(b.d_up_dst, b.h_up_dst, nr * 8, hipMemcpyHostToDevice, s));
         SRV_HIP(srv, hipMemcpyAsync(b.d_up_len, b.h_up_len, nr * 4, hipMemcpyHostToDevice, s));
@@ -961,10 +1045,11 @@ int finish_iteration(genasm_server* srv, int q) {
         RoctxRange r_wait("genasm_serve_wait");
         SRV_HIP(srv, hipEventSynchronize(b.ev_done));
     }
+    b.holds.clear();  // the iteration's uploads are done
     float ms = 0.f;
     SRV_HIP(srv, hipEventElapsedTime(&ms, b.ev_start, b.ev_done));
     const uint32_t n_fin = (uint32_t)b.h_hdr[0];
-    // the gathered elements that fit the buffer, in one copy, then into one
+    // the gathered elements that fit the buffer, in one copy into a pinned
     // block that the iteration's completions share; a pair past the buffer is
     // copied from the CIGAR pool by itself, to the end of the block
     uint64_t fit = 0, over_elems = 0;
@@ -978,22 +1063,26 @@ int finish_iteration(genasm_server* srv, int q) {
             over_elems += r.cigar_len;
         }
     }
-    auto block = std::make_shared<std::vector<uint32_t>>(std::max<uint64_t>(fit + over_elems, 1));
+    std::shared_ptr<uint8_t> block;
+    if (fit + over_elems) {
+        block = srv->hpool->get((fit + over_elems) * 4);
+        if (!block) return srv_fail(srv, "pinned completion block", hipErrorOutOfMemory);
+    }
+    uint32_t* els = reinterpret_cast<uint32_t*>(block.get());
     if (fit)
-        SRV_HIP(srv, hipMemcpyAsync(b.h_gather, b.d_gather, fit * 4, hipMemcpyDeviceToHost, srv->s_copy));
+        SRV_HIP(srv, hipMemcpyAsync(els, b.d_gather, fit * 4, hipMemcpyDeviceToHost, srv->s_copy));
     uint64_t at = fit;
     std::vector<uint64_t> over_at(over.size());
     for (size_t j = 0; j < over.size(); ++j) {
         const uint32_t k = over[j];
         const Slot& sl = srv->slots[b.h_slot[k]];
         over_at[j] = at;
-        SRV_HIP(srv, hipMemcpyAsync(block->data() + at, srv->d_cigar + sl.cstart,
+        SRV_HIP(srv, hipMemcpyAsync(els + at, srv->d_cigar + sl.cstart,
                                     (size_t)b.h_res[k].cigar_len * 4, hipMemcpyDeviceToHost,
                                     srv->s_copy));
         at += b.h_res[k].cigar_len;
     }
     SRV_HIP(srv, hipStreamSynchronize(srv->s_copy));
-    if (fit) std::memcpy(block->data(), b.h_gather, fit * 4);
     RoctxRange r_records("genasm_serve_records");
     std::vector<DoneRec> recs(n_fin);
     size_t oj = 0;
@@ -1009,8 +1098,8 @@ int finish_iteration(genasm_server* srv, int q) {
         d.admit_ns = sl.admit_ns;
         d.done_ns = now;
         d.block = block;
-        srv->pool.release(sl.bstart, sl.blen);
-        srv->cigpool.release(sl.cstart, sl.clen);
+        srv->pool.release(sl.bh);
+        srv->cigpool.release(sl.ch);
     }
     srv->resident -= std::min(srv->resident, n_fin);
     std::lock_guard<std::mutex> lk(srv->mu);
