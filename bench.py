@@ -73,6 +73,8 @@ def measured_peaks(ctx, achieved):
     pk = ctx.measure_peaks()
     return {"dc_mix_tops": pk["dc_mix_tops"], "int32_tops": pk["int32_tops"],
             "lds_tbps": pk["lds_tbps"], "hbm_tbps": pk["hbm_tbps"],
+            "shift64_tops": pk["shift64_tops"], "funnel_tops": pk["funnel_tops"],
+            "dpp_tops": pk["dpp_tops"],
             "frac_of_dc_mix": achieved / pk["dc_mix_tops"],
             "frac_of_int32": achieved / pk["int32_tops"]}
 

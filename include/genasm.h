@@ -549,11 +549,15 @@ uint64_t genasm_now_ns(void);
  * work, timed with HIP events on the context's stream:
  *   dc_mix_tops  the DC recurrence's own step in registers, as the window
  *                kernels execute it (one DPP lane shift of a 64-bit word and
- *                six 64-bit and/or/shift operations, counted as 12 int32
- *                operations), on independent chains at full occupancy;
+ *                six 64-bit and/or/shift operations worked on 32-bit halves,
+ *                counted as 12 int32 operations), on independent chains at
+ *                full occupancy;
  *   int32_tops   plain 32-bit and/or/xor chains;
  *   lds_tbps     16-byte LDS reads without bank conflicts;
- *   hbm_tbps     a 1 GiB device-to-device copy (read + write bytes).
+ *   hbm_tbps     a 1 GiB device-to-device copy (read + write bytes);
+ *   shift64_tops v_lshlrev_b64 chains (each counted as two int32 operations);
+ *   funnel_tops  v_alignbit_b32 chains (32-bit funnel shift);
+ *   dpp_tops     v_mov_b32_dpp row rotations.
  * Allocates about 2 GiB of device memory for the duration of the call.
  */
 typedef struct {
@@ -561,6 +565,9 @@ typedef struct {
     double int32_tops;
     double lds_tbps;      /* bytes per second / 1e12 */
     double hbm_tbps;
+    double shift64_tops;  /* int32 lane-operations per second / 1e12 */
+    double funnel_tops;
+    double dpp_tops;
     int32_t compute_units;
     int32_t reserved;
 } genasm_peaks;

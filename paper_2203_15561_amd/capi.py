@@ -121,6 +121,9 @@ class Peaks(ctypes.Structure):
         ("int32_tops", ctypes.c_double),
         ("lds_tbps", ctypes.c_double),
         ("hbm_tbps", ctypes.c_double),
+        ("shift64_tops", ctypes.c_double),
+        ("funnel_tops", ctypes.c_double),
+        ("dpp_tops", ctypes.c_double),
         ("compute_units", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
     ]

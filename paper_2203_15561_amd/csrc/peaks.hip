@@ -1,8 +1,9 @@
 // Microbenchmarks of the gfx950 limits the window kernel is measured
 // against: the rate of the DC recurrence's own integer instruction mix in
-// registers, plain 32-bit integer VALU throughput, LDS bandwidth and HBM
-// bandwidth. Each kernel's work is known exactly, so achieved rate = work /
-// time of the launch (HIP events).
+// registers, plain 32-bit integer VALU throughput, the issue rates of the
+// instruction kinds the recurrence is built from (64-bit shift, 32-bit funnel
+// shift, DPP lane move), LDS bandwidth and HBM bandwidth. Each kernel's work is
+// known exactly, so achieved rate = work / time of the launch (HIP events).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -21,7 +22,8 @@ constexpr int kMixSteps = 4096;   // steps of each chain per launch
 // The DC step, as the window kernels execute it, on kChains independent
 // chains: one DPP lane shift of a 64-bit word (the row above), then
 //   x = D & (((D & up) << 1) | low);  R = x & ((R << 1) | pm)
-// = 6 64-bit operations = 12 int32 lane-operations per step and chain. The
+// on 32-bit halves (the high halves' shifts as funnel shifts), counted as its
+// 6 64-bit operations = 12 int32 lane-operations per step and chain. The
 // result is stored so that nothing is optimized away.
 __global__ __launch_bounds__(256) void k_peak_mix(const u64* in, u64* out) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -42,10 +44,15 @@ __global__ __launch_bounds__(256) void k_peak_mix(const u64* in, u64* out) {
             const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(
                 (int)(unsigned)(R[c] >> 32), (int)(unsigned)(R[c] >> 32), 0x111, 0xF, 0xF, false);
             const u64 up = ((u64)hi << 32) | lo;
-            const u64 x = D[c] & (((D[c] & up) << 1) | low);
-            const u64 r = x & ((R[c] << 1) | pm);
+            const uint32_t Rl = (uint32_t)R[c], Rh = (uint32_t)(R[c] >> 32);
+            const uint32_t Dl = (uint32_t)D[c], Dh = (uint32_t)(D[c] >> 32);
+            const uint32_t el = Dl & lo, eh = Dh & hi;
+            const uint32_t xl = Dl & ((el << 1) | (uint32_t)low);
+            const uint32_t xh = Dh & __builtin_amdgcn_alignbit(eh, el, 31);
+            const uint32_t sl = (Rl << 1) | (uint32_t)pm;
+            const uint32_t sh = __builtin_amdgcn_alignbit(Rh, Rl, 31) | (uint32_t)(pm >> 32);
             D[c] = up;
-            R[c] = r;
+            R[c] = ((u64)(xh & sh) << 32) | (xl & sl);
         }
     }
     u64 acc = 0;
@@ -67,6 +74,42 @@ __global__ __launch_bounds__(256) void k_peak_int32(const unsigned* in, unsigned
         for (int c = 0; c < kChains; ++c) a[c] = ((a[c] & b) | c2) ^ (unsigned)s;
     }
     unsigned acc = 0;
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) acc ^= a[c];
+    out[t] = acc;
+}
+
+// Issue rate of one instruction kind: kChains independent chains per lane,
+// each instruction reading and writing its own chain. OP 0: v_lshlrev_b64 by
+// one; OP 1: v_alignbit_b32 (32-bit funnel shift); OP 2: v_mov_b32_dpp row
+// rotation by one lane.
+template <int OP>
+__device__ __forceinline__ void op_step(u64& a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (OP == 0) {
+        asm volatile("v_lshlrev_b64 %0, 1, %0" : "+v"(a));
+    } else {
+        uint32_t lo = (uint32_t)a;
+        const uint32_t hi = (uint32_t)(a >> 32);
+        if constexpr (OP == 1) asm volatile("v_alignbit_b32 %0, %0, %1, 31" : "+v"(lo) : "v"(hi));
+        else asm volatile("v_mov_b32_dpp %0, %0 row_ror:1 row_mask:0xf bank_mask:0xf" : "+v"(lo));
+        a = ((u64)hi << 32) | lo;
+    }
+#else
+    a = a << 1;
+#endif
+}
+template <int OP>
+__global__ __launch_bounds__(256) void k_peak_op(const u64* in, u64* out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    u64 a[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) a[c] = in[2 + c] ^ (u64)t;
+    for (int s = 0; s < kMixSteps; ++s) {
+#pragma unroll
+        for (int c = 0; c < kChains; ++c) op_step<OP>(a[c]);
+    }
+    u64 acc = 0;
 #pragma unroll
     for (int c = 0; c < kChains; ++c) acc ^= a[c];
     out[t] = acc;
@@ -163,6 +206,22 @@ int genasm_measure_peaks(genasm_ctx* ctx, genasm_peaks* out) {
             break;
         }
         out->lds_tbps = (double)threads * kLdsSteps * 16 / (ms / 1e3) / 1e12;
+        // a 64-bit shift counts as two int32 lane-operations, the others as one
+        const double op_work = (double)threads * kMixSteps * kChains;
+        double* const op_out[3] = {&out->shift64_tops, &out->funnel_tops, &out->dpp_tops};
+        bool op_ok = true;
+        for (int op = 0; op < 3 && op_ok; ++op) {
+            op_ok = timed([&] {
+                if (op == 0) hipLaunchKernelGGL(k_peak_op<0>, dim3(blocks), dim3(256), 0, s, d_in, d_out);
+                else if (op == 1) hipLaunchKernelGGL(k_peak_op<1>, dim3(blocks), dim3(256), 0, s, d_in, d_out);
+                else hipLaunchKernelGGL(k_peak_op<2>, dim3(blocks), dim3(256), 0, s, d_in, d_out);
+            }, &ms);
+            *op_out[op] = op_work * (op == 0 ? 2 : 1) / (ms / 1e3) / 1e12;
+        }
+        if (!op_ok) {
+            rc = GENASM_E_DEVICE;
+            break;
+        }
         if (!timed([&] {
                 hipLaunchKernelGGL(k_peak_copy, dim3(cus * 16), dim3(256), 0, s, d_src, d_dst, copy_words);
             }, &ms)) {

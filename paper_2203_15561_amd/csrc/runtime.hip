@@ -518,10 +518,11 @@ int align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_
     const int search_blocks = ctx->num_cus * L.search_per_cu;
     const int spill_rows = p.compact ? kCompactSpillRows : 64 - L.lds_rows;
     // Search chunks: at least kBatchSearchChunk columns, and large enough that
-    // the batch makes about two items per search group, so that a long
-    // reference splits only when the groups would otherwise sit idle.
+    // the batch makes about two items per search group (counted at 8 search
+    // workgroups per CU), so that a long reference splits only when the groups
+    // would otherwise sit idle.
     {
-        const uint64_t groups = (uint64_t)search_blocks * (64 / SG);
+        const uint64_t groups = (uint64_t)ctx->num_cus * 8 * (64 / SG);
         const uint64_t want = (total_ref_bases + 2 * groups - 1) / (2 * groups);
         p.search_chunk = (uint32_t)std::min<uint64_t>(
             std::max<uint64_t>(kBatchSearchChunk, (want + 1023) / 1024 * 1024), 1u << 30);

@@ -202,6 +202,7 @@ struct IterBufs {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev_start = nullptr, ev_done = nullptr;
+    hipEvent_t ev_up = nullptr;  // the iteration's uploads are done
     uint32_t n_new = 0;
 };
 
@@ -213,7 +214,9 @@ struct genasm_server {
     AlignParams base{};   // fields common to every iteration's kernels
     int search_blocks = 0, win_blocks = 0;
     uint32_t groups = 0;  // 16-lane window groups of the persistent grid
-    hipStream_t s = nullptr, s_copy = nullptr;
+    // s: the iterations; s_up: their uploads, which overlap the iteration
+    // before; s_copy: completions to the host and the arrival count
+    hipStream_t s = nullptr, s_up = nullptr, s_copy = nullptr;
     uint64_t gather_cap = 0;  // elements per gather buffer
 
     // device state shared by both parities
@@ -423,6 +426,7 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
         D(b.d_gather, srv->gather_cap);
         ok = ok && hipEventCreate(&b.ev_start) == hipSuccess;
         ok = ok && hipEventCreate(&b.ev_done) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&b.ev_up, hipEventDisableTiming) == hipSuccess;
     }
     // pinned host blocks for submissions and completions, ready before the first request
     srv->hpool->warm(kArenaChunk, 32);
@@ -430,6 +434,7 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     srv->hpool->warm(16ull << 20, 2);
     ok = ok && hipStreamCreateWithFlags(&srv->s, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&srv->s_copy, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&srv->s_up, hipStreamNonBlocking) == hipSuccess;
     if (ok) {
         // both counters blocks start empty (no resident pairs)
         for (IterBufs& b : srv->it)
@@ -827,6 +832,7 @@ void genasm_server_destroy(genasm_server* srv) {
     (void)hipSetDevice(srv->ctx->device);
     if (srv->s) (void)hipStreamSynchronize(srv->s);
     if (srv->s_copy) (void)hipStreamSynchronize(srv->s_copy);
+    if (srv->s_up) (void)hipStreamSynchronize(srv->s_up);
     std::vector<void*> dev = {srv->d_pool, srv->d_plo, srv->d_phi, srv->d_cigar, srv->d_read_off,
                               srv->d_ref_off, srv->d_run_base, srv->d_read_len, srv->d_ref_len,
                               srv->d_out, srv->d_state, srv->d_search, srv->d_new, srv->d_fin,
@@ -844,7 +850,7 @@ void genasm_server_destroy(genasm_server* srv) {
                         (void*)b.h_up_len, (void*)b.h_up_bases, (void*)b.h_admit, (void*)b.h_params,
                         (void*)b.h_hdr, (void*)b.h_slot, (void*)b.h_res})
             host.push_back(p);
-        for (hipEvent_t e : {b.ev_start, b.ev_done})
+        for (hipEvent_t e : {b.ev_start, b.ev_done, b.ev_up})
             if (e) (void)hipEventDestroy(e);
     }
     for (void* p : dev)
@@ -853,6 +859,7 @@ void genasm_server_destroy(genasm_server* srv) {
         if (p) (void)hipHostFree(p);
     if (srv->s) (void)hipStreamDestroy(srv->s);
     if (srv->s_copy) (void)hipStreamDestroy(srv->s_copy);
+    if (srv->s_up) (void)hipStreamDestroy(srv->s_up);
     delete srv;
 }
 
@@ -1005,31 +1012,38 @@ int launch_iteration(genasm_server* srv, int q) {
     b.h_params[kServeParamSoonTicks] = soon_us * 100u;
     b.h_params[kServeParamAdmitted] = (uint32_t)admitted_arrivals;
     b.h_params[kServeParamAdmitted + 1] = (uint32_t)(admitted_arrivals >> 32);
-    hipStream_t s = srv->s;
+    // The uploads go on their own stream and overlap the running iteration (this
+    // parity's buffers were last read by the iteration before it, which has
+    // finished); the iteration waits for them on its stream.
+    hipStream_t s = srv->s, su = srv->s_up;
     SRV_HIP(srv, hipEventRecord(b.ev_start, s));
     if (nr) {
         if (staged)
-            SRV_HIP(srv, hipMemcpyAsync(b.d_upload, b.h_upload, staged, hipMemcpyHostToDevice, s));
+            SRV_HIP(srv, hipMemcpyAsync(b.d_upload, b.h_upload, staged, hipMemcpyHostToDevice, su));
         for (const UpRun& u : upruns) {
             if (!u.direct) continue;
             SRV_HIP(srv, hipMemcpyAsync(b.d_upload + u.pos, u.first->block.get() + u.off, u.len,
-                                        hipMemcpyHostToDevice, s));
+                                        hipMemcpyHostToDevice, su));
             b.holds.push_back(u.first->block);  // read by the copy until the iteration ends
         }
-        SRV_HIP(srv, hipMemcpyAsync(b.d_up_src, b.h_up_src, nr * 8, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(b.d_up_dst, b.h_up_dst, nr * 8, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(b.d_up_len, b.h_up_len, nr * 4, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(b.d_up_word, b.h_up_word, nr * 8, hipMemcpyHostToDevice, s));
-        SRV_HIP(srv, hipMemcpyAsync(b.d_up_bases, b.h_up_bases, nr * 4, hipMemcpyHostToDevice, s));
+        SRV_HIP(srv, hipMemcpyAsync(b.d_up_src, b.h_up_src, nr * 8, hipMemcpyHostToDevice, su));
+        SRV_HIP(srv, hipMemcpyAsync(b.d_up_dst, b.h_up_dst, nr * 8, hipMemcpyHostToDevice, su));
+        SRV_HIP(srv, hipMemcpyAsync(b.d_up_len, b.h_up_len, nr * 4, hipMemcpyHostToDevice, su));
+        SRV_HIP(srv, hipMemcpyAsync(b.d_up_word, b.h_up_word, nr * 8, hipMemcpyHostToDevice, su));
+        SRV_HIP(srv, hipMemcpyAsync(b.d_up_bases, b.h_up_bases, nr * 4, hipMemcpyHostToDevice, su));
+    }
+    if (n_new)
+        SRV_HIP(srv, hipMemcpyAsync(b.d_admit, b.h_admit, n_new * sizeof(ServeAdmit),
+                                    hipMemcpyHostToDevice, su));
+    SRV_HIP(srv, hipMemcpyAsync(b.d_params, b.h_params, kServeParamWords * 4, hipMemcpyHostToDevice, su));
+    SRV_HIP(srv, hipEventRecord(b.ev_up, su));
+    SRV_HIP(srv, hipStreamWaitEvent(s, b.ev_up, 0));
+    if (nr) {
         SRV_HIP(srv, launch_scatter_bytes(b.d_upload, b.d_up_src, srv->d_pool, b.d_up_dst, b.d_up_len,
                                           nr, s));
         SRV_HIP(srv, launch_scatter_planes(b.d_upload, b.d_up_src, b.d_up_bases, srv->d_plo,
                                            srv->d_phi, b.d_up_word, nr, s));
     }
-    if (n_new)
-        SRV_HIP(srv, hipMemcpyAsync(b.d_admit, b.h_admit, n_new * sizeof(ServeAdmit),
-                                    hipMemcpyHostToDevice, s));
-    SRV_HIP(srv, hipMemcpyAsync(b.d_params, b.h_params, kServeParamWords * 4, hipMemcpyHostToDevice, s));
     if (b.exec) SRV_HIP(srv, hipGraphLaunch(b.exec, s));
     else SRV_HIP(srv, enqueue_iteration(srv, q));
     SRV_HIP(srv, hipEventRecord(b.ev_done, s));

@@ -504,3 +504,16 @@ def test_injected_allocation_failure(monkeypatch):
         assert_same(ps, want, on_gpu(fresh, ps), "after the injected failure")
     finally:
         fresh.close()
+
+
+def test_measured_peaks_are_plausible(ctx):
+    """genasm_measure_peaks: every rate positive and each microbenchmark
+    within what one MI355X can do (below the published or derived peaks; the
+    64-bit shift issuing no faster than plain int32 operations)."""
+    pk = ctx.measure_peaks()
+    assert pk["compute_units"] == 256
+    for key in ("dc_mix_tops", "int32_tops", "shift64_tops", "funnel_tops", "dpp_tops"):
+        assert 1.0 < pk[key] < 2 * 78.6, (key, pk[key])
+    assert pk["shift64_tops"] <= pk["int32_tops"] * 1.05
+    assert 0.5 < pk["hbm_tbps"] < 8.0
+    assert pk["lds_tbps"] > 1.0
