@@ -76,7 +76,8 @@ typedef struct {
 } genasm_result;
 
 #define GENASM_FLAG_CIGAR_OVERFLOW 1u  /* device form: the CIGAR did not fit; cigar_len is 0 */
-#define GENASM_FLAG_INTERNAL 2u        /* traceback found no valid edge (never expected) */
+#define GENASM_FLAG_INTERNAL 2u        /* traceback found no valid edge, or (debug builds) a checked
+                                          invariant failed for this pair; never expected */
 
 /* Device-form CIGAR element: run length in bits 31..2, op in bits 1..0. */
 #define GENASM_OP_MATCH 0u    /* '=' */

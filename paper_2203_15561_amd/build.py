@@ -13,6 +13,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgenasm.so")
+# debug variant (GENASM_DEBUG): invariant checks before the guarded LDS and
+# spill accesses and a queue audit, reported through the pairs' result flags
+LIB_DEBUG = os.path.join(HERE, "libgenasm_debug.so")
 SOURCES = ["kernels.hip", "runtime.hip", "server.hip", "peaks.hip"]
 ARCH = "gfx950"
 
@@ -34,11 +37,12 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False, extra_flags=None) -> str:
+def build(verbose: bool = False, extra_flags=None, debug: bool = False) -> str:
     objs = []
-    build_dir = os.path.join(HERE, "_build")
+    build_dir = os.path.join(HERE, "_build_debug" if debug else "_build")
     os.makedirs(build_dir, exist_ok=True)
-    flags = HIPCC_FLAGS + list(extra_flags or [])
+    flags = HIPCC_FLAGS + (["-DGENASM_DEBUG"] if debug else []) + list(extra_flags or [])
+    lib = LIB_DEBUG if debug else LIB
     for src in SOURCES:
         obj = os.path.join(build_dir, src.replace(".hip", ".o"))
         cmd = [hipcc(), *flags, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
@@ -46,15 +50,16 @@ def build(verbose: bool = False, extra_flags=None) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
            "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    write_build_info()
-    return LIB
+    os.replace(tmp, lib)
+    if not debug:
+        write_build_info()
+    return lib
 
 
 BUILD_INFO = os.path.join(HERE, "BUILD_INFO.json")
@@ -80,4 +85,4 @@ def write_build_info() -> None:
 
 
 if __name__ == "__main__":
-    build(verbose="-q" not in sys.argv)
+    build(verbose="-q" not in sys.argv, debug="--debug" in sys.argv)

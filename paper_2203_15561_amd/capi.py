@@ -12,7 +12,11 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgenasm.so")
+# GENASM_LIB_VARIANT=debug loads the debug build (invariant checks and a queue
+# audit, reported as GENASM_FLAG_INTERNAL in the results); the default is the
+# release build
+LIB_PATH = os.path.join(HERE, "libgenasm_debug.so" if os.environ.get("GENASM_LIB_VARIANT") == "debug"
+                        else "libgenasm.so")
 
 OK = 0
 E_INVAL = -1

@@ -27,6 +27,9 @@ struct genasm_ctx {
     // host-form staging (device)
     char* stage = nullptr;
     size_t stage_cap = 0;
+    // debug builds: per-pair audit words (device)
+    char* dbg = nullptr;
+    size_t dbg_cap = 0;
     // device address of the static scratch of the no-allocation device form
     // on this context's device
     void* static_scratch = nullptr;
@@ -148,7 +151,21 @@ struct AlignParams {
     uint32_t* next_cold;        // unfinished pairs that advanced more
     uint32_t* next_len;         // counters block of the next launch: its easy (hot) and hard
                                 // (cold) list lengths at kCounterEasyLen / kCounterHardLen
+    // Debug builds (GENASM_DEBUG) only: per-pair audit word (kAudit* bits in the
+    // low half, the number of workers that took the pair in the high half).
+    uint32_t* audit;
 };
+
+// Audit bits of a debug build: an invariant that failed for the pair. The
+// check runs before the access it guards, and a failed check ends the pair
+// (GENASM_FLAG_INTERNAL) instead of letting the access go out of bounds.
+constexpr uint32_t kAuditWindow = 1u;  // window sizes outside 1..W, or W past 64
+constexpr uint32_t kAuditLds = 2u;     // a DC pass's rows or columns outside the LDS table
+constexpr uint32_t kAuditSpill = 4u;   // a DC pass's rows outside the worker's spill area
+constexpr uint32_t kAuditRuns = 8u;    // more run records than the run area holds
+constexpr uint32_t kAuditTable = 16u;  // a traceback read outside the rows or columns stored
+constexpr uint32_t kAuditQueue = 32u;  // a pair taken by no window worker or by more than one
+constexpr uint32_t kAuditTake = 1u << 16;  // one worker took the pair
 
 // Per-pair work counters written when AlignParams::stats is set.
 constexpr int kStatWindowWordOps = 0;   // sum over windows of nw * (2 + 6 d*)  (64-bit DC ops)
@@ -220,6 +237,10 @@ hipError_t launch_search(const AlignParams& p, int group_lanes, int rows_per_lan
 // Start-search workgroups one compute unit holds at once, 0 on error.
 int search_blocks_per_cu(int group_lanes, int rows_per_lane);
 hipError_t launch_windows(const AlignParams& p, int blocks, hipStream_t s);
+// Debug builds: after the window kernel, checks that every pair whose search
+// hit was taken by exactly one worker (batched form: `queued` = 1) and marks
+// each pair with an audit bit GENASM_FLAG_INTERNAL in its result.
+hipError_t launch_audit(const AlignParams& p, int queued, hipStream_t s);
 // Window workgroups one compute unit holds at once (registers and LDS), 0 on error.
 int windows_blocks_per_cu(const AlignParams& p);
 hipError_t launch_pack(const char* ascii, uint64_t n, uint8_t* packed, uint32_t* bad,
@@ -281,6 +302,8 @@ hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long
 // Longest-read-first pair order (approximate: reads are bucketed by length)
 // into order[0..n_pairs); hist is kLptBuckets words of scratch.
 constexpr int kLptBuckets = 336;
+// Clears n 32-bit words.
+hipError_t launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s);
 hipError_t launch_lpt_order(const uint64_t* read_off, uint64_t n_pairs, uint32_t* hist,
                             uint32_t* order, hipStream_t s);
 hipError_t launch_compact_cigar(const genasm_result* d_out, const uint64_t* dst_off,

@@ -870,6 +870,29 @@ struct TurnClock {
     }
 };
 
+// Debug builds (GENASM_DEBUG): an invariant guarding the accesses that
+// follow; when it fails, the pair's audit word records `bit` (all lanes of the
+// group write the same bit) and the caller ends the pair. Release builds
+// compile the check away.
+__device__ __forceinline__ bool audit_ok(const AlignParams& P, uint64_t pair, uint32_t bit, bool ok) {
+#if defined(GENASM_DEBUG)
+    if (!ok && P.audit) atomicOr(P.audit + pair, bit);
+    return ok;
+#else
+    (void)P; (void)pair; (void)bit; (void)ok;
+    return true;
+#endif
+}
+
+// Rows of the spill area one G-lane group may use: (64 - lds_rows) of the
+// 16-lane layout per 16-lane group, a 32-lane group owning two such areas;
+// 64-lane groups keep every row in LDS.
+template <int G>
+__device__ __forceinline__ int spill_capacity(const AlignParams& P) {
+    if constexpr (G == 64) return 0;
+    else return (G / 16) * (64 - P.lds_rows);
+}
+
 // Advances one pair whose window state is `st` by at most `budget` windows
 // (0: to the end). All G lanes of the group call this together; lane 0 holds
 // the traceback-side fields (score, open run). When the pair ends (read
@@ -912,6 +935,12 @@ __device__ __forceinline__ uint32_t advance_pair(const AlignParams& P, u64* lds,
         const int mw = min(P.W, pc.m - st.pj);
         const int nw = min(P.W, pc.n - st.ti);
         const int Lc = min(nw, P.L);
+        if (!audit_ok(P, pair, kAuditWindow,
+                      P.W >= 2 && P.W <= 64 && mw >= 1 && nw >= 0 && Lc + 2 <= P.stride)) {
+            failed = true;
+            internal = true;
+            break;
+        }
         ++st.nwin;
         ++done_here;
         const u64 cyc0 = timing ? clock64() : 0;
@@ -930,9 +959,14 @@ __device__ __forceinline__ uint32_t advance_pair(const AlignParams& P, u64* lds,
         }
         int dstar = -1;
         st_cells += (u64)mw * nw;
+        bool pass_ok = true;
         for (int c = 0; c * G <= Kr; ++c) {
             st_steps += (u64)G * (nw + G - 1);
             const bool spill_pass = c * G >= lds_rows;
+            pass_ok = spill_pass
+                ? audit_ok(P, pair, kAuditSpill, (c + 1) * G - lds_rows <= spill_capacity<G>(P))
+                : audit_ok(P, pair, kAuditLds, (c + 1) * G <= lds_rows);
+            if (!pass_ok) break;
             if constexpr (G != 64) {
                 if (c >= 1) {
                     fill_brow<G>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
@@ -963,6 +997,7 @@ __device__ __forceinline__ uint32_t advance_pair(const AlignParams& P, u64* lds,
             const u64 bits = group_ballot(sol, G, lane);
             if (bits) { dstar = c * G + __builtin_ctzll(bits); break; }
         }
+        if (!pass_ok) { failed = true; internal = true; break; }
         if (dstar < 0) {
             if (mw <= P.K) dstar = mw;  // no row below mw solves: d* = mw
             else { failed = true; break; }
@@ -985,6 +1020,11 @@ __device__ __forceinline__ uint32_t advance_pair(const AlignParams& P, u64* lds,
         st_wops += (u64)nw * (2 + 6 * dstar);
         st_table += (u64)(dstar + 1) * (Lc + 1);
         if (t.internal) { failed = true; internal = true; break; }
+        if (!audit_ok(P, pair, kAuditRuns, rs.nr <= 2 * min(P.L, dstar) + 1)) {
+            failed = true;
+            internal = true;
+            break;
+        }
         wave_sync();  // run records written by the writer lane
         // closed runs of this window (slots below the open run) go to device memory
         const int closed = max(rs.nr, 0);
@@ -1053,6 +1093,9 @@ __device__ __forceinline__ uint32_t advance_pair(const AlignParams& P, u64* lds,
 template <int G>
 __device__ __forceinline__ void run_pair(const AlignParams& P, u64* lds, u64* spill, int lds_rows, int gl,
                          int lane, uint64_t pair, int s) {
+#if defined(GENASM_DEBUG)
+    if (P.audit && gl == 0) atomicAdd(P.audit + pair, kAuditTake);  // queue audit
+#endif
     const PairCursor pc = pair_cursor(P, pair);
     if (!P.state) {
         PairState st = fresh_state(s);
@@ -2083,6 +2126,9 @@ __device__ __forceinline__ uint32_t advance_pair_c(const AlignParams& P, u64* ld
 template <bool STATS>
 __device__ __forceinline__ void run_pair_c(const AlignParams& P, u64* lds, u64* spill, int gl, int lane,
                                            uint64_t pair, int s, bool deep_start) {
+#if defined(GENASM_DEBUG)
+    if (P.audit && gl == 0) atomicAdd(P.audit + pair, kAuditTake);  // queue audit
+#endif
     const PairCursor pc = pair_cursor(P, pair);
     if (!P.state) {
         PairState st = fresh_state(s);
@@ -2463,6 +2509,21 @@ __global__ void k_zero_u32(uint32_t* p, uint32_t n) {
     if (i < n) p[i] = 0u;
 }
 
+// Debug builds: the queue audit (batched form: a pair whose search hit is
+// taken by exactly one window worker, a pair that ended in the search by
+// none) and the hand-over of every audit bit to the pair's result flags.
+__global__ void k_audit(AlignParams P, int queued) {
+    const uint64_t pair = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pair >= P.n_pairs || !P.audit) return;
+    uint32_t a = P.audit[pair];
+    if (queued) {
+        const uint32_t expected = P.search[pair].row >= 0 ? 1u : 0u;
+        if (a / kAuditTake != expected) a |= kAuditQueue;
+    }
+    if (a % kAuditTake) P.out[pair].flags |= GENASM_FLAG_INTERNAL;
+    P.audit[pair] = a;
+}
+
 // Copies each pair's CIGAR elements to dst + dst_off[pair] (one block per pair).
 __global__ void k_compact(const genasm_result* out, const uint64_t* dst_off, uint64_t n_pairs,
                           const uint32_t* cigar, uint32_t* dst) {
@@ -2558,6 +2619,13 @@ int windows_blocks_per_cu(const AlignParams& p) {
     return e == hipSuccess ? n : 0;
 }
 
+hipError_t launch_audit(const AlignParams& p, int queued, hipStream_t s) {
+    if (!p.audit || p.n_pairs == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((p.n_pairs + 255) / 256);
+    hipLaunchKernelGGL(k_audit, dim3(blocks), dim3(256), 0, s, p, queued);
+    return hipGetLastError();
+}
+
 hipError_t launch_windows(const AlignParams& p, int blocks, hipStream_t s) {
     if (p.compact) {
         const int lds = compact_lds_bytes(p.stride);
@@ -2645,6 +2713,14 @@ hipError_t launch_scatter_planes(const uint8_t* src, const uint64_t* src_off, co
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t n, unsigned long long v, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s) {
+    for (uint64_t at = 0; at < n; at += 1ull << 30) {
+        const uint32_t k = (uint32_t)(n - at < (1ull << 30) ? n - at : (1ull << 30));
+        hipLaunchKernelGGL(k_zero_u32, dim3((k + 255) / 256), dim3(256), 0, s, p + at, k);
+    }
     return hipGetLastError();
 }
 

@@ -282,6 +282,7 @@ void genasm_destroy(genasm_ctx* ctx) {
     if (ctx->planes) (void)hipFree(ctx->planes);
     if (ctx->unimp) (void)hipFree(ctx->unimp);
     if (ctx->stage) (void)hipFree(ctx->stage);
+    if (ctx->dbg) (void)hipFree(ctx->dbg);
     if (ctx->stats) (void)hipFree(ctx->stats);
     for (hipEvent_t e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -480,6 +481,16 @@ int align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_
                              const_cast<unsigned long long*>(p.ref_lo),
                              const_cast<unsigned long long*>(p.ref_hi), s);
     };
+#if defined(GENASM_DEBUG)
+    // debug builds: per-pair audit words, cleared before the kernels run (the
+    // no-allocation form runs without them)
+    if (!noalloc && L.form != GENASM_FORM_UNIMPROVED) {
+        rc = ensure(ctx, &ctx->dbg, &ctx->dbg_cap, n_pairs * sizeof(uint32_t));
+        if (rc) return rc;
+        p.audit = reinterpret_cast<uint32_t*>(ctx->dbg);
+        CHECK_HIP(ctx, launch_zero_u32(p.audit, n_pairs, s));
+    }
+#endif
     if (L.form == GENASM_FORM_UNIMPROVED) {
         p.lds_rows = 64;
         rc = ensure(ctx, &ctx->unimp, &ctx->unimp_cap, unimproved_table_words(n_pairs) * 8);
@@ -499,6 +510,7 @@ int align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_
         CHECK_HIP(ctx, mark(1));
         CHECK_HIP(ctx, mark(2));
         CHECK_HIP(ctx, launch_plain(p, s));
+        CHECK_HIP(ctx, launch_audit(p, 0, s));  // debug builds only
         CHECK_HIP(ctx, mark(3));
         return GENASM_OK;
     }
@@ -612,6 +624,7 @@ int align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_
     p.items_in = nullptr;
     p.items_out = nullptr;
     CHECK_HIP(ctx, launch_windows(p, win_blocks, s));
+    CHECK_HIP(ctx, launch_audit(p, 1, s));  // debug builds only
     CHECK_HIP(ctx, mark(3));
     return GENASM_OK;
 }

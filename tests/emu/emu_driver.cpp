@@ -68,6 +68,12 @@ int main(int argc, char** argv) {
     p.out = out.data();
     p.cigar = cigar.data();
     p.cigar_cap = cap;
+#if defined(GENASM_DEBUG)
+    // debug build: per-pair audit words, handed to the results by the audit
+    // kernel after the window work (plain and batched forms)
+    std::vector<uint32_t> audit(std::max<uint64_t>(n, 1), 0u);
+    p.audit = form == 2 ? nullptr : audit.data();
+#endif
     // bit planes of both streams: from base 0 for the serving loop (slot offsets
     // are absolute), from the first offset otherwise, as the runtime does
     const bool serve = form == 2;
@@ -257,6 +263,7 @@ int main(int argc, char** argv) {
         emu::group_lanes = 64;
         p.lds_rows = 64;
         launch_plain(p, nullptr);
+        launch_audit(p, 0, nullptr);  // debug builds only
     } else if (form == GENASM_FORM_UNIMPROVED) {
         emu::group_lanes = 64;
         p.lds_rows = 64;
@@ -342,6 +349,8 @@ int main(int argc, char** argv) {
             emu::group_lanes = 16;
             launch_windows(p, blocks, nullptr);
         }
+        emu::group_lanes = 64;
+        launch_audit(p, 1, nullptr);  // debug builds only
         fprintf(stderr, "emu: %u easy pairs, %u hard pairs\n", n_easy, n_hard);
     }
     FILE* g = fopen(argv[2], "wb");

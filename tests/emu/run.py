@@ -13,12 +13,15 @@ RESULT_DTYPE = np.dtype([("edit_distance", "<i4"), ("ref_begin", "<u4"), ("ref_e
                          ("flags", "<u4")])
 
 
-def build(out_path: str, sanitize: bool = True) -> str:
+def build(out_path: str, sanitize: bool = True, debug: bool = False) -> str:
+    """debug: the GENASM_DEBUG build (invariant checks and the queue audit)."""
     cmd = ["g++", "-std=c++20", "-O1", "-g", "-fno-omit-frame-pointer", "-I", HERE,
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2203_15561_amd", "csrc"),
            "-x", "c++", os.path.join(HERE, "emu_driver.cpp"), "-o", out_path, "-lpthread"]
     if sanitize:
         cmd[1:1] = ["-fsanitize=address,undefined"]
+    if debug:
+        cmd[1:1] = ["-DGENASM_DEBUG"]
     subprocess.check_call(cmd)
     return out_path
 

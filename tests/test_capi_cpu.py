@@ -102,3 +102,11 @@ def test_create_without_device_is_an_error():
     with pytest.raises(ga.GenasmError) as e:
         ga.Context(0)
     assert e.value.code == capi.E_DEVICE
+
+
+def test_debug_library_exports_every_declared_symbol():
+    # the GENASM_DEBUG build (invariant checks, queue audit) keeps the same ABI
+    path = os.path.join(os.path.dirname(capi.LIB_PATH), "libgenasm_debug.so")
+    lib = ctypes.CDLL(path)
+    for name in declared_functions():
+        assert hasattr(lib, name), name

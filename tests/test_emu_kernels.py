@@ -24,6 +24,12 @@ def driver():
         yield emu.build(os.path.join(tmp, "emu_driver"))
 
 
+@pytest.fixture(scope="module")
+def debug_driver():
+    with tempfile.TemporaryDirectory() as tmp:
+        yield emu.build(os.path.join(tmp, "emu_driver_debug"), debug=True)
+
+
 def expected(ps):
     res, ops, _, _ = oracle.batch(ps)
     return [(int(res["score"][i]), rle(oracle.pair_ops(ps, res, ops, i)) if res["score"][i] >= 0 else "",
@@ -175,3 +181,44 @@ def test_chunked_start_search(driver, chunk):
            for r, c in zip(res, cig)]
     bad = [i for i in range(ps.n_pairs) if want[i] != got[i]]
     assert not bad, (chunk, bad[:5], want[bad[0]], got[bad[0]])
+
+
+@pytest.mark.parametrize("form,hard_lanes,compact", [(0, 16, 1), (1, 16, 1), (1, 16, 0), (1, 32, 0)])
+def test_debug_build_clean(debug_driver, form, hard_lanes, compact):
+    # the debug build's invariant checks pass and its queue audit finds every
+    # queued pair taken by exactly one window worker: results as the oracle's
+    # with no flags (check() asserts flags == 0)
+    pairs = gen.fuzz(8080 + hard_lanes, 16, max_len=200)
+    cases = [("", ""), ("", "ACGT"), ("ACGT", ""), ("A" * 64, "C" * 64), ("T" * 65, "")]
+    for k, W, O in ((64, 64, 24), (5, 16, 8)):
+        ps = gen.from_lists("debug", [p[0] for p in pairs] + [c[0] for c in cases],
+                            [p[1] for p in pairs] + [c[1] for c in cases], k, W, O)
+        check(debug_driver, ps, form, hard_lanes=hard_lanes, compact=compact)
+    ps = gen.make("long10k", 2, start=4)  # a decoy and a true pair, 1,000-base prefixes
+    cut = gen.from_lists("long-prefix", [ps.read(i)[:1000] for i in range(2)],
+                         [ps.ref(i)[:1100] for i in range(2)], 64)
+    check(debug_driver, cut, form, hard_lanes=hard_lanes, compact=compact)
+
+
+def test_debug_build_flags_broken_layout(debug_driver):
+    # a launch layout the library never makes (17 LDS rows for 16-lane groups,
+    # so a group's second row block would run past its LDS rows) is caught by
+    # the debug build before the access: the pairs that need that block end
+    # with the internal flag, every other pair still matches the oracle
+    ps = gen.make("long10k", 2, start=4)
+    cut = gen.from_lists("long-prefix", [ps.read(i)[:1000] for i in range(2)],
+                         [ps.ref(i)[:1100] for i in range(2)], 64)
+    pairs = gen.fuzz(9191, 8, max_len=120)
+    ps = gen.from_lists("mix", [cut.read(i) for i in range(2)] + [p[0] for p in pairs],
+                        [cut.ref(i) for i in range(2)] + [p[1] for p in pairs], 64)
+    want = expected(ps)
+    res, cig = emu.run(debug_driver, ps, 1, 16, 16, 17, hard_row=65, compact=0)
+    flagged = (res["flags"] & 2) != 0
+    assert flagged[0], "the decoy's windows need rows past the first block"
+    assert ((res["flags"] | 2) == 2).all()
+    for i in range(ps.n_pairs):
+        if not flagged[i]:
+            r = res[i]
+            got = (int(r["edit_distance"]), cig[i], int(r["ref_begin"]), int(r["ref_end"]),
+                   int(r["n_windows"]))
+            assert got == want[i], (i, got, want[i])
