@@ -1722,6 +1722,11 @@ __global__ void k_search_finalize(AlignParams P) {
 // otherwise, and always for the easy queue, every pair runs in a 16-lane group,
 // four pairs per wavefront, with `lds_rows` table rows in LDS and the rows
 // above spilled to device memory.
+//
+// HL, the hard queue's group width (16, 32 or 64), is a template argument so
+// that each instance holds only the paths its launch runs (the widest path
+// sets the register allocation of the whole kernel).
+template <int HL>
 __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
     extern __shared__ u64 smem[];
     const int lane = threadIdx.x & 63;
@@ -1740,7 +1745,7 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
         ? P.spill + ((uint64_t)blockIdx.x * 4 + grp) * (uint64_t)spill_rows * P.stride : nullptr;
     for (int phase = 0; phase < 2; ++phase) {
         const bool hard = (phase == 0) == hard_first;
-        if (hard && P.hard_lanes == 64) {
+        if (HL == 64 && hard) {
             for (uint32_t iter = 0; iter <= n_hard; ++iter) {
                 const uint32_t item = group_pop(P.counters + kCounterHardHead, smem, lane, n_hard);
                 if (item >= n_hard) break;
@@ -1751,7 +1756,7 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
             }
             continue;
         }
-        if (hard && P.hard_lanes == 32) {
+        if (HL == 32 && hard) {
             // two 32-lane groups, each with 32 table rows in LDS (the space of two
             // 16-lane groups) and rows 32..63 in the spill areas of those two
             // groups (2 (64 - lds_rows) >= 32 rows, as lds_rows <= 48)
@@ -2614,8 +2619,9 @@ int windows_blocks_per_cu(const AlignParams& p) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_windows_c<false>, 64,
                                                          compact_lds_bytes(p.stride));
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_windows, 64,
-                                                         window_lds_bytes(p.lds_rows, p.stride));
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, p.hard_lanes == 64 ? k_windows<64> : p.hard_lanes == 32 ? k_windows<32> : k_windows<16>,
+            64, window_lds_bytes(p.lds_rows, p.stride));
     return e == hipSuccess ? n : 0;
 }
 
@@ -2634,7 +2640,9 @@ hipError_t launch_windows(const AlignParams& p, int blocks, hipStream_t s) {
         return hipGetLastError();
     }
     const int lds = window_lds_bytes(p.lds_rows, p.stride);
-    hipLaunchKernelGGL(k_windows, dim3(blocks), dim3(64), lds, s, p);
+    if (p.hard_lanes == 64) hipLaunchKernelGGL(k_windows<64>, dim3(blocks), dim3(64), lds, s, p);
+    else if (p.hard_lanes == 32) hipLaunchKernelGGL(k_windows<32>, dim3(blocks), dim3(64), lds, s, p);
+    else hipLaunchKernelGGL(k_windows<16>, dim3(blocks), dim3(64), lds, s, p);
     return hipGetLastError();
 }
 

@@ -222,3 +222,35 @@ def test_debug_build_flags_broken_layout(debug_driver):
             got = (int(r["edit_distance"]), cig[i], int(r["ref_begin"]), int(r["ref_end"]),
                    int(r["n_windows"]))
             assert got == want[i], (i, got, want[i])
+
+
+@pytest.mark.parametrize("lds_rows", [16, 32])
+def test_window_distance_around_spilled_passes(driver, lds_rows):
+    # windows whose d* falls in the first spilled pass (kept as 32-bit slices),
+    # just past it (that pass computed again with whole words), deeper, and at
+    # the last row; substitutions, insertions and deletions spread over the
+    # first window
+    rng = np.random.default_rng(2718 + lds_rows)
+    reads, refs = [], []
+    for e in (lds_rows - 2, lds_rows, lds_rows + 3, lds_rows + 15, lds_rows + 16, lds_rows + 20, 63):
+        e = min(e, 63)
+        r = rng.integers(0, 4, 120).astype(np.uint8)
+        t = list(r)
+        for pos in sorted(rng.choice(60, size=min(e, 60), replace=False), reverse=True):
+            kind = rng.integers(0, 3)
+            if kind == 0:
+                t[pos] = (t[pos] + 1 + rng.integers(0, 3)) % 4
+            elif kind == 1:
+                del t[pos]
+            else:
+                t.insert(pos, int(rng.integers(0, 4)))
+        reads.append(r)
+        refs.append(np.array(t, dtype=np.uint8))
+    ps = gen.from_lists("deep", reads, refs, 64)
+    want = expected(ps)
+    res, cig = emu.run(driver, ps, 1, 16, 16, lds_rows, hard_row=65, compact=0)
+    assert (res["flags"] == 0).all()
+    got = [(int(r["edit_distance"]), c, int(r["ref_begin"]), int(r["ref_end"]), int(r["n_windows"]))
+           for r, c in zip(res, cig)]
+    bad = [i for i in range(ps.n_pairs) if want[i] != got[i]]
+    assert not bad, (bad[:5], want[bad[0]], got[bad[0]])
