@@ -509,11 +509,14 @@ def test_injected_allocation_failure(monkeypatch):
 def test_measured_peaks_are_plausible(ctx):
     """genasm_measure_peaks: every rate positive and each microbenchmark
     within what one MI355X can do (below the published or derived peaks; the
-    64-bit shift issuing no faster than plain int32 operations)."""
+    64-bit shift, the funnel shift and the DPP move each issuing at about half
+    the rate of a plain int32 operation: their instruction rates stay well
+    below the int32 rate, the shift counting two operations per instruction)."""
     pk = ctx.measure_peaks()
     assert pk["compute_units"] == 256
     for key in ("dc_mix_tops", "int32_tops", "shift64_tops", "funnel_tops", "dpp_tops"):
         assert 1.0 < pk[key] < 2 * 78.6, (key, pk[key])
-    assert pk["shift64_tops"] <= pk["int32_tops"] * 1.05
+    for key, ops_per_instruction in (("shift64_tops", 2), ("funnel_tops", 1), ("dpp_tops", 1)):
+        assert pk[key] / ops_per_instruction <= 0.6 * pk["int32_tops"], (key, pk[key], pk["int32_tops"])
     assert 0.5 < pk["hbm_tbps"] < 8.0
     assert pk["lds_tbps"] > 1.0
