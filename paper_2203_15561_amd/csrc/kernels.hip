@@ -735,6 +735,9 @@ __device__ __forceinline__ TbOut traceback_planes(const u64* lds, const u64* spi
     u64 pf = 0;            // this lane's word of the prefetched row
     int pf_row = -1, pf_col = 0;
     const int gbase = lane - gl;
+    // word offset of row d-1 (every edit lowers d by one: no multiply per edit)
+    int roff = (dstar - 1) * stride;
+    const int spill_off = lds_rows * stride;
     // every pass of the loop consumes a read or text base, or leaves it
     for (int it = 0; it <= 2 * L; ++it) {
         if (j >= jmax || i >= L) break;
@@ -761,11 +764,11 @@ __device__ __forceinline__ TbOut traceback_planes(const u64* lds, const u64* spi
         const int r = d - 1, p = mw - 1 - j;
         u64 B, C;
         if (r < lds_rows) {
-            const u64* row = tab + r * stride;
+            const u64* row = tab + roff;
             C = row[i];
             B = row[i + 1];
         } else {
-            const u64* row = spill + (size_t)(r - lds_rows) * stride + 1;
+            const u64* row = spill + (size_t)(roff - spill_off) + 1;
             const bool hit = r == pf_row && i >= pf_col && i + 1 < pf_col + G;
             const int src = gbase + (i - pf_col);
             const u64 have = pf;
@@ -796,6 +799,7 @@ __device__ __forceinline__ TbOut traceback_planes(const u64* lds, const u64* spi
         i += op != GENASM_OP_INS;
         j += op != GENASM_OP_DEL;
         d -= 1;
+        roff -= stride;
     }
     o.i_end = i;
     o.j_end = j;
