@@ -208,9 +208,24 @@ __host__ __device__ inline int window_group_words32(int lds_rows, int stride) {
 }
 // Compact window groups keep every row of a deep window in their spill area.
 constexpr int kCompactSpillRows = 64;
-// Words of the table stride, the spill of one worker and its end word.
-inline uint64_t spill_words(uint64_t workers, int spill_rows, int stride) {
-    return workers * (uint64_t)spill_rows * (uint64_t)stride + 1;
+// Spilled table rows are kept in step order: each spilled pass of a G-lane
+// group is a block of 64 + G slots of G words (the entry lane g computes at
+// step t sits at slot t + 1, word (t + 1) G + g), so the G stores of a step
+// fill adjacent words.
+__host__ __device__ constexpr int spill_pass_words(int G) { return (64 + G) * G; }
+// Words of one 16-lane group's spill area for `spill_rows` spilled rows (a
+// multiple of 16): one block per spilled pass, and at least half a 32-lane
+// block, since a 32-lane group keeps its spilled pass in the areas of the two
+// 16-lane groups it replaces.
+__host__ __device__ inline int spill_group_words(int spill_rows) {
+    if (spill_rows <= 0) return 0;
+    const int passes = spill_rows / 16 * spill_pass_words(16);
+    const int half32 = spill_pass_words(32) / 2;
+    return passes > half32 ? passes : half32;
+}
+// Words of the spill of `workers` 16-lane groups and an end word.
+inline uint64_t spill_words(uint64_t workers, int spill_rows) {
+    return workers * (uint64_t)spill_group_words(spill_rows) + 1;
 }
 // Start search group: PM and broadcast slots, then a ring of 128 text masks
 // kept twice (words kSearchRingOff + w and + 128 + w).

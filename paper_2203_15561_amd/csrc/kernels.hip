@@ -150,6 +150,21 @@ __device__ __forceinline__ u64 load_spill(const u64* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
+// Entry (row r, column col) of a window's spilled rows (r >= lds_rows, a
+// multiple of G): the rows are kept in step order, one block of
+// spill_pass_words(G) per spilled pass, lane g = (r - lds_rows) mod G of the
+// pass holding column col at slot nw - col + g (the slot of the step that
+// computed it, plus one). Slots below 0 (columns past nw + g, which no step
+// computes and whose values a reader does not use) read slot 0.
+template <int G>
+__device__ __forceinline__ const u64* spill_entry(const u64* spill, int r, int col, int nw,
+                                                  int lds_rows) {
+    const int q = r - lds_rows;
+    const int g = q & (G - 1);
+    const int slot = max(nw - col + g, 0);
+    return spill + (size_t)(q / G) * spill_pass_words(G) + slot * G + g;
+}
+
 // Per-group LDS layout (64-bit words).
 constexpr int OFF_PM = 0;      // 4 pattern masks / match accumulators
 constexpr int OFF_PMT = 4;     // PM[T[i]] for i in 0..nw, ~0 at nw..64 (66 words)
@@ -342,13 +357,13 @@ __device__ __forceinline__ void store_pmt_so(u64* lds, int gl, const u64 pm[4], 
 // value) when nw <= W-O, so that the traceback never special-cases it. Lane
 // G-1 writes its row into the boundary row, which lane 0 of the next pass
 // reads as the row above. FIRST: pass 0, whose row above is all ones.
-template <int G, bool SPILL, bool FIRST>
-__device__ void dc_pass(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int stride,
-                        int lds_rows) {
+template <int G, bool FIRST>
+__device__ void dc_pass(u64* lds, int gl, int c, int nw, int Lc, int stride) {
+    static_assert(G == 64, "whole-wavefront groups keep every row in LDS");
     const u64* pmt = lds + OFF_PMT;
     u64* brow = lds + OFF_BROW;
     const int d = c * G + gl;
-    u64* trow = SPILL ? spill + (size_t)(d - lds_rows) * stride : lds + OFF_TAB + d * stride;
+    u64* trow = lds + OFF_TAB + d * stride;
     u64 R = init_word(d);
     u64 Dp = d == 0 ? ~0ull : init_word(d - 1);
     const u64 lowin = d == 0 ? 1ull : 0ull;
@@ -391,14 +406,20 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
                            int lds_rows) {
     using Lay = SoLayout<G>;
     const int d = c * G + gl;
-    u64* trow = SPILL ? spill + (size_t)(d - lds_rows) * stride : lds + Lay::tab + d * stride;
+    u64* trow = lds + Lay::tab + d * stride;
+    // spilled pass: this lane's column of the pass's step-ordered block (slot t+1
+    // holds the entry of step t, slot 0 column nw)
+    u64* sp = SPILL ? spill + (size_t)((d - lds_rows) / G) * spill_pass_words(G) + gl : nullptr;
     const u64* pp = lds + Lay::pmt - gl;   // + t: PMT[t - gl]
     const u64* bp = lds + Lay::brow;       // + t: BROW[t]
     u64* bw = lds + Lay::brow - (G - 1);   // + t: BROW[t - (G-1)]
     u64 R = init_word(d);
     u64 Dp = d == 0 ? ~0ull : init_word(d - 1);
     const u64 lowin = d == 0 ? 1ull : 0ull;
-    if (Lc == nw) trow[1 + nw] = R;  // lane 0 of a pass never computes column nw
+    if (Lc == nw) {  // lane 0 of a pass never computes column nw
+        if constexpr (SPILL) sp[gl * G] = R;
+        else trow[1 + nw] = R;
+    }
     const int slot0 = nw + gl;       // table slot 1 + i at t = 0 (column i = nw - 1 - t + gl)
     const int hi_slot = Lc + 2;
     const int steps = nw + G - 1;
@@ -419,7 +440,10 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
             const u64 up = shift_up<G>(ov, R, gl);
             R = dc_step(R, Dp, up, pm_t, lowin);
             Dp = up;
-            if constexpr (decltype(store)::value) trow[med3i(slot0 - t, 0, hi_slot)] = R;
+            if constexpr (decltype(store)::value) {
+                if constexpr (SPILL) sp[(t + 1) * G] = R;
+                else trow[med3i(slot0 - t, 0, hi_slot)] = R;
+            }
             if constexpr (decltype(brow_store)::value) {
                 if (gl == G - 1) bw[t] = R;
             }
@@ -458,11 +482,11 @@ template <int G>
 __device__ __forceinline__ void fill_brow(u64* lds, const u64* spill, int gl, int c, int nw, int Lc,
                                           int stride, int lds_rows) {
     const int r = c * G - 1;
-    const u64* row = r >= lds_rows ? spill + (size_t)(r - lds_rows) * stride
-                                   : lds + SoLayout<G>::tab + r * stride;
+    const u64* row = lds + SoLayout<G>::tab + r * stride;
     u64* b = lds + SoLayout<G>::brow;
     for (int col = gl; col <= Lc && col < nw; col += G) {
-        const u64 v = r >= lds_rows ? load_spill(row + 1 + col) : row[1 + col];
+        const u64 v = r >= lds_rows ? load_spill(spill_entry<G>(spill, r, col, nw, lds_rows))
+                                    : row[1 + col];
         b[nw - 1 - col] = v;
     }
 }
@@ -737,7 +761,6 @@ __device__ __forceinline__ TbOut traceback_planes(const u64* lds, const u64* spi
     const int gbase = lane - gl;
     // word offset of row d-1 (every edit lowers d by one: no multiply per edit)
     int roff = (dstar - 1) * stride;
-    const int spill_off = lds_rows * stride;
     // every pass of the loop consumes a read or text base, or leaves it
     for (int it = 0; it <= 2 * L; ++it) {
         if (j >= jmax || i >= L) break;
@@ -768,13 +791,12 @@ __device__ __forceinline__ TbOut traceback_planes(const u64* lds, const u64* spi
             C = row[i];
             B = row[i + 1];
         } else {
-            const u64* row = spill + (size_t)(roff - spill_off) + 1;
             const bool hit = r == pf_row && i >= pf_col && i + 1 < pf_col + G;
             const int src = gbase + (i - pf_col);
             const u64 have = pf;
             // the row below, for the next edit, before this edit waits for its words
             if (prefetch && r - 1 >= lds_rows) {
-                pf = load_spill(row - stride + min(i + gl, L));
+                pf = load_spill(spill_entry<G>(spill, r - 1, min(i + gl, L), nw, lds_rows));
                 pf_row = r - 1;
                 pf_col = i;
             } else {
@@ -784,8 +806,8 @@ __device__ __forceinline__ TbOut traceback_planes(const u64* lds, const u64* spi
                 C = __shfl(have, src);
                 B = __shfl(have, src + 1);
             } else {
-                C = load_spill(row + i);
-                B = load_spill(row + i + 1);
+                C = load_spill(spill_entry<G>(spill, r, i, nw, lds_rows));
+                B = load_spill(spill_entry<G>(spill, r, i + 1, nw, lds_rows));
             }
         }
         const bool intext = i < nw;
@@ -888,13 +910,13 @@ __device__ __forceinline__ bool audit_ok(const AlignParams& P, uint64_t pair, ui
 #endif
 }
 
-// Rows of the spill area one G-lane group may use: (64 - lds_rows) of the
-// 16-lane layout per 16-lane group, a 32-lane group owning two such areas;
-// 64-lane groups keep every row in LDS.
+// Rows of the spill area one G-lane group may use: whole spilled passes of
+// its step-ordered blocks in its area (a 32-lane group owning the areas of
+// two 16-lane groups); 64-lane groups keep every row in LDS.
 template <int G>
 __device__ __forceinline__ int spill_capacity(const AlignParams& P) {
     if constexpr (G == 64) return 0;
-    else return (G / 16) * (64 - P.lds_rows);
+    else return (G / 16) * spill_group_words(64 - P.lds_rows) / spill_pass_words(G) * G;
 }
 
 // Advances one pair whose window state is `st` by at most `budget` windows
@@ -985,17 +1007,12 @@ __device__ __forceinline__ uint32_t advance_pair(const AlignParams& P, u64* lds,
                     wave_sync();
                 }
             } else {
-                if (spill_pass) {
-                    dc_pass<G, true, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
-                    mem_sync();
-                } else {
-                    if (c == 0) dc_pass<G, false, true>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
-                    else dc_pass<G, false, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
-                    wave_sync();
-                }
+                // 64 rows in LDS: one pass, never spilled (lds_rows is 64)
+                dc_pass<G, true>(lds, gl, c, nw, Lc, P.stride);
+                wave_sync();
             }
             const int d = c * G + gl;
-            const u64 r0 = spill_pass ? load_spill(spill + (size_t)(d - lds_rows) * P.stride + 1)
+            const u64 r0 = spill_pass ? load_spill(spill_entry<G>(spill, d, 0, nw, lds_rows))
                                       : lds[tab_off<G>() + d * P.stride + 1];
             const bool sol = d <= Kr && !((r0 >> (mw - 1)) & 1ull);
             const u64 bits = group_ballot(sol, G, lane);
@@ -1746,7 +1763,7 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
     u64* lds = smem + grp * window_group_words(P.lds_rows, P.stride);
     const int spill_rows = 64 - P.lds_rows;
     u64* spill = spill_rows > 0
-        ? P.spill + ((uint64_t)blockIdx.x * 4 + grp) * (uint64_t)spill_rows * P.stride : nullptr;
+        ? P.spill + ((uint64_t)blockIdx.x * 4 + grp) * (uint64_t)spill_group_words(spill_rows) : nullptr;
     for (int phase = 0; phase < 2; ++phase) {
         const bool hard = (phase == 0) == hard_first;
         if (HL == 64 && hard) {
@@ -1762,13 +1779,14 @@ __global__ __launch_bounds__(64) void k_windows(AlignParams P) {
         }
         if (HL == 32 && hard) {
             // two 32-lane groups, each with 32 table rows in LDS (the space of two
-            // 16-lane groups) and rows 32..63 in the spill areas of those two
-            // groups (2 (64 - lds_rows) >= 32 rows, as lds_rows <= 48)
+            // 16-lane groups) and rows 32..63 (one spilled pass) in the spill
+            // areas of those two groups (each at least half a 32-lane block; a
+            // 16-lane group spills when lds_rows <= 48, the limit for this form)
             const int gl32 = lane & 31;
             const int h = lane >> 5;
             u64* lds32 = smem + h * window_group_words32(32, P.stride);
             u64* spill32 = P.spill + ((uint64_t)blockIdx.x * 4 + 2 * h) *
-                                         (uint64_t)(64 - P.lds_rows) * P.stride;
+                                         (uint64_t)spill_group_words(64 - P.lds_rows);
             for (uint32_t iter = 0; iter <= n_hard; ++iter) {
                 const uint32_t item = group_pop(P.counters + kCounterHardHead, lds32, gl32, n_hard);
                 if (item >= n_hard) break;
@@ -2031,7 +2049,7 @@ __device__ __forceinline__ uint32_t advance_pair_c(const AlignParams& P, u64* ld
                     }
                     mem_sync();
                     const int d = c * G + gl;
-                    const u64 r0 = load_spill(spill + (size_t)d * P.stride + 1);
+                    const u64 r0 = load_spill(spill_entry<G>(spill, d, 0, nw, 0));
                     const bool sol = d <= Kr && !((r0 >> (mw - 1)) & 1ull);
                     const u64 bits = group_ballot(sol, G, lane);
                     if (bits) { dstar = c * G + __builtin_ctzll(bits); break; }
@@ -2168,7 +2186,7 @@ __device__ __forceinline__ void run_pair_c(const AlignParams& P, u64* lds, u64* 
 
 // Window kernel with compact groups (four 16-lane groups per wavefront, both
 // queues; see k_windows for the queues and the hard share). Each group's
-// spill area holds 64 rows of `stride` words.
+// spill area holds the four step-ordered blocks of a deep window's 64 rows.
 template <bool STATS>
 __global__ __launch_bounds__(64) void k_windows_c(AlignParams P) {
     extern __shared__ u64 smem[];
@@ -2181,7 +2199,7 @@ __global__ __launch_bounds__(64) void k_windows_c(AlignParams P) {
     const int gl = lane & 15;
     const int grp = lane >> 4;
     u64* lds = smem + grp * compact_group_words(P.stride);
-    u64* spill = P.spill + ((uint64_t)blockIdx.x * 4 + grp) * (uint64_t)kCompactSpillRows * P.stride;
+    u64* spill = P.spill + ((uint64_t)blockIdx.x * 4 + grp) * (uint64_t)spill_group_words(kCompactSpillRows);
     for (int phase = 0; phase < 2; ++phase) {
         const bool hard = (phase == 0) == hard_first;
         const uint32_t* list = hard ? P.hard_list : P.easy_list;

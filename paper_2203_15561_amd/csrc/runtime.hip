@@ -547,7 +547,7 @@ int align_dev(genasm_ctx* ctx, const uint8_t* d_reads2b, const uint64_t* d_read_
         uint64_t* items = c.take<uint64_t>(2 * item_cap);
         p.easy_list = c.take<uint32_t>(n_pairs);
         p.hard_list = c.take<uint32_t>(n_pairs);
-        p.spill = spill_rows > 0 ? c.take<unsigned long long>(spill_words(workers, spill_rows, p.stride)) : nullptr;
+        p.spill = spill_rows > 0 ? c.take<unsigned long long>(spill_words(workers, spill_rows)) : nullptr;
         uint32_t* hist = c.take<uint32_t>(kLptBuckets);
         uint32_t* order = c.take<uint32_t>(n_pairs);
         return std::make_tuple(items, hist, order);

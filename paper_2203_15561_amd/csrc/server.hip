@@ -412,7 +412,7 @@ int genasm_server_create(genasm_ctx* ctx, const genasm_server_config* cfg_in,
     srv->item_cap = search_item_cap(NS, cfg.pool_bases, kServeSearchChunk);
     D(srv->d_items, 2 * srv->item_cap); D(srv->d_key, NS); D(srv->d_turn, 1);
     D(srv->d_arrivals, 1); H(srv->h_arrivals, 1);
-    D(srv->d_spill, spill_words(workers, kCompactSpillRows, stride));
+    D(srv->d_spill, spill_words(workers, kCompactSpillRows));
     for (IterBufs& b : srv->it) {
         H(b.h_upload, srv->upload_cap); D(b.d_upload, srv->upload_cap);
         H(b.h_up_src, 2 * (size_t)NS); H(b.h_up_dst, 2 * (size_t)NS); H(b.h_up_word, 2 * (size_t)NS);

@@ -129,7 +129,7 @@ int main(int argc, char** argv) {
         std::vector<unsigned long long> key(n_slots);
         std::vector<uint32_t> new_list(n_slots + 1), fin(n_slots + 1), fin_len(1, 0);
         std::vector<ServeAdmit> admit(n_slots + 1);
-        std::vector<unsigned long long> spill(spill_words(workers, kCompactSpillRows, p.stride));
+        std::vector<unsigned long long> spill(spill_words(workers, kCompactSpillRows));
         std::vector<TurnLimits> turn(1);
         std::vector<unsigned long long> arrivals(1, 0);
         std::vector<uint64_t> s_roff(n_slots), s_foff(n_slots), s_base(n_slots);
@@ -280,7 +280,7 @@ int main(int argc, char** argv) {
         std::vector<uint64_t> items(2 * icap);
         std::vector<unsigned long long> key(n);
         std::vector<uint32_t> easy(n + 1), hard(n + 1);
-        std::vector<unsigned long long> spill(spill_words(workers, spill_rows, p.stride));
+        std::vector<unsigned long long> spill(spill_words(workers, spill_rows));
         std::iota(order.begin(), order.end(), 0u);
         std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
             return roff[a + 1] - roff[a] > roff[b + 1] - roff[b];
