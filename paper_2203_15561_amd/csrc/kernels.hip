@@ -401,7 +401,11 @@ __device__ void dc_pass(u64* lds, int gl, int c, int nw, int Lc, int stride) {
 // SoLayout): the same computation, with the operand reads and the
 // boundary-row write at per-step constant offsets and one clamp for the table
 // store.
-template <int G, bool SPILL, bool FIRST, int U = 8>
+//
+// SINK (the window groups' own layout): the boundary-row store is made by every
+// lane, lane G-1 to BROW and the others to the left dummy slot of their LDS
+// table row (slot 0, which no reader uses), so that it needs no execution mask.
+template <int G, bool SPILL, bool FIRST, int U = 8, bool SINK = true>
 __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int stride,
                            int lds_rows) {
     using Lay = SoLayout<G>;
@@ -413,6 +417,8 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
     const u64* pp = lds + Lay::pmt - gl;   // + t: PMT[t - gl]
     const u64* bp = lds + Lay::brow;       // + t: BROW[t]
     u64* bw = lds + Lay::brow - (G - 1);   // + t: BROW[t - (G-1)]
+    const int bstep = gl == G - 1 ? 1 : 0;
+    u64* bsink = gl == G - 1 ? bw : lds + Lay::tab + gl * stride;
     u64 R = init_word(d);
     u64 Dp = d == 0 ? ~0ull : init_word(d - 1);
     const u64 lowin = d == 0 ? 1ull : 0ull;
@@ -445,7 +451,8 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
                 else trow[med3i(slot0 - t, 0, hi_slot)] = R;
             }
             if constexpr (decltype(brow_store)::value) {
-                if (gl == G - 1) bw[t] = R;
+                if constexpr (SINK) bsink[t * bstep] = R;
+                else if (gl == G - 1) bw[t] = R;
             }
             // operands of steps t+U-1 and t+U, loaded in pairs of adjacent words
             // after both slots' last use (no register copies); the boundary
@@ -2041,11 +2048,11 @@ __device__ __forceinline__ uint32_t advance_pair_c(const AlignParams& P, u64* ld
                 for (int c = 0; c * G <= Kr; ++c) {
                     if constexpr (STATS) st_steps += (u64)G * (nw + G - 1);
                     if (c == 0) {
-                        dc_pass_so<G, true, true, kCompactU>(lds, spill, gl, c, nw, Lc, P.stride, 0);
+                        dc_pass_so<G, true, true, kCompactU, false>(lds, spill, gl, c, nw, Lc, P.stride, 0);
                     } else {
                         fill_brow<G>(lds, spill, gl, c, nw, Lc, P.stride, 0);
                         wave_sync();
-                        dc_pass_so<G, true, false, kCompactU>(lds, spill, gl, c, nw, Lc, P.stride, 0);
+                        dc_pass_so<G, true, false, kCompactU, false>(lds, spill, gl, c, nw, Lc, P.stride, 0);
                     }
                     mem_sync();
                     const int d = c * G + gl;
