@@ -402,10 +402,14 @@ __device__ void dc_pass(u64* lds, int gl, int c, int nw, int Lc, int stride) {
 // boundary-row write at per-step constant offsets and one clamp for the table
 // store.
 //
-// SINK (the window groups' own layout): the boundary-row store is made by every
-// lane, lane G-1 to BROW and the others to the left dummy slot of their LDS
-// table row (slot 0, which no reader uses), so that it needs no execution mask.
-template <int G, bool SPILL, bool FIRST, int U = 8, bool SINK = true>
+// SINK: the boundary-row store is made by every lane, lane g writing BROW[t-g]
+// at step t: lane G-1 its own entry, the others an entry that lane 0 of this
+// pass has already read and that lane G-1 writes again later (or, for the
+// columns up to Lc, fill_brow before a next pass), so that the store needs no
+// execution mask and a group's G words are adjacent. Every such entry lies at
+// or below BROW[63] (t - g < nw + G - 2 - Lc, and nw - Lc <= 66 - G when
+// L >= G - 2, which the caller checks) and at or above BROW[-(G-1)].
+template <int G, bool SPILL, bool FIRST, int U = 8, bool SINK = false>
 __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, int stride,
                            int lds_rows) {
     using Lay = SoLayout<G>;
@@ -417,8 +421,7 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
     const u64* pp = lds + Lay::pmt - gl;   // + t: PMT[t - gl]
     const u64* bp = lds + Lay::brow;       // + t: BROW[t]
     u64* bw = lds + Lay::brow - (G - 1);   // + t: BROW[t - (G-1)]
-    const int bstep = gl == G - 1 ? 1 : 0;
-    u64* bsink = gl == G - 1 ? bw : lds + Lay::tab + gl * stride;
+    u64* bsink = bw + (G - 1 - gl);  // + t: BROW[t - gl]
     u64 R = init_word(d);
     u64 Dp = d == 0 ? ~0ull : init_word(d - 1);
     const u64 lowin = d == 0 ? 1ull : 0ull;
@@ -451,7 +454,7 @@ __device__ void dc_pass_so(u64* lds, u64* spill, int gl, int c, int nw, int Lc, 
                 else trow[med3i(slot0 - t, 0, hi_slot)] = R;
             }
             if constexpr (decltype(brow_store)::value) {
-                if constexpr (SINK) bsink[t * bstep] = R;
+                if constexpr (SINK) bsink[t] = R;
                 else if (gl == G - 1) bw[t] = R;
             }
             // operands of steps t+U-1 and t+U, loaded in pairs of adjacent words
@@ -993,6 +996,7 @@ __device__ __forceinline__ uint32_t advance_pair(const AlignParams& P, u64* lds,
         int dstar = -1;
         st_cells += (u64)mw * nw;
         bool pass_ok = true;
+        const bool sink = P.L >= G - 2;  // the boundary-row store of every lane fits
         for (int c = 0; c * G <= Kr; ++c) {
             st_steps += (u64)G * (nw + G - 1);
             const bool spill_pass = c * G >= lds_rows;
@@ -1006,11 +1010,17 @@ __device__ __forceinline__ uint32_t advance_pair(const AlignParams& P, u64* lds,
                     wave_sync();
                 }
                 if (spill_pass) {
-                    dc_pass_so<G, true, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    if (sink) dc_pass_so<G, true, false, 8, true>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    else dc_pass_so<G, true, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
                     mem_sync();
                 } else {
-                    if (c == 0) dc_pass_so<G, false, true>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
-                    else dc_pass_so<G, false, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    if (c == 0) {
+                        if (sink) dc_pass_so<G, false, true, 8, true>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                        else dc_pass_so<G, false, true>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    } else {
+                        if (sink) dc_pass_so<G, false, false, 8, true>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                        else dc_pass_so<G, false, false>(lds, spill, gl, c, nw, Lc, P.stride, lds_rows);
+                    }
                     wave_sync();
                 }
             } else {
@@ -2048,11 +2058,11 @@ __device__ __forceinline__ uint32_t advance_pair_c(const AlignParams& P, u64* ld
                 for (int c = 0; c * G <= Kr; ++c) {
                     if constexpr (STATS) st_steps += (u64)G * (nw + G - 1);
                     if (c == 0) {
-                        dc_pass_so<G, true, true, kCompactU, false>(lds, spill, gl, c, nw, Lc, P.stride, 0);
+                        dc_pass_so<G, true, true, kCompactU>(lds, spill, gl, c, nw, Lc, P.stride, 0);
                     } else {
                         fill_brow<G>(lds, spill, gl, c, nw, Lc, P.stride, 0);
                         wave_sync();
-                        dc_pass_so<G, true, false, kCompactU, false>(lds, spill, gl, c, nw, Lc, P.stride, 0);
+                        dc_pass_so<G, true, false, kCompactU>(lds, spill, gl, c, nw, Lc, P.stride, 0);
                     }
                     mem_sync();
                     const int d = c * G + gl;
