@@ -254,3 +254,15 @@ def test_window_distance_around_spilled_passes(driver, lds_rows):
            for r, c in zip(res, cig)]
     bad = [i for i in range(ps.n_pairs) if want[i] != got[i]]
     assert not bad, (bad[:5], want[bad[0]], got[bad[0]])
+
+
+@pytest.mark.parametrize("W,O", [(64, 56), (32, 20)])
+def test_deep_windows_small_overlap_step(driver, W, O):
+    # decoy windows (three or more DC passes) with W - O under 14, where only the
+    # last lane of a group stores the boundary row, and above it; 64-bit tables
+    # in 16- and 32-lane groups
+    ps = gen.make("long10k", 2, start=4)
+    cut = gen.from_lists("deep", [ps.read(i)[:600] for i in range(2)],
+                         [ps.ref(i)[:700] for i in range(2)], 64, W, O)
+    check(driver, cut, 1, 16, 16, compact=0)
+    check(driver, cut, 1, 16, 32, compact=0)

@@ -520,3 +520,18 @@ def test_measured_peaks_are_plausible(ctx):
         assert pk[key] / ops_per_instruction <= 0.6 * pk["int32_tops"], (key, pk[key], pk["int32_tops"])
     assert 0.5 < pk["hbm_tbps"] < 8.0
     assert pk["lds_tbps"] > 1.0
+
+
+@pytest.mark.parametrize("W,O", [(64, 24), (64, 56), (32, 20), (48, 8)])
+@pytest.mark.parametrize("hard_lanes", [16, 32])
+def test_deep_windows_across_overlaps(ctx, W, O, hard_lanes):
+    # 1,000-base prefixes of decoy and true pairs: the decoys' windows need
+    # three or more DC passes, so the boundary row between passes, the spilled
+    # passes and their traceback reads all run; W - O below and above the width
+    # where every lane of a group takes part in the boundary-row store
+    ps = gen.make("long10k", 8, start=4)
+    cut = gen.from_lists("deep", [ps.read(i)[:1000] for i in range(ps.n_pairs)],
+                         [ps.ref(i)[:1100] for i in range(ps.n_pairs)], 64, W, O)
+    assert ps.decoy.any()
+    L = ga.make_launch(ga.FORM_BATCHED, hard_lanes=hard_lanes, table_bits=64)
+    assert_same(cut, expected(cut), on_gpu(ctx, cut, L), f"deep W={W} O={O} hard_lanes={hard_lanes}")
